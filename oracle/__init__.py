@@ -1,0 +1,164 @@
+"""Python face of the plain CPU oracle (``fractal_oracle.c``).
+
+TEST INFRASTRUCTURE.  Only the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  It shares no code with
+the GPU library and never imports it.
+
+Functions mirror the C file one to one; each docstring names the passage of
+the paper it follows.  Parity status: every function below is pinned by
+``tests/test_oracle_pins.py`` (closed forms, brute force, a textbook-routine
+special case, hand-derived values); none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fractal_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+RULE_CA = 0
+RULE_HEAT = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE doubles)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+               _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, u64, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    vp = ctypes.c_void_p
+    lib.oracle_member.argtypes = [i64, i64, i32]
+    lib.oracle_member.restype = i32
+    lib.oracle_count_members.argtypes = [i32]
+    lib.oracle_count_members.restype = u64
+    lib.oracle_grid_dims.argtypes = [i32, ctypes.POINTER(u64),
+                                     ctypes.POINTER(u64)]
+    lib.oracle_grid_dims.restype = None
+    lib.oracle_lambda_paper.argtypes = [i32, u64, u64, ctypes.POINTER(u64),
+                                        ctypes.POINTER(u64)]
+    lib.oracle_lambda.argtypes = lib.oracle_lambda_paper.argtypes
+    lib.oracle_lambda_grid.argtypes = [i32, i32, vp]
+    lib.oracle_nonempty_blocks.argtypes = [i32, i32, vp]
+    lib.oracle_ca_run.argtypes = [i32, i64, i64, i64, i64, vp, i32, vp]
+    lib.oracle_ca_run.restype = i32
+    lib.oracle_heat_run.argtypes = [i32, i64, i64, i64, i64, vp,
+                                    ctypes.c_double, i32, vp]
+    lib.oracle_heat_run.restype = i32
+    lib.oracle_threads.restype = i32
+    _lib = lib
+    return lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's steppers use."""
+    return _load().oracle_threads()
+
+
+def member(x: int, y: int, k: int) -> bool:
+    """Gasket membership, (x & y) == 0 inside [0, 2^k)^2 (Section 6.1 test,
+    mirrored)."""
+    return bool(_load().oracle_member(x, y, k))
+
+
+def count_members(k: int) -> int:
+    """Brute-force member count of the level-k gasket (Eq. 2 says 3^k)."""
+    return int(_load().oracle_count_members(k))
+
+
+def grid_dims(rb: int):
+    """Compact grid 3^ceil(rb/2) x 3^floor(rb/2) (Lemma 2)."""
+    gx, gy = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().oracle_grid_dims(rb, ctypes.byref(gx), ctypes.byref(gy))
+    return int(gx.value), int(gy.value)
+
+
+def lambda_paper(rb: int, wx: int, wy: int):
+    """lambda(omega) in the paper's orientation (Theorem 1, Section 6.1)."""
+    lx, ly = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().oracle_lambda_paper(rb, wx, wy, ctypes.byref(lx), ctypes.byref(ly))
+    return int(lx.value), int(ly.value)
+
+
+def lambda_(rb: int, wx: int, wy: int):
+    """lambda(omega) for the (x & y) == 0 embedding (paper's value mirrored)."""
+    lx, ly = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().oracle_lambda(rb, wx, wy, ctypes.byref(lx), ctypes.byref(ly))
+    return int(lx.value), int(ly.value)
+
+
+def lambda_grid(rb: int, paper_orient: bool = False) -> np.ndarray:
+    """lambda over the whole compact grid: array (gy, gx, 2) uint32,
+    [wy, wx] = (lambda_x, lambda_y)."""
+    gx, gy = grid_dims(rb)
+    out = np.zeros((gy, gx, 2), dtype=np.uint32)
+    _load().oracle_lambda_grid(rb, int(paper_orient), out.ctypes.data)
+    return out
+
+
+def nonempty_blocks(k: int, r: int) -> np.ndarray:
+    """(n_b, n_b) uint8 mask of blocks holding a member, by scanning cells
+    (what the bounding-box approach discards: Section 1, Section 6.2)."""
+    nb = 1 << (k - r)
+    out = np.zeros((nb, nb), dtype=np.uint8)
+    _load().oracle_nonempty_blocks(k, r, out.ctypes.data)
+    return out
+
+
+def ca_run(k: int, state: np.ndarray, steps: int, x0: int = 0,
+           y0: int = 0) -> np.ndarray:
+    """`steps` automaton steps (Section 6.2 test CA, rule B3/S23) on the
+    window whose top-left cell is (x0, y0); `state` is (h, w) uint8."""
+    a = np.ascontiguousarray(state, dtype=np.uint8)
+    h, w = a.shape
+    out = np.empty_like(a)
+    rc = _load().oracle_ca_run(k, x0, y0, w, h, a.ctypes.data, steps,
+                               out.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_ca_run: out of memory")
+    return out
+
+
+def heat_run(k: int, state: np.ndarray, alpha: float, steps: int,
+             x0: int = 0, y0: int = 0) -> np.ndarray:
+    """`steps` float64 heat steps (5-point, Dirichlet 0 off the gasket) on the
+    window whose top-left cell is (x0, y0)."""
+    a = np.ascontiguousarray(state, dtype=np.float64)
+    h, w = a.shape
+    out = np.empty_like(a)
+    rc = _load().oracle_heat_run(k, x0, y0, w, h, a.ctypes.data,
+                                 float(alpha), steps, out.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_heat_run: out of memory")
+    return out
+
+
+def valid_interior(k: int, x0: int, y0: int, w: int, h: int, steps: int):
+    """Slices (rows, cols) of a window result that are exact after `steps`
+    steps: cells within `steps` of a window edge that is not an array edge
+    may have seen the zeros assumed outside the window."""
+    n = 1 << k
+    lo_x = 0 if x0 <= 0 else steps
+    lo_y = 0 if y0 <= 0 else steps
+    hi_x = w if x0 + w >= n else w - steps
+    hi_y = h if y0 + h >= n else h - steps
+    return slice(lo_y, max(lo_y, hi_y)), slice(lo_x, max(lo_x, hi_x))
