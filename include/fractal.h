@@ -1,0 +1,230 @@
+/*
+ * fractal.h -- C ABI of libfractal: the block-space map lambda(omega) on an
+ * embedded Sierpinski gasket (arXiv 2004.13475, Sections 3-6) and the
+ * neighbourhood kernels it drives, for AMD Instinct MI355X (gfx950).
+ *
+ * Geometry.  A level-k gasket lives in an n x n embedding, n = 2^k.  Cell
+ * (x, y) -- x the column, y the row -- is a member iff (x & y) == 0; there are
+ * 3^k members (Eq. 2).  This is the vertical mirror of the paper's
+ * orientation (its intra-block test in Section 6.1 reads x & (b-1-y) == 0);
+ * every lambda value below is given for the (x & y) == 0 orientation.
+ * Work is cut into rho x rho tiles (blocks in the paper), rho = 2^r; the
+ * block space has side n_b = 2^(k-r) and level r_b = k - r, and exactly
+ * 3^r_b tiles hold members.
+ *
+ * Buffers.  Every state buffer is a caller-owned, row-major n x n array in
+ * device memory: cell (x, y) sits at element (size_t)y * n + x.  Cells are
+ * uint8 in {0, 1} for the automaton (rule FRACTAL_RULE_CA) and float32 for
+ * heat (FRACTAL_RULE_HEAT).  The two buffers of a step call must not overlap,
+ * and BOTH must hold 0 in every off-gasket cell on entry: the lambda kernels
+ * never visit empty tiles, and every kernel writes only the 16-byte chunks
+ * that contain a member (off-gasket cells inside them are written as 0).
+ * After `steps` steps the state is in buf[steps & 1] (buf0 when steps is even);
+ * steps == 0 does nothing.
+ *
+ * Asynchrony and errors.  `stream` is a hipStream_t (NULL = the null stream).
+ * Calls enqueue work on it and return without waiting.  Every call returns a
+ * status; arguments are checked on the host before anything is enqueued, and
+ * a call that fails validation has no side effect.  fractal_last_error()
+ * returns a message for the calling thread's last failure.  Device buffers
+ * are never allocated on the step paths.
+ */
+#ifndef FRACTAL_H
+#define FRACTAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FRACTAL_OK 0
+#define FRACTAL_E_INVAL 1  /* bad argument; nothing was enqueued */
+#define FRACTAL_E_NOMEM 2  /* a request larger than the serving arena */
+#define FRACTAL_E_DEVICE 3 /* a HIP runtime call or kernel launch failed */
+#define FRACTAL_E_AGAIN 4  /* result not ready yet (serving poll) */
+
+/* neighbourhood rules */
+#define FRACTAL_RULE_CA 0   /* uint8 B3/S23 automaton, Moore neighbourhood,
+                               only gasket members counted (Section 6.2,
+                               test CA) */
+#define FRACTAL_RULE_HEAT 1 /* float32 explicit 5-point heat step,
+                               u' = (1-4a)u + a(uN+uS+uE+uW) on members,
+                               off-gasket neighbours count as 0 */
+
+/* workgroup dispatch orders (a bijection from hardware workgroup id to the
+ * tile it handles; results do not depend on it) */
+#define FRACTAL_ORDER_NATURAL 0 /* omega = (blockIdx.x, blockIdx.y)         */
+#define FRACTAL_ORDER_CURVE 1   /* lambda: omega taken along the gasket's
+                                   self-similar order (base-3 digits of the
+                                   linear id are the beta_mu); BB: row-major */
+#define FRACTAL_ORDER_CURVE_XCD 2 /* as CURVE, with contiguous id ranges per
+                                     accelerator die (XCD) so neighbouring
+                                     tiles share an L2 */
+
+#define FRACTAL_R_AUTO (-1) /* use the tuned (or default) tile size */
+
+/* Launch parameters of a step kernel. */
+typedef struct fractal_tuning {
+    int r;       /* log2 of the tile side rho, 0..6 (rho <= 64)            */
+    int threads; /* threads per workgroup: 64 or 256                        */
+    int order;   /* FRACTAL_ORDER_*                                         */
+    int reserved;
+} fractal_tuning;
+
+/* Lemma 2 / Theorem 1: dimensions of the compact launch grid for a level-k
+ * gasket cut into 2^r tiles: gx = 3^ceil(r_b/2), gy = 3^floor(r_b/2),
+ * r_b = k - r.  Host only.  0 <= r <= k <= 40.  Returns FRACTAL_E_INVAL on a
+ * bad level or a NULL output pointer. */
+int fractal_grid_dims(int k, int r, uint32_t *gx, uint32_t *gy);
+
+/* Theorem 1 and Section 6.1: evaluate lambda(omega) for every omega of the
+ * compact grid and write d_xy[2*(wy*gx + wx) + 0] = lambda_x,
+ * d_xy[... + 1] = lambda_y (block coordinates, (x & y) == 0 orientation).
+ * d_xy: device array of 2*gx*gy uint32, caller-owned.  0 <= r <= k,
+ * k - r <= 30.  One workgroup per omega; each wavefront computes the base-3
+ * digits beta_mu in its lanes and assembles lambda with two ballots. */
+int fractal_lambda_map(int k, int r, uint32_t *d_xy, void *stream);
+
+/* Section 6.3, Variant 1: the same map with the sum of offsets done by one
+ * matrix-core product per workgroup (row 0 of A holds 2^0..2^(r_b-1) in
+ * float16, columns 0 and 1 of B hold tau_x and tau_y; D[0][0..1] is lambda
+ * before mirroring).  Exact for k - r <= 16; larger levels give E_INVAL. */
+int fractal_lambda_map_mfma(int k, int r, uint32_t *d_xy, void *stream);
+
+/* Seeded initial state: writes all n*n cells of d_buf.  Members get
+ * SplitMix64 output number i+1 (state 0), i = stream_id * 2^32 + y*n + x:
+ * the automaton takes its top bit, heat takes (z >> 40) * 2^-24; other
+ * cells get 0.  0 <= k <= 16. */
+int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
+                      void *stream);
+
+/* Bounding-box step (Section 1; Section 6.2): a grid of all (n/rho)^2
+ * workgroups with the identity map omega -> tile; a workgroup whose tile
+ * holds no member exits at once.  Runs `steps` synchronous steps of `rule`
+ * ping-ponging between d_buf0 (input of step 0) and d_buf1.
+ * 0 <= k <= 16, 0 <= r <= min(k, 6) or FRACTAL_R_AUTO, alpha ignored for the
+ * automaton and 0 < alpha <= 0.25 for heat, steps >= 0. */
+int fractal_bb_step(int k, int r, int rule, float alpha, void *d_buf0,
+                    void *d_buf1, int steps, void *stream);
+
+/* lambda step (Theorem 1, Sections 5 and 6.1): a compact grid of exactly
+ * 3^(k-r) workgroups, each mapped by lambda(omega) to a non-empty tile; the
+ * tile and a 1-cell halo are staged in LDS and the rule is applied to the
+ * members (bounding sub-box intra-block mapping).  Arguments as for
+ * fractal_bb_step.  Result is bit-identical to fractal_bb_step. */
+int fractal_lambda_step(int k, int r, int rule, float alpha, void *d_buf0,
+                        void *d_buf1, int steps, void *stream);
+
+/* fractal_lambda_step with lambda computed by the matrix-core product of
+ * fractal_lambda_map_mfma.  Same arguments and results; k - r <= 16. */
+int fractal_lambda_step_mfma(int k, int r, int rule, float alpha,
+                             void *d_buf0, void *d_buf1, int steps,
+                             void *stream);
+
+/* lambda step (map 0) or bounding-box step (map 1) or matrix-core lambda
+ * step (map 2) with explicit launch parameters.  Same buffer contract. */
+int fractal_step_tuned(int map, int k, int rule, float alpha, void *d_buf0,
+                       void *d_buf1, int steps, const fractal_tuning *tuning,
+                       void *stream);
+
+/* Autotuner: times every supported (r, threads, order) for this level and
+ * rule on the given buffers (a few steps each, synchronising `stream`) and
+ * records the fastest lambda launch in a per-process cache keyed by
+ * (device, k, rule).  The buffers must satisfy the step contract; they end up
+ * holding a state advanced by some number of steps.  `out` may be NULL. */
+int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1,
+                     void *stream, fractal_tuning *out);
+
+/* Tuning used for FRACTAL_R_AUTO: the cached autotuned entry for
+ * (current device, k, rule) if one exists, else a built-in default. */
+int fractal_get_tuning(int k, int rule, fractal_tuning *out);
+
+/* Replace the cached entry for (current device, k, rule). */
+int fractal_set_tuning(int k, int rule, const fractal_tuning *tuning);
+
+/* One gasket of a batch. */
+typedef struct fractal_instance {
+    int k;       /* level, 0..16                                  */
+    int rule;    /* FRACTAL_RULE_*                                */
+    int steps;   /* >= 0                                          */
+    float alpha; /* heat only                                     */
+    void *d_buf0; /* state at step 0; result in buf[steps & 1]    */
+    void *d_buf1;
+} fractal_instance;
+
+/* Advance many gaskets of uneven levels together.  Each step is one launch
+ * of a persistent kernel whose workgroups walk a device table of tiles
+ * (per-instance prefix offsets of 3^(k_i - r_i), lambda per instance); the
+ * max_i steps_i launches are captured once into a HIP graph and the graph is
+ * launched on `stream`.  Instances with fewer steps drop out of later
+ * launches.  `tuning` may be NULL (per-level defaults / cached tuning).
+ * Results are bit-identical to one fractal_lambda_step call per instance.
+ * The call allocates a device table (freed when the graph has run) and
+ * returns after enqueuing; it synchronises nothing else.  count <= 65536. */
+int fractal_batch_step(const fractal_instance *inst, int count,
+                       const fractal_tuning *tuning, void *stream);
+
+/* ---------------------------------------------------------------- serving
+ * A request server keeps gasket simulations resident in a caller-provided
+ * device arena and advances all admitted ones together (continuous batching
+ * at step granularity): each iteration is a group of batched launches over
+ * every active slot; requests that arrive meanwhile are admitted, first come
+ * first served, as soon as both a slot and arena space are free. */
+typedef struct fractal_request {
+    int k, rule, steps;
+    float alpha;
+    uint32_t seed;      /* stream id of the seeded state when h_init == NULL */
+    const void *h_init; /* n*n host cells, or NULL for the seeded state; must
+                           stay valid until poll returns FRACTAL_OK          */
+    void *h_out;        /* n*n host cells receiving the final state, or NULL
+                           (then only the checksum is produced)              */
+    double t_arrival;   /* caller's arrival stamp (seconds, any origin used
+                           consistently with fractal_now); < 0 = now         */
+} fractal_request;
+
+typedef struct fractal_result {
+    int status;       /* FRACTAL_OK, or the error of this request          */
+    int reserved;
+    double t_arrival; /* stamps in seconds on the fractal_now() clock      */
+    double t_admit;
+    double t_done;
+    uint64_t checksum; /* sum over cells of the final state's bit patterns
+                          (uint8 value or float32 bits), modulo 2^64       */
+} fractal_result;
+
+/* Monotonic clock (seconds) used for every serving stamp. */
+double fractal_now(void);
+
+/* Create a server over d_arena (arena_bytes of device memory owned by the
+ * caller, 256-byte aligned) with at most max_slots concurrently admitted
+ * requests, working on `stream`.  steps_per_iter is the number of batched
+ * step launches per scheduling iteration (>= 1).  A host thread is started. */
+int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots,
+                         int steps_per_iter, void *stream, void **server);
+
+/* Queue a request; never waits for the GPU.  A request whose footprint
+ * (2 * 4^k cells, plus alignment) exceeds the arena fails with
+ * FRACTAL_E_NOMEM, a malformed one with FRACTAL_E_INVAL. */
+int fractal_serve_submit(void *server, const fractal_request *rq,
+                         uint64_t *ticket);
+
+/* FRACTAL_OK and *res filled once the ticket is done (then the ticket is
+ * forgotten), FRACTAL_E_AGAIN while it is pending, FRACTAL_E_INVAL for an
+ * unknown ticket. */
+int fractal_serve_poll(void *server, uint64_t ticket, fractal_result *res);
+
+/* Stop the server thread after the queued work has drained and free its
+ * host state.  Outstanding tickets are completed first. */
+int fractal_serve_destroy(void *server);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *fractal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRACTAL_H */

@@ -1,0 +1,11 @@
+"""Block-space map lambda(omega) on embedded Sierpinski gaskets for MI355X.
+
+Python face of libfractal.so (hand-written HIP for gfx950).  See
+include/fractal.h for the C ABI; every function here forwards to it.
+"""
+from ._lib import (  # noqa: F401
+    E_AGAIN, E_DEVICE, E_INVAL, E_NOMEM, EXPORTED, LIB_PATH, MAP_BB, MAP_LAMBDA,
+    MAP_MFMA, OK, ORDER_CURVE, ORDER_CURVE_XCD, ORDER_NATURAL, R_AUTO, RULE_CA,
+    RULE_HEAT, FractalError, Server, autotune, batch_step, bb_step,
+    exported_symbols, get_tuning, grid_dims, lambda_map, lambda_map_mfma,
+    lambda_step, lambda_step_mfma, load, now, seed_fill, set_tuning, step_tuned)

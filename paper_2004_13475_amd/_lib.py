@@ -1,0 +1,254 @@
+"""ctypes binding of libfractal.so (argument marshalling only).
+
+Every function forwards to the C entry point of the same name in
+include/fractal.h; all computation happens in the library's HIP kernels.
+Device buffers are passed as torch tensors (or raw integer addresses) and
+streams as torch streams, raw hipStream_t integers or None (torch's current
+stream).  A missing library is an error: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfractal.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_AGAIN = 0, 1, 2, 3, 4
+RULE_CA, RULE_HEAT = 0, 1
+ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
+MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
+R_AUTO = -1
+
+EXPORTED = [
+    "fractal_grid_dims", "fractal_lambda_map", "fractal_lambda_map_mfma",
+    "fractal_seed_fill", "fractal_bb_step", "fractal_lambda_step",
+    "fractal_lambda_step_mfma", "fractal_step_tuned", "fractal_autotune",
+    "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_step",
+    "fractal_now", "fractal_serve_create", "fractal_serve_submit",
+    "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
+]
+
+
+class FractalError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfractal error {code}: {msg}")
+        self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int), ("threads", ctypes.c_int),
+                ("order", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.r, self.threads, self.order)
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("rule", ctypes.c_int),
+                ("steps", ctypes.c_int), ("alpha", ctypes.c_float),
+                ("d_buf0", ctypes.c_void_p), ("d_buf1", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("rule", ctypes.c_int),
+                ("steps", ctypes.c_int), ("alpha", ctypes.c_float),
+                ("seed", ctypes.c_uint32), ("h_init", ctypes.c_void_p),
+                ("h_out", ctypes.c_void_p), ("t_arrival", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("checksum", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libfractal.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with paper_2004_13475_amd.build "
+            "(or __graft_entry__.build()); there is no non-HIP fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    i, u32, f, vp = ctypes.c_int, ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p
+    pu32 = ctypes.POINTER(u32)
+    sig = {
+        "fractal_grid_dims": ([i, i, pu32, pu32], i),
+        "fractal_lambda_map": ([i, i, vp, vp], i),
+        "fractal_lambda_map_mfma": ([i, i, vp, vp], i),
+        "fractal_seed_fill": ([i, i, u32, vp, vp], i),
+        "fractal_bb_step": ([i, i, i, f, vp, vp, i, vp], i),
+        "fractal_lambda_step": ([i, i, i, f, vp, vp, i, vp], i),
+        "fractal_lambda_step_mfma": ([i, i, i, f, vp, vp, i, vp], i),
+        "fractal_step_tuned": ([i, i, i, f, vp, vp, i, ctypes.POINTER(Tuning), vp], i),
+        "fractal_autotune": ([i, i, f, vp, vp, vp, ctypes.POINTER(Tuning)], i),
+        "fractal_get_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
+        "fractal_set_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
+        "fractal_batch_step": ([ctypes.POINTER(Instance), i, ctypes.POINTER(Tuning), vp], i),
+        "fractal_now": ([], ctypes.c_double),
+        "fractal_serve_create": ([vp, ctypes.c_size_t, i, i, vp, ctypes.POINTER(vp)], i),
+        "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
+        "fractal_serve_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(Result)], i),
+        "fractal_serve_destroy": ([vp], i),
+        "fractal_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        if not hasattr(lib, name):
+            continue  # reported by exported_symbols(); calls raise AttributeError
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names of EXPORTED that the loaded library defines."""
+    lib = load()
+    return [n for n in EXPORTED if hasattr(lib, n)]
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = load().fractal_last_error().decode(errors="replace")
+        raise FractalError(rc, msg)
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def grid_dims(k: int, r: int):
+    gx, gy = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().fractal_grid_dims(k, r, ctypes.byref(gx), ctypes.byref(gy)))
+    return gx.value, gy.value
+
+
+def lambda_map(k, r, out, stream=None):
+    return _check(load().fractal_lambda_map(k, r, _ptr(out), _stream(stream)))
+
+
+def lambda_map_mfma(k, r, out, stream=None):
+    return _check(load().fractal_lambda_map_mfma(k, r, _ptr(out), _stream(stream)))
+
+
+def seed_fill(k, rule, stream_id, buf, stream=None):
+    return _check(load().fractal_seed_fill(k, rule, stream_id, _ptr(buf), _stream(stream)))
+
+
+def bb_step(k, r, rule, alpha, buf0, buf1, steps, stream=None):
+    return _check(load().fractal_bb_step(k, r, rule, alpha, _ptr(buf0), _ptr(buf1),
+                                         steps, _stream(stream)))
+
+
+def lambda_step(k, r, rule, alpha, buf0, buf1, steps, stream=None):
+    return _check(load().fractal_lambda_step(k, r, rule, alpha, _ptr(buf0), _ptr(buf1),
+                                             steps, _stream(stream)))
+
+
+def lambda_step_mfma(k, r, rule, alpha, buf0, buf1, steps, stream=None):
+    return _check(load().fractal_lambda_step_mfma(k, r, rule, alpha, _ptr(buf0),
+                                                  _ptr(buf1), steps, _stream(stream)))
+
+
+def step_tuned(map_, k, rule, alpha, buf0, buf1, steps, r, threads, order, stream=None):
+    t = Tuning(r, threads, order, 0)
+    return _check(load().fractal_step_tuned(map_, k, rule, alpha, _ptr(buf0), _ptr(buf1),
+                                            steps, ctypes.byref(t), _stream(stream)))
+
+
+def autotune(k, rule, alpha, buf0, buf1, stream=None):
+    t = Tuning()
+    _check(load().fractal_autotune(k, rule, alpha, _ptr(buf0), _ptr(buf1),
+                                   _stream(stream), ctypes.byref(t)))
+    return t.as_tuple()
+
+
+def get_tuning(k, rule):
+    t = Tuning()
+    _check(load().fractal_get_tuning(k, rule, ctypes.byref(t)))
+    return t.as_tuple()
+
+
+def set_tuning(k, rule, r, threads, order):
+    t = Tuning(r, threads, order, 0)
+    return _check(load().fractal_set_tuning(k, rule, ctypes.byref(t)))
+
+
+def batch_step(instances, tuning=None, stream=None):
+    """instances: list of (k, rule, steps, alpha, buf0, buf1)."""
+    arr = (Instance * len(instances))()
+    for j, (k, rule, steps, alpha, b0, b1) in enumerate(instances):
+        arr[j] = Instance(k, rule, steps, alpha, _ptr(b0), _ptr(b1))
+    tp = None
+    if tuning is not None:
+        tp = ctypes.byref(Tuning(*tuning, 0) if len(tuning) == 3 else Tuning(*tuning))
+    return _check(load().fractal_batch_step(arr, len(instances), tp, _stream(stream)))
+
+
+def now() -> float:
+    return load().fractal_now()
+
+
+class Server:
+    """Handle on a libfractal request server (continuous batching)."""
+
+    def __init__(self, arena, arena_bytes, max_slots, steps_per_iter=8, stream=None):
+        h = ctypes.c_void_p()
+        _check(load().fractal_serve_create(_ptr(arena), arena_bytes, max_slots,
+                                           steps_per_iter, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, k, rule, steps, alpha=0.2, seed=0, h_init=None, h_out=None,
+               t_arrival=-1.0):
+        """h_init / h_out: numpy arrays (kept alive until the ticket is polled)."""
+        rq = Request(k, rule, steps, alpha, seed,
+                     None if h_init is None else h_init.ctypes.data,
+                     None if h_out is None else h_out.ctypes.data, t_arrival)
+        t = ctypes.c_uint64()
+        _check(load().fractal_serve_submit(self._h, ctypes.byref(rq), ctypes.byref(t)))
+        self._keep[t.value] = (h_init, h_out)
+        return t.value
+
+    def poll(self, ticket):
+        """Result (status, t_arrival, t_admit, t_done, checksum) or None."""
+        res = Result()
+        rc = load().fractal_serve_poll(self._h, ticket, ctypes.byref(res))
+        if rc == E_AGAIN:
+            return None
+        _check(rc)
+        self._keep.pop(ticket, None)
+        return (res.status, res.t_arrival, res.t_admit, res.t_done, res.checksum)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().fractal_serve_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

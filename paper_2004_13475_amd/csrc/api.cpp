@@ -1,0 +1,345 @@
+// api.cpp -- the C ABI of libfractal: argument validation, error reporting,
+// tuning cache, autotuner and the map / step entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fractal {
+
+static thread_local std::string g_error;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return FRACTAL_OK;
+    return set_error(FRACTAL_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool ranges_overlap(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+int check_step_args(int k, int r, int rule, float alpha, const void *b0, const void *b1,
+                    int steps)
+{
+    if (k < 0 || k > kMaxStepLevel)
+        return set_error(FRACTAL_E_INVAL, "level k=%d outside [0, %d]", k, kMaxStepLevel);
+    if (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT)
+        return set_error(FRACTAL_E_INVAL, "unknown rule %d", rule);
+    if (r != FRACTAL_R_AUTO) {
+        if (r < 0 || r > k || r > kMaxR)
+            return set_error(FRACTAL_E_INVAL, "tile level r=%d outside [0, min(k=%d, %d)]", r,
+                             k, kMaxR);
+        if (k - r > kMaxBlockLevel)
+            return set_error(FRACTAL_E_INVAL, "block level k-r=%d above %d", k - r,
+                             kMaxBlockLevel);
+    }
+    if (rule == FRACTAL_RULE_HEAT && !(std::isfinite(alpha) && alpha > 0.0f && alpha <= 0.25f))
+        return set_error(FRACTAL_E_INVAL, "heat coefficient alpha=%g outside (0, 0.25]",
+                         (double)alpha);
+    if (steps < 0)
+        return set_error(FRACTAL_E_INVAL, "negative step count %d", steps);
+    if (!b0 || !b1)
+        return set_error(FRACTAL_E_INVAL, "null state buffer");
+    if (ranges_overlap(b0, b1, state_bytes(k, rule)))
+        return set_error(FRACTAL_E_INVAL, "state buffers overlap");
+    const size_t align = rule == FRACTAL_RULE_CA ? 16u : 16u;
+    if ((reinterpret_cast<uintptr_t>(b0) | reinterpret_cast<uintptr_t>(b1)) % align)
+        return set_error(FRACTAL_E_INVAL, "state buffers must be 16-byte aligned");
+    return FRACTAL_OK;
+}
+
+static int default_threads(int rule, int r)
+{
+    // one 16-byte chunk per lane: 256 threads once a tile has >= 256 chunks
+    const int row_bytes = (1 << r) * (int)cell_bytes(rule);
+    const int chunks = row_bytes >= 16 ? (row_bytes / 16) << r : (1 << r);
+    return chunks >= 256 ? 256 : 64;
+}
+
+fractal_tuning tuning_for_r(int map, int k, int rule, int r)
+{
+    (void)k;
+    fractal_tuning t;
+    t.r = r;
+    t.threads = default_threads(rule, r);
+    t.order = map == MAP_BB ? FRACTAL_ORDER_NATURAL : FRACTAL_ORDER_CURVE_XCD;
+    t.reserved = 0;
+    return t;
+}
+
+static int clamp_r(int k, int r)
+{
+    if (r > k)
+        r = k;
+    if (k - r > kMaxBlockLevel)
+        r = k - kMaxBlockLevel;
+    return r;
+}
+
+static fractal_tuning builtin_default(int k, int rule)
+{
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 5 : 4);
+    return tuning_for_r(MAP_LAMBDA, k, rule, r);
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, fractal_tuning> g_tune;
+
+static int current_device()
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess)
+        d = 0;
+    return d;
+}
+
+fractal_tuning default_tuning(int k, int rule)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(current_device(), k, rule));
+    if (it != g_tune.end())
+        return it->second;
+    return builtin_default(k, rule);
+}
+
+int check_tuning(int map, int k, int rule, const fractal_tuning *t)
+{
+    if (!t)
+        return set_error(FRACTAL_E_INVAL, "null tuning");
+    if (map != MAP_LAMBDA && map != MAP_BB && map != MAP_MFMA)
+        return set_error(FRACTAL_E_INVAL, "unknown map %d", map);
+    if (t->r < 0 || t->r > k || t->r > kMaxR || k - t->r > kMaxBlockLevel)
+        return set_error(FRACTAL_E_INVAL, "tuning r=%d invalid for k=%d", t->r, k);
+    if (t->threads != 64 && t->threads != 256)
+        return set_error(FRACTAL_E_INVAL, "threads=%d must be 64 or 256", t->threads);
+    if (t->order < FRACTAL_ORDER_NATURAL || t->order > FRACTAL_ORDER_CURVE_XCD)
+        return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
+    (void)rule;
+    return FRACTAL_OK;
+}
+
+static int step_entry(int map, int k, int r, int rule, float alpha, void *b0, void *b1,
+                      int steps, void *stream)
+{
+    int rc = check_step_args(k, r, rule, alpha, b0, b1, steps);
+    if (rc)
+        return rc;
+    fractal_tuning t;
+    if (r == FRACTAL_R_AUTO) {
+        t = default_tuning(k, rule);
+        if (map == MAP_BB)
+            t = tuning_for_r(MAP_BB, k, rule, t.r);
+    } else {
+        t = tuning_for_r(map, k, rule, r);
+    }
+    if (map == MAP_MFMA && k - t.r > 16)
+        return set_error(FRACTAL_E_INVAL, "matrix-core lambda needs k-r <= 16");
+    if (steps == 0)
+        return FRACTAL_OK;
+    return launch_steps(map, k, rule, alpha, b0, b1, steps, t, static_cast<hipStream_t>(stream));
+}
+
+} // namespace fractal
+
+using namespace fractal;
+
+extern "C" {
+
+const char *fractal_last_error(void) { return g_error.c_str(); }
+
+int fractal_grid_dims(int k, int r, uint32_t *gx, uint32_t *gy)
+{
+    if (!gx || !gy)
+        return set_error(FRACTAL_E_INVAL, "null output pointer");
+    if (k < 0 || k > 40 || r < 0 || r > k)
+        return set_error(FRACTAL_E_INVAL, "need 0 <= r <= k <= 40 (k=%d r=%d)", k, r);
+    const int rb = k - r;
+    *gx = (uint32_t)pow3_u64((rb + 1) / 2);
+    *gy = (uint32_t)pow3_u64(rb / 2);
+    return FRACTAL_OK;
+}
+
+static int map_entry(int k, int r, uint32_t *d_xy, void *stream, bool mfma)
+{
+    if (!d_xy)
+        return set_error(FRACTAL_E_INVAL, "null output buffer");
+    if (k < 0 || r < 0 || r > k || k - r > 30)
+        return set_error(FRACTAL_E_INVAL, "need 0 <= r <= k and k-r <= 30 (k=%d r=%d)", k, r);
+    if (mfma && k - r > 16)
+        return set_error(FRACTAL_E_INVAL, "matrix-core lambda needs k-r <= 16 (got %d)", k - r);
+    return launch_lambda_map(k, r, d_xy, mfma, static_cast<hipStream_t>(stream));
+}
+
+int fractal_lambda_map(int k, int r, uint32_t *d_xy, void *stream)
+{
+    return map_entry(k, r, d_xy, stream, false);
+}
+
+int fractal_lambda_map_mfma(int k, int r, uint32_t *d_xy, void *stream)
+{
+    return map_entry(k, r, d_xy, stream, true);
+}
+
+int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf, void *stream)
+{
+    if (k < 0 || k > kMaxStepLevel)
+        return set_error(FRACTAL_E_INVAL, "level k=%d outside [0, %d]", k, kMaxStepLevel);
+    if (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT)
+        return set_error(FRACTAL_E_INVAL, "unknown rule %d", rule);
+    if (!d_buf)
+        return set_error(FRACTAL_E_INVAL, "null buffer");
+    if (reinterpret_cast<uintptr_t>(d_buf) % 16)
+        return set_error(FRACTAL_E_INVAL, "buffer must be 16-byte aligned");
+    return launch_seed_fill(k, rule, stream_id, d_buf, static_cast<hipStream_t>(stream));
+}
+
+int fractal_bb_step(int k, int r, int rule, float alpha, void *d_buf0, void *d_buf1, int steps,
+                    void *stream)
+{
+    return step_entry(MAP_BB, k, r, rule, alpha, d_buf0, d_buf1, steps, stream);
+}
+
+int fractal_lambda_step(int k, int r, int rule, float alpha, void *d_buf0, void *d_buf1,
+                        int steps, void *stream)
+{
+    return step_entry(MAP_LAMBDA, k, r, rule, alpha, d_buf0, d_buf1, steps, stream);
+}
+
+int fractal_lambda_step_mfma(int k, int r, int rule, float alpha, void *d_buf0, void *d_buf1,
+                             int steps, void *stream)
+{
+    return step_entry(MAP_MFMA, k, r, rule, alpha, d_buf0, d_buf1, steps, stream);
+}
+
+int fractal_step_tuned(int map, int k, int rule, float alpha, void *d_buf0, void *d_buf1,
+                       int steps, const fractal_tuning *tuning, void *stream)
+{
+    int rc = check_tuning(map, k, rule, tuning);
+    if (rc)
+        return rc;
+    rc = check_step_args(k, tuning->r, rule, alpha, d_buf0, d_buf1, steps);
+    if (rc)
+        return rc;
+    if (map == MAP_MFMA && k - tuning->r > 16)
+        return set_error(FRACTAL_E_INVAL, "matrix-core lambda needs k-r <= 16");
+    if (steps == 0)
+        return FRACTAL_OK;
+    return launch_steps(map, k, rule, alpha, d_buf0, d_buf1, steps, *tuning,
+                        static_cast<hipStream_t>(stream));
+}
+
+int fractal_get_tuning(int k, int rule, fractal_tuning *out)
+{
+    if (!out)
+        return set_error(FRACTAL_E_INVAL, "null output");
+    if (k < 0 || k > kMaxStepLevel || (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT))
+        return set_error(FRACTAL_E_INVAL, "bad level or rule");
+    *out = default_tuning(k, rule);
+    return FRACTAL_OK;
+}
+
+int fractal_set_tuning(int k, int rule, const fractal_tuning *t)
+{
+    if (k < 0 || k > kMaxStepLevel || (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT))
+        return set_error(FRACTAL_E_INVAL, "bad level or rule");
+    int rc = check_tuning(MAP_LAMBDA, k, rule, t);
+    if (rc)
+        return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(current_device(), k, rule)] = *t;
+    return FRACTAL_OK;
+}
+
+int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, void *stream,
+                     fractal_tuning *out)
+{
+    int rc = check_step_args(k, FRACTAL_R_AUTO, rule, alpha, d_buf0, d_buf1, 0);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if ((rc = hip_error(hipEventCreate(&e0), "event create")))
+        return rc;
+    if ((rc = hip_error(hipEventCreate(&e1), "event create"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    // Few-step timings; enough launches that per-launch gaps are included.
+    const int reps = k >= 15 ? 4 : (k >= 12 ? 16 : 64);
+    fractal_tuning best{};
+    float best_ms = 1e30f;
+    std::vector<fractal_tuning> cands;
+    for (int r = 0; r <= kMaxR && r <= k; ++r) {
+        if (k - r > kMaxBlockLevel)
+            continue;
+        const int row_bytes = (1 << r) * (int)cell_bytes(rule);
+        if (row_bytes < 16 && k >= 8)
+            continue; // tiles below one 16-byte chunk per row are never faster here
+        for (int th : {64, 256}) {
+            if (th == 256 && default_threads(rule, r) == 64 && r < 5)
+                continue;
+            for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE_XCD}) {
+                fractal_tuning t{r, th, order, 0};
+                cands.push_back(t);
+            }
+        }
+    }
+    for (const fractal_tuning &t : cands) {
+        // warm-up (even count keeps the state in buf0)
+        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 2, t, s);
+        if (!rc)
+            rc = hip_error(hipEventRecord(e0, s), "event record");
+        if (!rc)
+            rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, reps, t, s);
+        if (!rc)
+            rc = hip_error(hipEventRecord(e1, s), "event record");
+        if (!rc)
+            rc = hip_error(hipEventSynchronize(e1), "event sync");
+        float ms = 0.0f;
+        if (!rc)
+            rc = hip_error(hipEventElapsedTime(&ms, e0, e1), "event time");
+        if (rc)
+            break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc)
+        return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::make_tuple(current_device(), k, rule)] = best;
+    }
+    if (out)
+        *out = best;
+    return FRACTAL_OK;
+}
+
+} // extern "C"

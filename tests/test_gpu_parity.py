@@ -1,0 +1,233 @@
+"""GPU parity: lambda map, seeded fill, lambda / bounding-box / matrix-core
+steps against the CPU oracle, through the C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+import fractal_inputs as fi
+import oracle
+import paper_2004_13475_amd as F
+from gpu_util import (ALPHA, assert_match, heat_err, oracle_steps, to_device,
+                      torch_dev, window_plan, zeros_state)
+
+pytestmark = pytest.mark.gpu
+
+RULES = [fi.RULE_CA, fi.RULE_HEAT]
+MAPS = [F.MAP_LAMBDA, F.MAP_BB, F.MAP_MFMA]
+
+
+def _sync():
+    torch_dev().cuda.synchronize()
+
+
+# ------------------------------------------------------------------ map
+@pytest.mark.parametrize("mfma", [False, True])
+def test_lambda_map_all_levels(mfma):
+    torch = torch_dev()
+    for rb in range(0, 13):
+        for r in (0, 3):
+            k = rb + r
+            gx, gy = F.grid_dims(k, r)
+            out = torch.zeros(gx * gy * 2, dtype=torch.int32, device="cuda")
+            (F.lambda_map_mfma if mfma else F.lambda_map)(k, r, out)
+            _sync()
+            got = out.cpu().numpy().view(np.uint32).reshape(gy, gx, 2)
+            want = oracle.lambda_grid(rb)
+            assert np.array_equal(got, want), f"rb={rb} r={r} mfma={mfma}"
+
+
+@pytest.mark.parametrize("mfma", [False, True])
+def test_lambda_map_large_levels_sampled(mfma):
+    torch = torch_dev()
+    rng = np.random.default_rng(5)
+    levels = [13, 14, 15, 16] if mfma else [13, 14, 15, 16, 17, 18]
+    for rb in levels:
+        gx, gy = F.grid_dims(rb, 0)
+        out = torch.zeros(gx * gy * 2, dtype=torch.int32, device="cuda")
+        (F.lambda_map_mfma if mfma else F.lambda_map)(rb, 0, out)
+        _sync()
+        got = out.cpu().numpy().view(np.uint32).reshape(gy, gx, 2)
+        for _ in range(3000):
+            wx, wy = int(rng.integers(gx)), int(rng.integers(gy))
+            assert tuple(got[wy, wx]) == oracle.lambda_(rb, wx, wy)
+        # bijection onto X & Y == 0 over the whole grid
+        flat = got.reshape(-1, 2).astype(np.int64)
+        assert np.all((flat[:, 0] & flat[:, 1]) == 0)
+        keys = flat[:, 1] * (1 << rb) + flat[:, 0]
+        assert np.unique(keys).size == gx * gy
+
+
+def test_lambda_map_rejects_bad_levels():
+    torch = torch_dev()
+    out = torch.zeros(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(F.FractalError):
+        F.lambda_map_mfma(17, 0, out)
+    with pytest.raises(F.FractalError):
+        F.lambda_map(3, 4, out)
+
+
+# ------------------------------------------------------------------ seed
+@pytest.mark.parametrize("rule", RULES)
+def test_seed_fill_matches_input_generator(rule):
+    for k in (0, 1, 2, 3, 4, 5, 9, 11):
+        buf = zeros_state(k, rule)
+        buf.fill_(7 if rule == fi.RULE_CA else 3.0)
+        F.seed_fill(k, rule, 1234 + k, buf)
+        _sync()
+        want = fi.window_values(k, rule, 1234 + k)
+        got = buf.cpu().numpy()
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), f"k={k}"
+
+
+# ------------------------------------------------------------------ steps
+def _run(map_, k, r, rule, b0, b1, steps):
+    alpha = ALPHA
+    if map_ == F.MAP_LAMBDA:
+        F.lambda_step(k, r, rule, alpha, b0, b1, steps)
+    elif map_ == F.MAP_BB:
+        F.bb_step(k, r, rule, alpha, b0, b1, steps)
+    else:
+        F.lambda_step_mfma(k, r, rule, alpha, b0, b1, steps)
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("map_", MAPS)
+def test_steps_small_levels_every_r(rule, map_):
+    """Every tile size on small gaskets, checked after each of 6 steps."""
+    for k in range(0, 8):
+        for r in range(0, min(k, 6) + 1):
+            init = fi.window_values(k, rule, 100 + k)
+            b0 = to_device(init)
+            b1 = zeros_state(k, rule)
+            ref = init if rule == fi.RULE_CA else init.astype(np.float64)
+            for t in range(1, 7):
+                # one step from the current buffer into the other
+                src, dst = (b0, b1) if (t - 1) % 2 == 0 else (b1, b0)
+                _run(map_, k, r, rule, src, dst, 1)
+                _sync()
+                ref = oracle_steps(k, rule, ref, 1)
+                assert_match(k, rule, dst.cpu().numpy(), ref,
+                             f"map={map_} k={k} r={r} t={t}")
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("r", [3, 4, 5, 6])
+def test_steps_k10_checkpoints(rule, r):
+    """Level 10 (n = 1024, 59049 cells): every step up to 32, then 100, for
+    lambda and bounding box, against the whole-array oracle."""
+    k = 10
+    init = fi.window_values(k, rule, 77)
+    bufs = {m: (to_device(init), zeros_state(k, rule)) for m in (F.MAP_LAMBDA, F.MAP_BB)}
+    ref = init if rule == fi.RULE_CA else init.astype(np.float64)
+    t = 0
+    for target in list(range(1, 33)) + [100]:
+        dt = target - t
+        ref = oracle_steps(k, rule, ref, dt)
+        for m, (b0, b1) in bufs.items():
+            _run(m, k, r, rule, b0, b1, dt)
+            _sync()
+            res = b0 if dt % 2 == 0 else b1
+            assert_match(k, rule, res.cpu().numpy(), ref, f"map={m} r={r} t={target}")
+            if dt % 2 == 1:
+                bufs[m] = (b1, b0)
+        t = target
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_lambda_bb_mfma_bit_identical_k12(rule):
+    torch = torch_dev()
+    k, steps = 12, 9
+    init = fi.window_values(k, rule, 5)
+    outs = []
+    for m in MAPS:
+        for (r, th, order) in [(3, 64, 0), (4, 64, 2), (5, 256, 1), (6, 256, 2), (5, 64, 0)]:
+            b0, b1 = to_device(init), zeros_state(k, rule)
+            F.step_tuned(m, k, rule, ALPHA, b0, b1, steps, r, th, order)
+            _sync()
+            outs.append(((m, r, th, order), b1.cpu().numpy()))
+    base = outs[0][1]
+    for cfg, o in outs[1:]:
+        assert np.array_equal(o.view(np.uint8), base.view(np.uint8)), f"{cfg} differs"
+    ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), steps)
+    assert_match(k, rule, base, ref, "k12")
+    del torch
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_off_gasket_stays_zero_and_steps0_noop(rule):
+    torch = torch_dev()
+    k = 11
+    init = fi.window_values(k, rule, 8)
+    b0, b1 = to_device(init), zeros_state(k, rule)
+    F.lambda_step(k, 4, rule, ALPHA, b0, b1, 0)
+    _sync()
+    assert torch.equal(b0.cpu(), torch.from_numpy(init))
+    F.lambda_step(k, 4, rule, ALPHA, b0, b1, 5)
+    _sync()
+    mem = torch.from_numpy(fi.member_mask(k)).cuda()
+    assert not bool((b1.to(torch.float32)[~mem] != 0).any())
+
+
+# ---------------------------------------------------------- full sizes
+def _full_size_check(k, rule, r, checkpoints, boxes, map_=F.MAP_LAMBDA, seed=1):
+    """Seed on the GPU, run to each checkpoint, and compare sampled boxes
+    with the oracle run on light-cone windows of the CPU-generated input."""
+    torch = torch_dev()
+    b0, b1 = zeros_state(k, rule), zeros_state(k, rule)
+    F.seed_fill(k, rule, seed, b0)
+    tmax = checkpoints[-1]
+    plans = []
+    for (cx, cy, w, h) in boxes:
+        x0, y0, ww, hh = window_plan(k, tmax, w, h, cx, cy)
+        win = fi.window_values(k, rule, seed, x0, y0, ww, hh)
+        state = win if rule == fi.RULE_CA else win.astype(np.float64)
+        plans.append([(cx, cy, w, h), (x0, y0, ww, hh), state])
+    t = 0
+    cur, other = b0, b1
+    for target in checkpoints:
+        dt = target - t
+        _run(map_, k, r, rule, cur, other, dt)
+        if dt % 2 == 1:
+            cur, other = other, cur
+        _sync()
+        for plan in plans:
+            (cx, cy, w, h), (x0, y0, ww, hh), state = plan
+            state = oracle_steps(k, rule, state, dt, x0, y0)
+            plan[2] = state
+            rs, cs = oracle.valid_interior(k, x0, y0, ww, hh, target)
+            ref = state[rs, cs]
+            gy0, gx0 = y0 + rs.start, x0 + cs.start
+            got = cur[gy0:gy0 + ref.shape[0], gx0:gx0 + ref.shape[1]].cpu().numpy()
+            assert_match(k, rule, got, ref, f"k={k} t={target} box=({cx},{cy})")
+        t = target
+    del torch
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_full_size_k14(rule):
+    """Level 14 (n = 16384, 4,782,969 cells) at the benchmark's launch
+    configuration: 1000 steps, sampled at the four corners (light cones
+    clipped by the array edge) and two interior boxes at early steps."""
+    k = 14
+    n = 1 << k
+    r = F.get_tuning(k, rule)[0]
+    _full_size_check(k, rule, r, list(range(1, 9)) + [32, 100, 1000],
+                     [(0, 0, 48, 48), (n - 48, 0, 48, 48), (0, n - 48, 48, 48)])
+    _full_size_check(k, rule, r, [1, 2, 3, 10, 40],
+                     [(5000, 3000, 64, 64), (8192 - 20, 8192 - 20, 40, 40)])
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_full_size_k16(rule):
+    """Level 16 (n = 65536, 43,046,721 cells, 17 GB float32 per buffer):
+    200 steps, sampled boxes at corners and inside."""
+    k = 16
+    n = 1 << k
+    r = F.get_tuning(k, rule)[0]
+    _full_size_check(k, rule, r, [1, 2, 50, 200],
+                     [(0, 0, 32, 32), (n - 32, 0, 32, 32), (0, n - 32, 32, 32),
+                      (40000, 20000, 32, 32), (32768 - 16, 32768 - 16, 32, 32)])
+
+
+def test_heat_error_metric_sane():
+    a = np.array([1.0, 2.0, 0.0], dtype=np.float32)
+    assert heat_err(a, a.astype(np.float64)) == 0.0

@@ -1,0 +1,121 @@
+"""CPU-only checks of the C ABI's host side: exported symbols, launch
+geometry, argument validation, tuning defaults, and the serving
+scheduler's allocator and admission queue (g++ with sanitizers)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import paper_2004_13475_amd as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fractal.h")
+FAKE0, FAKE1 = 0x10000000, 0x90000000  # never dereferenced: calls fail first
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fractal_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    declared = header_functions()
+    assert len(declared) >= 17
+    lib = F.load()
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, f"declared in fractal.h but not exported: {missing}"
+    assert sorted(F.EXPORTED) == declared
+
+
+def test_grid_dims_match_lemma2():
+    for k in range(0, 21):
+        for r in range(0, min(k, 6) + 1):
+            assert F.grid_dims(k, r) == oracle.grid_dims(k - r)
+    with pytest.raises(F.FractalError) as e:
+        F.grid_dims(4, 5)
+    assert e.value.code == F.E_INVAL
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((17, 4, 0, 0.2, FAKE0, FAKE1, 1), "level"),
+    ((10, 7, 0, 0.2, FAKE0, FAKE1, 1), "tile level"),
+    ((16, 0, 0, 0.2, FAKE0, FAKE1, 1), "block level"),
+    ((10, 4, 2, 0.2, FAKE0, FAKE1, 1), "rule"),
+    ((10, 4, 1, 0.3, FAKE0, FAKE1, 1), "alpha"),
+    ((10, 4, 1, float("nan"), FAKE0, FAKE1, 1), "alpha"),
+    ((10, 4, 1, 0.0, FAKE0, FAKE1, 1), "alpha"),
+    ((10, 4, 0, 0.2, FAKE0, FAKE1, -1), "negative"),
+    ((10, 4, 0, 0.2, 0, FAKE1, 1), "null"),
+    ((10, 4, 0, 0.2, FAKE0, FAKE0 + 1024, 1), "overlap"),
+    ((10, 4, 0, 0.2, FAKE0 + 4, FAKE1, 1), "aligned"),
+])
+def test_step_validation(args, frag):
+    for fn in (F.lambda_step, F.bb_step, F.lambda_step_mfma):
+        with pytest.raises(F.FractalError) as e:
+            fn(*args, stream=0)
+        assert e.value.code == F.E_INVAL
+        assert frag in str(e.value)
+
+
+def test_steps_zero_is_noop_without_device():
+    # a valid call with zero steps returns before touching the GPU
+    F.lambda_step(10, 4, 0, 0.2, FAKE0, FAKE1, 0, stream=0)
+    F.bb_step(10, 4, 1, 0.2, FAKE0, FAKE1, 0, stream=0)
+
+
+def test_mfma_level_limit():
+    with pytest.raises(F.FractalError):
+        F.lambda_map_mfma(20, 3, FAKE0, stream=0)
+    with pytest.raises(F.FractalError):
+        F.lambda_map(40, 3, FAKE0, stream=0)
+
+
+def test_tuning_defaults_and_validation():
+    for k in range(0, 17):
+        for rule in (0, 1):
+            r, th, order = F.get_tuning(k, rule)
+            assert 0 <= r <= min(k, 6) and k - r <= 15
+            assert th in (64, 256) and order in (0, 1, 2)
+    with pytest.raises(F.FractalError):
+        F.set_tuning(10, 0, 7, 64, 0)
+    with pytest.raises(F.FractalError):
+        F.set_tuning(10, 0, 4, 128, 0)
+    with pytest.raises(F.FractalError):
+        F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 1, 4, 64, 9, stream=0)
+
+
+def test_batch_validation():
+    with pytest.raises(F.FractalError):
+        F.batch_step([(17, 0, 5, 0.2, FAKE0, FAKE1)], stream=0)
+    with pytest.raises(F.FractalError):  # two instances share a buffer
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1),
+                      (10, 0, 5, 0.2, FAKE1, FAKE1 + (1 << 22))], stream=0)
+    F.batch_step([], stream=0)
+    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], stream=0)  # no steps: no-op
+
+
+def test_serving_scheduler_unit(tmp_path):
+    exe = tmp_path / "serve_sched_test"
+    src = os.path.join(ROOT, "tests", "serve_sched_test.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-fno-omit-frame-pointer", src, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert "serve_sched ok" in out.stdout
+
+
+def test_oracle_and_product_share_nothing():
+    """The oracle never imports the GPU package and vice versa."""
+    prod = os.path.join(ROOT, "paper_2004_13475_amd")
+    for dirpath, _, files in os.walk(prod):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in txt.lower(), f"{f} mentions the oracle"
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2004_13475_amd" not in txt and "csrc" not in txt
