@@ -1,20 +1,32 @@
 """Benchmark: lambda(omega)-mapped gasket steps on one MI355X.
 
-Default workload: a level-14 Sierpinski gasket (n = 16384, 4,782,969 cells);
-one benchmark step = one uint8 B3/S23 automaton step plus one float32 heat
-step (alpha = 0.2), both through the lambda kernels at their tuned tile size.
-`value` = gasket cells updated per second over the timed K steps (both
-rules), with the state resident in HBM.  The line also carries the roofline
-of the dominant kernel, the bounding-box comparison and the CPU oracle's rate
-on a bounded sample.
+Default workload (the one `value` is quoted on): a level-14 Sierpinski
+gasket (n = 16384, 4,782,969 cells); one benchmark step = one uint8 B3/S23
+automaton step plus one float32 heat step (alpha = 0.2), both through the
+lambda kernels at their autotuned launch.  `value` = gasket cells updated per
+second over the timed K steps (both rules), state resident in HBM, timed with
+HIP events on the stream the kernels run on.
+
+Also on the same JSON line:
+  roofline      dominant kernel's algorithmic HBM GB/s vs the 8 TB/s peak
+  bb            bounding-box steps at the same tile size and at BB's best
+  k16           level-16 gasket (17 GB float32 per buffer): per-rule rates
+                and roofline fractions
+  batch         256 gaskets of levels 8..14, 500 steps, one graph launch vs
+                256 plain lambda_step calls
+  serve         (with --serve SECONDS) Poisson request stream, p50/p99
+  cpu_baseline  the CPU oracle on a bounded sample of the default workload
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
+                    [--no-cpu] [--no-bb] [--no-k16] [--no-batch]
+                    [--serve SECONDS] [--copy-calibration]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -32,6 +44,7 @@ ALPHA = 0.2
 #   float32: 8 * (4/3)^4 = 25.284 B per member cell
 BYTES_PER_CELL = {0: 2.0 * (4.0 / 3.0) ** 6, 1: 8.0 * (4.0 / 3.0) ** 4}
 WORKLOADS = {"k14": 14, "k16": 16}
+RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernels.hip"]
 
 
@@ -46,7 +59,7 @@ def kernel_hash() -> str:
 def read_traffic(workload: str, rule_name: str):
     """Per-launch HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) from the
     committed counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"step_{rule_name}_{workload}_counters.md")
+    path = os.path.join(ROOT, "profiles", f"lambda_step_{rule_name}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -57,6 +70,236 @@ def read_traffic(workload: str, rule_name: str):
     return float(m_bytes.group(1))
 
 
+class Gasket:
+    """A pair of state buffers per rule for one level, plus timing helpers."""
+
+    def __init__(self, F, torch, k, seed=1):
+        self.F, self.torch, self.k = F, torch, k
+        self.n = 1 << k
+        self.cells = 3 ** k
+        self.alpha = float(__import__("numpy").float32(ALPHA))
+        self.stream = torch.cuda.current_stream()
+        self.bufs = {}
+        for rule, dt in ((0, torch.uint8), (1, torch.float32)):
+            b0 = torch.empty((self.n, self.n), dtype=dt, device="cuda")
+            b1 = torch.zeros((self.n, self.n), dtype=dt, device="cuda")
+            F.seed_fill(k, rule, seed, b0)
+            self.bufs[rule] = [b0, b1]
+        self.tunings = {}
+        torch.cuda.synchronize()
+
+    def reseed(self, rule, seed=1):
+        self.F.seed_fill(self.k, rule, seed, self.bufs[rule][0])
+        self.bufs[rule][1].zero_()
+
+    def autotune(self):
+        for rule in (0, 1):
+            self.tunings[rule] = self.F.autotune(self.k, rule, self.alpha, *self.bufs[rule])
+            self.reseed(rule)
+        self.torch.cuda.synchronize()
+
+    def run(self, rule, steps, map_=None, tuning=None):
+        F = self.F
+        t = tuning or self.tunings[rule]
+        F.step_tuned(F.MAP_LAMBDA if map_ is None else map_, self.k, rule, self.alpha,
+                     self.bufs[rule][0], self.bufs[rule][1], steps, t[0], t[1], t[2],
+                     t[3] if len(t) > 3 else 0)
+        if steps % 2:
+            self.bufs[rule].reverse()
+
+    def time(self, rule, steps, map_=None, tuning=None):
+        """Seconds per launch, HIP events around `steps` back-to-back launches."""
+        torch = self.torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        self.run(rule, steps, map_, tuning)
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / steps
+
+    def free(self):
+        self.bufs.clear()
+        self.torch.cuda.empty_cache()
+
+
+def roofline(rule, cells, sec_per_launch, traffic=None, kernel=""):
+    alg = BYTES_PER_CELL[rule] * cells
+    achieved = alg / sec_per_launch / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "alg_bytes_per_launch": alg, "avg_launch_us": sec_per_launch * 1e6}
+
+
+def bb_leg(g, per_launch, nsteps):
+    F = g.F
+    out = {}
+    for rule in (0, 1):
+        res = {}
+        for r in range(max(2, g.k - 15), 7):
+            tb = (r, 256 if (r >= 5 and rule == 1) or r >= 6 else 64, F.ORDER_NATURAL)
+            g.run(rule, 2, F.MAP_BB, tb)
+            res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
+        lam = per_launch[rule]
+        best = min(res, key=res.get)
+        same = res.get(g.tunings[rule][0])
+        out[RULE_NAME[rule]] = {
+            "lambda_us": lam * 1e6, "lambda_r": g.tunings[rule][0],
+            "bb_us_same_r": None if same is None else same * 1e6,
+            "bb_best_r": best, "bb_us_best": res[best] * 1e6,
+            "speedup_same_r": None if same is None else same / lam,
+            "speedup_best": res[best] / lam,
+            "bb_us_by_r": {str(r): v * 1e6 for r, v in res.items()},
+        }
+    return out
+
+
+def k16_leg(F, torch, steps):
+    g = Gasket(F, torch, 16)
+    g.autotune()
+    out = {"k": 16, "cells": g.cells, "steps": steps}
+    for rule in (0, 1):
+        g.run(rule, 4)
+        sec = g.time(rule, steps)
+        rf = roofline(rule, g.cells, sec, read_traffic("k16", RULE_NAME[rule]),
+                      f"lambda_step_{RULE_NAME[rule]}")
+        out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]),
+                                "cells_per_s": g.cells / sec, "roofline": rf}
+    # bounding box at lambda's tile size and at rho = 32 (the paper's best)
+    for rule in (0, 1):
+        r = g.tunings[rule][0]
+        for rr in sorted({r, 5}):
+            tb = (rr, 256 if rr >= 5 else 64, F.ORDER_NATURAL)
+            g.run(rule, 2, F.MAP_BB, tb)
+            sec = g.time(rule, max(4, steps // 4), F.MAP_BB, tb)
+            out[RULE_NAME[rule]][f"bb_r{rr}_us"] = sec * 1e6
+        out[RULE_NAME[rule]]["lambda_us"] = 1e6 * g.cells / out[RULE_NAME[rule]]["cells_per_s"]
+    g.free()
+    return out
+
+
+def batch_leg(F, torch, count=256, steps=500, seed=2004):
+    import fractal_inputs as fi
+    pairs = fi.batch_instances(count, seed, 8, 14)
+    alpha = float(__import__("numpy").float32(ALPHA))
+    bufs = []
+    for j, (k, rule) in enumerate(pairs):
+        dt = torch.uint8 if rule == 0 else torch.float32
+        n = 1 << k
+        b0 = torch.empty((n, n), dtype=dt, device="cuda")
+        b1 = torch.zeros((n, n), dtype=dt, device="cuda")
+        bufs.append((k, rule, b0, b1))
+
+    def reseed():
+        for j, (k, rule, b0, b1) in enumerate(bufs):
+            F.seed_fill(k, rule, 7000 + j, b0)
+            b1.zero_()
+        torch.cuda.synchronize()
+
+    cells = sum(3 ** k for (k, _, _, _) in bufs) * steps
+    stream = torch.cuda.current_stream()
+    inst = [(k, rule, steps, alpha, b0, b1) for (k, rule, b0, b1) in bufs]
+
+    def sums():
+        return [int((b0 if steps % 2 == 0 else b1).view(torch.uint8).to(torch.int64).sum())
+                for (k, rule, b0, b1) in bufs]
+
+    def timed(fn):
+        reseed()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, time.perf_counter() - t0, sums()
+
+    # warm the graph path once on a short run
+    reseed()
+    F.batch_step([(k, rule, 2, alpha, b0, b1) for (k, rule, b0, b1) in bufs])
+    modes = {"per_tile": None, "persistent": (F.R_AUTO, 64, 2, F.FLAG_PERSISTENT)}
+    res = {}
+    for name, tun in modes.items():
+        res[name] = timed(lambda: F.batch_step(inst, tuning=tun))
+
+    def plain():
+        for (k, rule, b0, b1) in bufs:
+            F.lambda_step(k, F.R_AUTO, rule, alpha, b0, b1, steps)
+
+    tp, wall_plain, sums_plain = timed(plain)
+    out = {"instances": count, "steps": steps, "cell_updates": cells,
+           "state_GB": sum(2 * (1 << (2 * k)) * (1 if r == 0 else 4) for (k, r, _, _) in bufs) / 1e9,
+           "plain_s": tp, "plain_wall_s": wall_plain, "plain_cells_per_s": cells / tp}
+    for name, (tb, wall, sm) in res.items():
+        out[name] = {"s": tb, "wall_s": wall, "cells_per_s": cells / tb,
+                     "speedup_vs_plain": tp / tb, "same_result": sm == sums_plain}
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nreq = int(rate * seconds)
+    gaps = rng.exponential(1.0 / rate, size=nreq)
+    arrivals = np.cumsum(gaps)
+    ks = rng.integers(9, 16, size=nreq)
+    steps = rng.integers(10, 1001, size=nreq)
+    rules = rng.integers(0, 2, size=nreq)
+    nbytes = int(arena_gb * 1e9) // 256 * 256
+    arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    cells = int(sum(3 ** int(k) * int(s) for k, s in zip(ks, steps)))
+    alpha = float(np.float32(ALPHA))
+    tickets = []
+    with F.Server(arena, nbytes, max_slots=256, steps_per_iter=8) as srv:
+        t0 = F.now()
+        for i in range(nreq):
+            target = t0 + float(arrivals[i])
+            while F.now() < target:
+                time.sleep(min(0.0005, max(0.0, target - F.now())))
+            tickets.append(srv.submit(int(ks[i]), int(rules[i]), int(steps[i]), alpha,
+                                      seed=10000 + i, t_arrival=target))
+        res = {}
+        while len(res) < nreq:
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.002)
+        t_end = F.now()
+    lat = np.array([res[t][3] - res[t][1] for t in tickets])
+    ok = all(res[t][0] == 0 for t in tickets)
+    out = {"requests": nreq, "rate": rate, "arrival_s": float(arrivals[-1]),
+           "drain_s": t_end - t0, "cell_updates": cells,
+           "cells_per_s": cells / (t_end - t0), "p50_s": float(np.percentile(lat, 50)),
+           "p99_s": float(np.percentile(lat, 99)), "all_ok": ok}
+    # the same trace solved one request at a time with plain launches
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e0.record(stream)
+    for i in range(nreq):
+        k, rule = int(ks[i]), int(rules[i])
+        n = 1 << k
+        one = n * n * (1 if rule == 0 else 4)
+        b0 = arena[: one]
+        b1 = arena[one: 2 * one]
+        F.seed_fill(k, rule, 10000 + i, b0)
+        b1.zero_()
+        F.lambda_step(k, F.R_AUTO, rule, alpha, b0, b1, int(steps[i]))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq = e0.elapsed_time(e1) * 1e-3
+    out.update({"sequential_s": seq, "sequential_wall_s": time.perf_counter() - t1,
+                "sequential_cells_per_s": cells / seq})
+    del arena
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,112 +308,74 @@ def main() -> int:
     ap.add_argument("--workload", default="k14", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-bb", action="store_true", help="skip the bounding-box leg")
+    ap.add_argument("--no-k16", action="store_true", help="skip the level-16 leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-gasket batch leg")
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="seconds of Poisson arrivals for the serving leg (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 4 GiB with a plain device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2004_13475_amd as F
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    k = WORKLOADS[args.workload]
-    n = 1 << k
-    cells = 3 ** k
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 32, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+
     K, W = args.steps, args.warmup
-    alpha = float(np.float32(ALPHA))
-
-    bufs = {}
-    for rule, dt in ((0, torch.uint8), (1, torch.float32)):
-        b0 = torch.empty((n, n), dtype=dt, device=dev)
-        b1 = torch.zeros((n, n), dtype=dt, device=dev)
-        F.seed_fill(k, rule, 1, b0)
-        bufs[rule] = [b0, b1]
+    g = Gasket(F, torch, WORKLOADS[args.workload])
+    g.autotune()
+    g.run(0, W)
+    g.run(1, W)
     torch.cuda.synchronize()
-
-    # autotune the lambda launch for each rule (records the cached tuning)
-    tunings = {}
-    for rule in (0, 1):
-        tunings[rule] = F.autotune(k, rule, alpha, bufs[rule][0], bufs[rule][1])
-        F.seed_fill(k, rule, 1, bufs[rule][0])
-        bufs[rule][1].zero_()
-    torch.cuda.synchronize()
-
-    def run(rule, steps, map_=F.MAP_LAMBDA, tuning=None):
-        b0, b1 = bufs[rule]
-        t = tuning or tunings[rule]
-        F.step_tuned(map_, k, rule, alpha, b0, b1, steps, t[0], t[1], t[2])
-        if steps % 2:
-            bufs[rule].reverse()
-
-    # warm-up
-    run(0, W)
-    run(1, W)
-    torch.cuda.synchronize()
-
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record(stream)
-    run(0, K)
-    ev[1].record(stream)
-    run(1, K)
-    ev[2].record(stream)
+    ev[0].record(g.stream)
+    g.run(0, K)
+    ev[1].record(g.stream)
+    g.run(1, K)
+    ev[2].record(g.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_ca = ev[0].elapsed_time(ev[1])
-    ms_heat = ev[1].elapsed_time(ev[2])
+    ms_ca, ms_heat = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     total_ms = ms_ca + ms_heat
-    value = 2.0 * cells * K / (total_ms / 1e3)
-
+    value = 2.0 * g.cells * K / (total_ms / 1e3)
     per_launch = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}
     dom = 1 if per_launch[1] >= per_launch[0] else 0
-    rule_name = {0: "ca", 1: "heat"}
-    alg_bytes = {r: BYTES_PER_CELL[r] * cells for r in (0, 1)}
-    achieved = alg_bytes[dom] / per_launch[dom] / 1e9
-    traffic = read_traffic(args.workload, rule_name[dom])
+    rf = roofline(dom, g.cells, per_launch[dom], read_traffic(args.workload, RULE_NAME[dom]),
+                  f"lambda_step_{RULE_NAME[dom]}")
 
-    # bounding box: same tile size, and its own best tile size
-    bb = {}
-    if not args.no_bb:
-        nbb = max(10, min(K, 200))
-        for rule in (0, 1):
-            res = {}
-            for r in range(max(2, k - 15), 7):
-                tb = (r, 256 if (r >= 5 and rule == 1) or r >= 6 else 64, 0)
-                run(rule, 2, F.MAP_BB, tb)
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                run(rule, nbb, F.MAP_BB, tb)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                res[r] = e0.elapsed_time(e1) / nbb
-            lam_ms = per_launch[rule] * 1e3
-            best_r = min(res, key=res.get)
-            bb[rule_name[rule]] = {
-                "lambda_ms_per_step": lam_ms, "lambda_r": tunings[rule][0],
-                "bb_ms_per_step_same_r": res.get(tunings[rule][0]),
-                "bb_best_r": best_r, "bb_ms_per_step_best": res[best_r],
-                "speedup_same_r": res.get(tunings[rule][0], float("nan")) / lam_ms,
-                "speedup_best": res[best_r] / lam_ms,
-            }
+    bb = None if args.no_bb else bb_leg(g, per_launch, max(10, min(K, 200)))
+    k, cells, tunings = g.k, g.cells, dict(g.tunings)
+    g.free()
+    k16 = None if (args.no_k16 or k == 16) else k16_leg(F, torch, 50)
+    batch = None if args.no_batch else batch_leg(F, torch)
+    serve = serve_leg(F, torch, args.serve) if args.serve > 0 else None
 
     cpu = None
     if not args.no_cpu:
+        import numpy as np
+
         import fractal_inputs as fi
         import oracle
         ck = 14
         states = {0: fi.full_state(ck, 0, 1), 1: fi.full_state(ck, 1, 1, dtype=np.float64)}
-        nsteps = {0: 4, 1: 2}
+        nsteps = {0: 40, 1: 10}
         tc = time.perf_counter()
         oracle.ca_run(ck, states[0], nsteps[0])
-        oracle.heat_run(ck, states[1], alpha, nsteps[1])
+        oracle.heat_run(ck, states[1], g.alpha, nsteps[1])
         dtc = time.perf_counter() - tc
         cpu = {"value": 3 ** ck * (nsteps[0] + nsteps[1]) / dtc, "unit": "cells/s",
                "cores": oracle.threads(), "kind": "oracle",
@@ -183,23 +388,19 @@ def main() -> int:
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": total_ms / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8+f32", "data": "synthetic",
-        "config": {"workload": f"sierpinski-k{k}-lambda-ca-u8+heat-f32",
-                   "k": k, "n": n, "cells": cells,
-                   "tuning_ca": list(tunings[0]), "tuning_heat": list(tunings[1]),
-                   "wall_s": wall},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"lambda_step_{rule_name[dom]}",
-                     "alg_bytes_per_launch": alg_bytes[dom],
-                     "avg_launch_us": per_launch[dom] * 1e6},
-        "per_rule": {rule_name[r]: {"ms_per_step": per_launch[r] * 1e3,
+        "config": {"workload": f"sierpinski-k{k}-lambda-ca-u8+heat-f32", "k": k,
+                   "n": 1 << k, "cells": cells, "tuning_ca": list(tunings[0]),
+                   "tuning_heat": list(tunings[1]), "wall_s": wall},
+        "roofline": rf,
+        "per_rule": {RULE_NAME[r]: {"us_per_step": per_launch[r] * 1e6,
                                     "cells_per_s": cells / per_launch[r],
-                                    "alg_GBs": alg_bytes[r] / per_launch[r] / 1e9}
+                                    "alg_GBs": BYTES_PER_CELL[r] * cells / per_launch[r] / 1e9}
                      for r in (0, 1)},
-        "bb": bb,
+        "bb": bb, "k16": k16, "batch": batch, "serve": serve,
         "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_hash(),
     }
-    print(json.dumps(line))
+    print(json.dumps(line, default=lambda o: None if isinstance(o, float) and math.isnan(o) else o))
     return 0
 
 

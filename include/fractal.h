@@ -18,7 +18,9 @@
  * heat (FRACTAL_RULE_HEAT).  The two buffers of a step call must not overlap,
  * and BOTH must hold 0 in every off-gasket cell on entry: the lambda kernels
  * never visit empty tiles, and every kernel writes only the 16-byte chunks
- * that contain a member (off-gasket cells inside them are written as 0).
+ * that contain a member, or with FRACTAL_FLAG_SEGMENTS the 16-byte chunks of
+ * 64-byte row segments that contain a member (off-gasket cells inside them
+ * are written as 0).
  * After `steps` steps the state is in buf[steps & 1] (buf0 when steps is even);
  * steps == 0 does nothing.
  *
@@ -66,13 +68,21 @@ extern "C" {
 
 #define FRACTAL_R_AUTO (-1) /* use the tuned (or default) tile size */
 
-/* Launch parameters of a step kernel. */
+/* flags of a step launch (bitwise or) */
+#define FRACTAL_FLAG_SEGMENTS 1 /* move whole 64-byte row segments that hold a
+                                   member (their member-free chunks are read
+                                   and written as 0) instead of 16-byte chunks */
+#define FRACTAL_FLAG_NT_STORE 2 /* non-temporal hint on output stores */
+#define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
+                                     contiguous ranges of the tile list, instead
+                                     of one workgroup per tile */
+
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..6 (rho <= 64)            */
     int threads; /* threads per workgroup: 64 or 256                        */
     int order;   /* FRACTAL_ORDER_*                                         */
-    int reserved;
-} fractal_tuning;
+    int flags;   /* FRACTAL_FLAG_*                                          */
+} fractal_tuning; /* launch parameters of a step kernel */
 
 /* Lemma 2 / Theorem 1: dimensions of the compact launch grid for a level-k
  * gasket cut into 2^r tiles: gx = 3^ceil(r_b/2), gy = 3^floor(r_b/2),
@@ -130,7 +140,7 @@ int fractal_step_tuned(int map, int k, int rule, float alpha, void *d_buf0,
                        void *d_buf1, int steps, const fractal_tuning *tuning,
                        void *stream);
 
-/* Autotuner: times every supported (r, threads, order) for this level and
+/* Autotuner: times every supported (r, threads, order, flags) for this level and
  * rule on the given buffers (a few steps each, synchronising `stream`) and
  * records the fastest lambda launch in a per-process cache keyed by
  * (device, k, rule).  The buffers must satisfy the step contract; they end up
@@ -156,11 +166,17 @@ typedef struct fractal_instance {
 } fractal_instance;
 
 /* Advance many gaskets of uneven levels together.  Each step is one launch
- * of a persistent kernel whose workgroups walk a device table of tiles
- * (per-instance prefix offsets of 3^(k_i - r_i), lambda per instance); the
- * max_i steps_i launches are captured once into a HIP graph and the graph is
- * launched on `stream`.  Instances with fewer steps drop out of later
- * launches.  `tuning` may be NULL (per-level defaults / cached tuning).
+ * over the combined tile list of all instances: a tile id is turned into
+ * (instance, local omega) with a device table of per-instance prefix offsets
+ * of 3^(k_i - r_i), then into a tile by that instance's lambda.  By default
+ * every tile gets a workgroup; with FRACTAL_FLAG_PERSISTENT in tuning->flags
+ * a persistent grid (CUs x 32 workgroups) walks contiguous ranges of the
+ * list.  The max_i steps_i launches are captured once into a HIP graph and
+ * the graph is launched on `stream`.  Instances with fewer steps drop out of
+ * later launches.  `tuning` may be NULL (per-level defaults / cached tuning);
+ * otherwise tuning->r applies to every instance (clamped per level), or
+ * FRACTAL_R_AUTO keeps the per-level defaults, and only
+ * FRACTAL_FLAG_PERSISTENT is accepted in tuning->flags.
  * Results are bit-identical to one fractal_lambda_step call per instance.
  * The call allocates a device table (freed when the graph has run) and
  * returns after enqueuing; it synchronises nothing else.  count <= 65536. */

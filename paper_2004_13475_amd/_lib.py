@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfractal.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_AGAIN = 0, 1, 2, 3, 4
 RULE_CA, RULE_HEAT = 0, 1
 ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
+FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT = 1, 2, 4
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 
@@ -38,10 +39,10 @@ class FractalError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int), ("threads", ctypes.c_int),
-                ("order", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("order", ctypes.c_int), ("flags", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.r, self.threads, self.order)
+        return (self.r, self.threads, self.order, self.flags)
 
 
 class Instance(ctypes.Structure):
@@ -171,8 +172,9 @@ def lambda_step_mfma(k, r, rule, alpha, buf0, buf1, steps, stream=None):
                                                   _ptr(buf1), steps, _stream(stream)))
 
 
-def step_tuned(map_, k, rule, alpha, buf0, buf1, steps, r, threads, order, stream=None):
-    t = Tuning(r, threads, order, 0)
+def step_tuned(map_, k, rule, alpha, buf0, buf1, steps, r, threads, order, flags=0,
+               stream=None):
+    t = Tuning(r, threads, order, flags)
     return _check(load().fractal_step_tuned(map_, k, rule, alpha, _ptr(buf0), _ptr(buf1),
                                             steps, ctypes.byref(t), _stream(stream)))
 
@@ -190,8 +192,8 @@ def get_tuning(k, rule):
     return t.as_tuple()
 
 
-def set_tuning(k, rule, r, threads, order):
-    t = Tuning(r, threads, order, 0)
+def set_tuning(k, rule, r, threads, order, flags=0):
+    t = Tuning(r, threads, order, flags)
     return _check(load().fractal_set_tuning(k, rule, ctypes.byref(t)))
 
 
@@ -202,7 +204,7 @@ def batch_step(instances, tuning=None, stream=None):
         arr[j] = Instance(k, rule, steps, alpha, _ptr(b0), _ptr(b1))
     tp = None
     if tuning is not None:
-        tp = ctypes.byref(Tuning(*tuning, 0) if len(tuning) == 3 else Tuning(*tuning))
+        tp = ctypes.byref(Tuning(*tuning) if len(tuning) == 4 else Tuning(*tuning, 0))
     return _check(load().fractal_batch_step(arr, len(instances), tp, _stream(stream)))
 
 

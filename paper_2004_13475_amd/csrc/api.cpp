@@ -87,7 +87,7 @@ fractal_tuning tuning_for_r(int map, int k, int rule, int r)
     t.r = r;
     t.threads = default_threads(rule, r);
     t.order = map == MAP_BB ? FRACTAL_ORDER_NATURAL : FRACTAL_ORDER_CURVE_XCD;
-    t.reserved = 0;
+    t.flags = 0;
     return t;
 }
 
@@ -138,6 +138,8 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "threads=%d must be 64 or 256", t->threads);
     if (t->order < FRACTAL_ORDER_NATURAL || t->order > FRACTAL_ORDER_CURVE_XCD)
         return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
+    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE))
+        return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
     (void)rule;
     return FRACTAL_OK;
 }
@@ -302,10 +304,11 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         for (int th : {64, 256}) {
             if (th == 256 && default_threads(rule, r) == 64 && r < 5)
                 continue;
-            for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE_XCD}) {
-                fractal_tuning t{r, th, order, 0};
-                cands.push_back(t);
-            }
+            for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE_XCD})
+                for (int fl = 0; fl < 4; ++fl) {
+                    fractal_tuning t{r, th, order, fl};
+                    cands.push_back(t);
+                }
         }
     }
     for (const fractal_tuning &t : cands) {

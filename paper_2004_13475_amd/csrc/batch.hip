@@ -38,10 +38,51 @@ __device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, ui
     tile_step<RULE, R, kBatchThreads>(lds, p, t.x << R, t.y << R);
 }
 
-// Workgroup b handles the contiguous tile ids [b*per, (b+1)*per) in order, so
-// tiles that are neighbours in the gasket's self-similar order stay on one
-// die and share its L2.  Entries [0, count) are the active instances, sorted
-// by tile_begin; `total` is the end of the last one's range.
+// Find the instance owning tile id w: the last of entries [0, count) whose
+// range starts at or before w (entries are sorted by tile_begin).
+__device__ __forceinline__ int find_instance(const BatchEntry *__restrict__ table, int count,
+                                             uint64_t w)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].tile_begin <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void batch_dispatch(uint8_t *lds, const BatchEntry &e, uint32_t L,
+                                               int local_step)
+{
+    if (e.rule == RULE_CA) {
+        switch (e.r) {
+        case 0: batch_tile<RULE_CA, 0>(lds, e, L, local_step); break;
+        case 1: batch_tile<RULE_CA, 1>(lds, e, L, local_step); break;
+        case 2: batch_tile<RULE_CA, 2>(lds, e, L, local_step); break;
+        case 3: batch_tile<RULE_CA, 3>(lds, e, L, local_step); break;
+        case 4: batch_tile<RULE_CA, 4>(lds, e, L, local_step); break;
+        case 5: batch_tile<RULE_CA, 5>(lds, e, L, local_step); break;
+        default: batch_tile<RULE_CA, 6>(lds, e, L, local_step); break;
+        }
+    } else {
+        switch (e.r) {
+        case 0: batch_tile<RULE_HEAT, 0>(lds, e, L, local_step); break;
+        case 1: batch_tile<RULE_HEAT, 1>(lds, e, L, local_step); break;
+        case 2: batch_tile<RULE_HEAT, 2>(lds, e, L, local_step); break;
+        case 3: batch_tile<RULE_HEAT, 3>(lds, e, L, local_step); break;
+        case 4: batch_tile<RULE_HEAT, 4>(lds, e, L, local_step); break;
+        default: batch_tile<RULE_HEAT, 5>(lds, e, L, local_step); break;
+        }
+    }
+}
+
+// Persistent form: workgroup b handles the contiguous tile ids
+// [b*per, (b+1)*per) in order, so tiles that are neighbours in the gasket's
+// self-similar order stay on one die and share its L2.  Entries [0, count)
+// are the active instances; `total` is the end of the last one's range.
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(
     const BatchEntry *__restrict__ table, int count, uint64_t total, int local_step)
 {
@@ -51,15 +92,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(
     const uint64_t w1 = w0 + per < total ? w0 + per : total;
     if (w0 >= w1)
         return;
-    int lo = 0, hi = count - 1; // last entry whose range starts at or before w0
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (table[mid].tile_begin <= w0)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    int j = lo;
+    int j = find_instance(table, count, w0);
     uint64_t next = j + 1 < count ? table[j + 1].tile_begin : ~0ull;
     for (uint64_t w = w0; w < w1; ++w) {
         while (w >= next) {
@@ -67,29 +100,20 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(
             next = j + 1 < count ? table[j + 1].tile_begin : ~0ull;
         }
         const BatchEntry e = table[j];
-        const uint32_t L = (uint32_t)(w - e.tile_begin);
         __syncthreads(); // previous tile's LDS reads are done
-        if (e.rule == RULE_CA) {
-            switch (e.r) {
-            case 0: batch_tile<RULE_CA, 0>(lds, e, L, local_step); break;
-            case 1: batch_tile<RULE_CA, 1>(lds, e, L, local_step); break;
-            case 2: batch_tile<RULE_CA, 2>(lds, e, L, local_step); break;
-            case 3: batch_tile<RULE_CA, 3>(lds, e, L, local_step); break;
-            case 4: batch_tile<RULE_CA, 4>(lds, e, L, local_step); break;
-            case 5: batch_tile<RULE_CA, 5>(lds, e, L, local_step); break;
-            default: batch_tile<RULE_CA, 6>(lds, e, L, local_step); break;
-            }
-        } else {
-            switch (e.r) {
-            case 0: batch_tile<RULE_HEAT, 0>(lds, e, L, local_step); break;
-            case 1: batch_tile<RULE_HEAT, 1>(lds, e, L, local_step); break;
-            case 2: batch_tile<RULE_HEAT, 2>(lds, e, L, local_step); break;
-            case 3: batch_tile<RULE_HEAT, 3>(lds, e, L, local_step); break;
-            case 4: batch_tile<RULE_HEAT, 4>(lds, e, L, local_step); break;
-            default: batch_tile<RULE_HEAT, 5>(lds, e, L, local_step); break;
-            }
-        }
+        batch_dispatch(lds, e, (uint32_t)(w - e.tile_begin), local_step);
     }
+}
+
+// One workgroup per tile of the combined work list (ids laid out per die in
+// contiguous ranges, as the lambda step kernels do).
+__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(
+    const BatchEntry *__restrict__ table, int count, uint32_t total, int local_step)
+{
+    __shared__ __align__(16) uint8_t lds[kBatchLds];
+    const uint32_t w = xcd_chunk(blockIdx.x, total);
+    const BatchEntry e = table[find_instance(table, count, w)];
+    batch_dispatch(lds, e, (uint32_t)(w - e.tile_begin), local_step);
 }
 
 int batch_supported_r(int rule, int r)
@@ -127,6 +151,13 @@ int launch_batch(const BatchEntry *d_table, int count, uint64_t total_tiles, int
 {
     if (count <= 0 || total_tiles == 0)
         return FRACTAL_OK;
+    if (grid == 0 && total_tiles < 0x7FFFFFFFull) {
+        hipLaunchKernelGGL(batch_tile_kernel, dim3((unsigned)total_tiles), dim3(kBatchThreads), 0,
+                           s, d_table, count, (uint32_t)total_tiles, local_step);
+        return hip_error(hipGetLastError(), "batch kernel launch");
+    }
+    if (grid == 0)
+        grid = batch_grid_size();
     const uint64_t g = total_tiles < (uint64_t)grid ? total_tiles : (uint64_t)grid;
     hipLaunchKernelGGL(batch_kernel, dim3((unsigned)g), dim3(kBatchThreads), 0, s, d_table,
                        count, total_tiles, local_step);
@@ -173,14 +204,18 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         return FRACTAL_OK;
     if (!inst)
         return set_error(FRACTAL_E_INVAL, "null instance array");
-    if (tuning && (tuning->r < 0 || tuning->r > kMaxR))
+    if (tuning && tuning->r != FRACTAL_R_AUTO && (tuning->r < 0 || tuning->r > kMaxR))
         return set_error(FRACTAL_E_INVAL, "tuning r=%d outside [0, %d]", tuning->r, kMaxR);
+    if (tuning && (tuning->flags & ~FRACTAL_FLAG_PERSISTENT))
+        return set_error(FRACTAL_E_INVAL, "batch tuning flags 0x%x (only PERSISTENT)",
+                         tuning->flags);
     // validate every instance, pick its tile level
     std::vector<int> rs(count);
     int max_steps = 0;
     for (int i = 0; i < count; ++i) {
         const fractal_instance &q = inst[i];
-        int r = tuning ? tuning->r : batch_default_r(q.k, q.rule);
+        int r = (tuning && tuning->r != FRACTAL_R_AUTO) ? tuning->r
+                                                        : batch_default_r(q.k < 0 ? 0 : q.k, q.rule);
         if (q.k >= 0 && r > q.k)
             r = q.k;
         if (q.rule == FRACTAL_RULE_HEAT && r > kBatchMaxRHeat)
@@ -248,7 +283,8 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     hipStream_t cs = nullptr;
-    const int grid = batch_grid_size();
+    // persistent workgroups when asked for, else one workgroup per tile
+    const int grid = (tuning && (tuning->flags & FRACTAL_FLAG_PERSISTENT)) ? batch_grid_size() : 0;
     auto fail = [&](int code) {
         if (cs) {
             hipGraph_t g2 = nullptr;

@@ -41,6 +41,16 @@ struct Geom {
     static constexpr int OFFW = OFF / 4;
     static constexpr int PITCHW = PITCH / 4;
     static constexpr int RIGHTW = OFFW + CPR * W;             // right halo word
+    // 64-byte row segments: log2 of the cells in one segment
+    static constexpr int SEGLOG = S == 1 ? 6 : 4;
+    static constexpr int SLOG = SEGLOG > CLOG ? SEGLOG : CLOG;
+};
+
+// Launch-variant flags of the tile engine.
+enum : int {
+    TILE_SEGMENTS = 1, // read and write whole 64-byte segments that hold a
+                       // member (chunks of them without members carry 0s)
+    TILE_NT_STORE = 2, // non-temporal hint on output stores
 };
 
 template <int BYTES>
@@ -92,26 +102,22 @@ __device__ __forceinline__ uint32_t buf_load<4>(rsrc_t r, uint32_t off)
     return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
-template <int BYTES>
-__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, const typename VecT<BYTES>::T &v);
-template <>
-__device__ __forceinline__ void buf_store<16>(rsrc_t r, uint32_t off, const uint4 &v)
+// AUX is the instruction's cache-policy field (0 = default; 2 = the
+// non-temporal hint, for output that is not read again by this launch).
+template <int BYTES, int AUX>
+__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, const typename VecT<BYTES>::T &v)
 {
-    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-    const u4 d = {v.x, v.y, v.z, v.w};
-    __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, 0);
-}
-template <>
-__device__ __forceinline__ void buf_store<8>(rsrc_t r, uint32_t off, const uint2 &v)
-{
-    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    const u2 d = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b64(d, r, off, 0, 0);
-}
-template <>
-__device__ __forceinline__ void buf_store<4>(rsrc_t r, uint32_t off, const uint32_t &v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+    if constexpr (BYTES == 16) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        const u4 d = {v.x, v.y, v.z, v.w};
+        __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, AUX);
+    } else if constexpr (BYTES == 8) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 d = {v.x, v.y};
+        __builtin_amdgcn_raw_buffer_store_b64(d, r, off, 0, AUX);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, AUX);
+    }
 }
 
 template <int N>
@@ -190,11 +196,14 @@ struct StepParams {
 
 // Process the tile whose top-left cell is (x0, y0).  All NT threads of the
 // workgroup must call it (it contains a workgroup barrier).
-template <int RULE, int R, int NT>
+template <int RULE, int R, int NT, int FL = 0>
 __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
                                           uint32_t x0, uint32_t y0)
 {
     using G = Geom<RULE, R>;
+    // granularity of the load / store predicate (log2 cells)
+    constexpr int PLOG = (FL & TILE_SEGMENTS) ? G::SLOG : G::CLOG;
+    constexpr int AUX = (FL & TILE_NT_STORE) ? 2 : 0;
     using V = typename VecT<G::CB>::T;
     const uint32_t n = 1u << p.k;
     const uint32_t pitch = n * G::S; // bytes per state row (<= 2^18)
@@ -221,7 +230,7 @@ __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
         const int64_t y = (int64_t)y0 - 1 + ry;
         const uint32_t xc = x0 + (uint32_t)c * G::CCELLS;
         const bool rowok = it < NCHUNK && y >= 0 && y < (int64_t)n;
-        const bool live = rowok && (((xc >> G::CLOG) & ((uint32_t)y >> G::CLOG)) == 0u);
+        const bool live = rowok && (((xc >> PLOG) & ((uint32_t)y >> PLOG)) == 0u);
         const uint32_t roff = (uint32_t)ry * pitch;
         if constexpr (G::TINY) {
             // rho <= 2 uint8 tile: one word = tile cells, right halo, zeros
@@ -291,8 +300,16 @@ __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
         const int j = it / G::CPR, c = it % G::CPR;
         const uint32_t y = y0 + (uint32_t)j;
         const uint32_t xc = x0 + (uint32_t)c * G::CCELLS;
-        if (((xc >> G::CLOG) & (y >> G::CLOG)) != 0u)
-            continue; // no member in this chunk: it is 0 and stays 0
+        const uint32_t ooff = (uint32_t)j * pitch + xc * G::S;
+        if (((xc >> G::CLOG) & (y >> G::CLOG)) != 0u) {
+            // no member in this chunk: it is 0 and stays 0; with whole
+            // segments it is rewritten as 0 when its segment holds a member
+            if constexpr (PLOG != G::CLOG && !G::TINY) {
+                if (((xc >> PLOG) & (y >> PLOG)) == 0u)
+                    buf_store<G::CB, AUX>(dst, ooff, V{});
+            }
+            continue;
+        }
         const uint32_t *lw = reinterpret_cast<const uint32_t *>(lds);
         const int base = G::OFFW + c * G::W;
         const int r_up = j * G::PITCHW, r_md = (j + 1) * G::PITCHW, r_dn = (j + 2) * G::PITCHW;
@@ -333,17 +350,16 @@ __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
                 out[w] = ((x & y) == 0u) ? __float_as_uint(v) : 0u;
             }
         }
-        const uint32_t ooff = (uint32_t)j * pitch + xc * G::S;
         if constexpr (G::TINY) {
             // x0 is not word-aligned here: mask and store each cell on its own
 #pragma unroll
             for (int i = 0; i < G::RHO; ++i) {
                 const uint8_t b = (((xc + (uint32_t)i) & y) == 0u) ? (uint8_t)((out[0] >> (8 * i)) & 1u)
                                                                    : (uint8_t)0;
-                __builtin_amdgcn_raw_buffer_store_b8(b, dst, ooff + (uint32_t)i, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b8(b, dst, ooff + (uint32_t)i, 0, AUX);
             }
         } else {
-            buf_store<G::CB>(dst, ooff, pack<G::W>(out));
+            buf_store<G::CB, AUX>(dst, ooff, pack<G::W>(out));
         }
     }
 }

@@ -107,7 +107,7 @@ class Server {
         if ((rc = hip_error(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking),
                             "copy stream")))
             return rc;
-        grid_ = batch_grid_size();
+        grid_ = 0; // one workgroup per tile (see launch_batch)
         worker_ = std::thread([this] { run(); });
         retirer_ = std::thread([this] { retire_loop(); });
         return FRACTAL_OK;

@@ -60,7 +60,7 @@ struct LaunchArgs {
 // One workgroup per tile.  lambda maps: the grid is the compact 3^ceil(rb/2)
 // x 3^floor(rb/2) orthotope.  Bounding box: the grid is n_b x n_b and a
 // workgroup on an empty tile returns before touching memory.
-template <int RULE, int R, int NT, int MAP>
+template <int RULE, int R, int NT, int MAP, int FL>
 __global__ __launch_bounds__(NT) void step_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
@@ -90,40 +90,56 @@ __global__ __launch_bounds__(NT) void step_kernel(LaunchArgs a)
         else
             t = lambda_wave_curve(L, a.rb);
     }
-    tile_step<RULE, R, NT>(lds, a.p, t.x << R, t.y << R);
+    tile_step<RULE, R, NT, FL>(lds, a.p, t.x << R, t.y << R);
 }
 
 typedef void (*StepFn)(LaunchArgs);
 
-template <int MAP, int RULE, int NT>
+template <int MAP, int RULE, int NT, int FL>
 static StepFn pick_r(int r)
 {
     switch (r) {
-    case 0: return step_kernel<RULE, 0, NT, MAP>;
-    case 1: return step_kernel<RULE, 1, NT, MAP>;
-    case 2: return step_kernel<RULE, 2, NT, MAP>;
-    case 3: return step_kernel<RULE, 3, NT, MAP>;
-    case 4: return step_kernel<RULE, 4, NT, MAP>;
-    case 5: return step_kernel<RULE, 5, NT, MAP>;
-    case 6: return step_kernel<RULE, 6, NT, MAP>;
+    case 0: return step_kernel<RULE, 0, NT, MAP, FL>;
+    case 1: return step_kernel<RULE, 1, NT, MAP, FL>;
+    case 2: return step_kernel<RULE, 2, NT, MAP, FL>;
+    case 3: return step_kernel<RULE, 3, NT, MAP, FL>;
+    case 4: return step_kernel<RULE, 4, NT, MAP, FL>;
+    case 5: return step_kernel<RULE, 5, NT, MAP, FL>;
+    case 6: return step_kernel<RULE, 6, NT, MAP, FL>;
     default: return nullptr;
     }
 }
 
-template <int MAP>
-static StepFn pick_rule(int rule, int r, int threads)
+template <int MAP, int RULE, int FL>
+static StepFn pick_threads(int r, int threads)
 {
-    if (rule == FRACTAL_RULE_CA)
-        return threads == 256 ? pick_r<MAP, RULE_CA, 256>(r) : pick_r<MAP, RULE_CA, 64>(r);
-    return threads == 256 ? pick_r<MAP, RULE_HEAT, 256>(r) : pick_r<MAP, RULE_HEAT, 64>(r);
+    return threads == 256 ? pick_r<MAP, RULE, 256, FL>(r) : pick_r<MAP, RULE, 64, FL>(r);
 }
 
-static StepFn pick(int map, int rule, int r, int threads)
+template <int MAP, int FL>
+static StepFn pick_rule(int rule, int r, int threads)
+{
+    return rule == FRACTAL_RULE_CA ? pick_threads<MAP, RULE_CA, FL>(r, threads)
+                                   : pick_threads<MAP, RULE_HEAT, FL>(r, threads);
+}
+
+template <int MAP>
+static StepFn pick_flags(int rule, int r, int threads, int flags)
+{
+    switch (flags & 3) {
+    case 0: return pick_rule<MAP, 0>(rule, r, threads);
+    case 1: return pick_rule<MAP, 1>(rule, r, threads);
+    case 2: return pick_rule<MAP, 2>(rule, r, threads);
+    default: return pick_rule<MAP, 3>(rule, r, threads);
+    }
+}
+
+static StepFn pick(int map, int rule, int r, int threads, int flags)
 {
     switch (map) {
-    case MAP_LAMBDA: return pick_rule<MAP_LAMBDA>(rule, r, threads);
-    case MAP_BB: return pick_rule<MAP_BB>(rule, r, threads);
-    case MAP_MFMA: return pick_rule<MAP_MFMA>(rule, r, threads);
+    case MAP_LAMBDA: return pick_flags<MAP_LAMBDA>(rule, r, threads, flags);
+    case MAP_BB: return pick_flags<MAP_BB>(rule, r, threads, flags);
+    case MAP_MFMA: return pick_flags<MAP_MFMA>(rule, r, threads, flags);
     default: return nullptr;
     }
 }
@@ -131,7 +147,7 @@ static StepFn pick(int map, int rule, int r, int threads)
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s)
 {
-    StepFn fn = pick(map, rule, t.r, t.threads);
+    StepFn fn = pick(map, rule, t.r, t.threads, t.flags);
     if (!fn)
         return set_error(FRACTAL_E_INVAL, "no kernel for map %d rule %d r %d threads %d",
                          map, rule, t.r, t.threads);

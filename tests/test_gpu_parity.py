@@ -79,9 +79,12 @@ def test_seed_fill_matches_input_generator(rule):
 
 
 # ------------------------------------------------------------------ steps
-def _run(map_, k, r, rule, b0, b1, steps):
+def _run(map_, k, r, rule, b0, b1, steps, flags=None):
     alpha = ALPHA
-    if map_ == F.MAP_LAMBDA:
+    if flags is not None:
+        t = F.get_tuning(k, rule) if r == F.R_AUTO else (r, 64, 2, 0)
+        F.step_tuned(map_, k, rule, alpha, b0, b1, steps, t[0], t[1], t[2], flags)
+    elif map_ == F.MAP_LAMBDA:
         F.lambda_step(k, r, rule, alpha, b0, b1, steps)
     elif map_ == F.MAP_BB:
         F.bb_step(k, r, rule, alpha, b0, b1, steps)
@@ -89,10 +92,12 @@ def _run(map_, k, r, rule, b0, b1, steps):
         F.lambda_step_mfma(k, r, rule, alpha, b0, b1, steps)
 
 
+@pytest.mark.parametrize("flags", [None, 1, 2, 3])
 @pytest.mark.parametrize("rule", RULES)
 @pytest.mark.parametrize("map_", MAPS)
-def test_steps_small_levels_every_r(rule, map_):
-    """Every tile size on small gaskets, checked after each of 6 steps."""
+def test_steps_small_levels_every_r(rule, map_, flags):
+    """Every tile size and launch flag on small gaskets, checked after each
+    of 6 steps."""
     for k in range(0, 8):
         for r in range(0, min(k, 6) + 1):
             init = fi.window_values(k, rule, 100 + k)
@@ -102,7 +107,7 @@ def test_steps_small_levels_every_r(rule, map_):
             for t in range(1, 7):
                 # one step from the current buffer into the other
                 src, dst = (b0, b1) if (t - 1) % 2 == 0 else (b1, b0)
-                _run(map_, k, r, rule, src, dst, 1)
+                _run(map_, k, r, rule, src, dst, 1, flags)
                 _sync()
                 ref = oracle_steps(k, rule, ref, 1)
                 assert_match(k, rule, dst.cpu().numpy(), ref,
@@ -139,11 +144,12 @@ def test_lambda_bb_mfma_bit_identical_k12(rule):
     init = fi.window_values(k, rule, 5)
     outs = []
     for m in MAPS:
-        for (r, th, order) in [(3, 64, 0), (4, 64, 2), (5, 256, 1), (6, 256, 2), (5, 64, 0)]:
+        for (r, th, order, fl) in [(3, 64, 0, 0), (4, 64, 2, 1), (5, 256, 1, 2), (6, 256, 2, 3),
+                                   (5, 64, 0, 1), (2, 64, 2, 3), (1, 64, 0, 1)]:
             b0, b1 = to_device(init), zeros_state(k, rule)
-            F.step_tuned(m, k, rule, ALPHA, b0, b1, steps, r, th, order)
+            F.step_tuned(m, k, rule, ALPHA, b0, b1, steps, r, th, order, fl)
             _sync()
-            outs.append(((m, r, th, order), b1.cpu().numpy()))
+            outs.append(((m, r, th, order, fl), b1.cpu().numpy()))
     base = outs[0][1]
     for cfg, o in outs[1:]:
         assert np.array_equal(o.view(np.uint8), base.view(np.uint8)), f"{cfg} differs"

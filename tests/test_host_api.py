@@ -76,15 +76,17 @@ def test_mfma_level_limit():
 def test_tuning_defaults_and_validation():
     for k in range(0, 17):
         for rule in (0, 1):
-            r, th, order = F.get_tuning(k, rule)
+            r, th, order, flags = F.get_tuning(k, rule)
             assert 0 <= r <= min(k, 6) and k - r <= 15
-            assert th in (64, 256) and order in (0, 1, 2)
+            assert th in (64, 256) and order in (0, 1, 2) and flags in (0, 1, 2, 3)
     with pytest.raises(F.FractalError):
         F.set_tuning(10, 0, 7, 64, 0)
     with pytest.raises(F.FractalError):
         F.set_tuning(10, 0, 4, 128, 0)
     with pytest.raises(F.FractalError):
         F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 1, 4, 64, 9, stream=0)
+    with pytest.raises(F.FractalError):
+        F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 1, 4, 64, 0, 4, stream=0)
 
 
 def test_batch_validation():
@@ -93,6 +95,8 @@ def test_batch_validation():
     with pytest.raises(F.FractalError):  # two instances share a buffer
         F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1),
                       (10, 0, 5, 0.2, FAKE1, FAKE1 + (1 << 22))], stream=0)
+    with pytest.raises(F.FractalError):  # step-only flags are refused
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 1), stream=0)
     F.batch_step([], stream=0)
     F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], stream=0)  # no steps: no-op
 
