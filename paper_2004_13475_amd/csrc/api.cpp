@@ -100,10 +100,17 @@ static int clamp_r(int k, int r)
     return r;
 }
 
+// Used until the autotuner has run for (device, k, rule): the fastest lambda
+// launches measured at level 16 on MI355X (64 x 64 automaton tiles moving
+// whole segments; 32 x 32 heat tiles moving whole segments with
+// non-temporal stores).
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 5 : 4);
-    return tuning_for_r(MAP_LAMBDA, k, rule, r);
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 6 : 5);
+    fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
+    t.flags = rule == FRACTAL_RULE_CA ? FRACTAL_FLAG_SEGMENTS
+                                      : (FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE);
+    return t;
 }
 
 static std::mutex g_tune_mu;

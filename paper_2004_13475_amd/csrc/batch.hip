@@ -1,14 +1,19 @@
-// batch.hip -- many gaskets of uneven levels advanced by one persistent
-// kernel per step.  The tiles of all instances form one work list: instance j
-// owns tile ids [tile_begin_j, tile_begin_j + 3^(k_j - r_j)); a tile id is
-// turned into (instance, local omega) with the per-instance offset table and
-// then into a tile by that instance's lambda.  The T step launches of a
-// fractal_batch_step call are captured once into a HIP graph.
+// batch.hip -- many gaskets of uneven levels advanced together.
+//
+// Instances are grouped into launch classes by their tile launch (rule, tile
+// level r, threads, step flags).  The tiles of a class form one work list:
+// instance j owns tile ids [tile_begin_j, tile_begin_j + 3^(k_j - r)); a tile
+// id is turned into (instance, local omega) with the per-instance offset
+// table and then into a tile by that instance's lambda.  Each step is one
+// launch per class; the launches of a fractal_batch_step call are captured
+// once into a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "device_map.hpp"
@@ -17,29 +22,8 @@
 
 namespace fractal {
 
-constexpr int kBatchThreads = 64;
-constexpr int kBatchMaxRHeat = 5;
-constexpr int kBatchMaxRCa = 6;
-constexpr int kBatchLds =
-    Geom<RULE_CA, 6>::LDS_BYTES > Geom<RULE_HEAT, 5>::LDS_BYTES ? Geom<RULE_CA, 6>::LDS_BYTES
-                                                                 : Geom<RULE_HEAT, 5>::LDS_BYTES;
-
-template <int RULE, int R>
-__device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, uint32_t L,
-                                           int local_step)
-{
-    const TileXY t = lambda_wave_curve(L, e.k - R);
-    const bool odd = ((e.phase + local_step) & 1) != 0;
-    StepParams p;
-    p.src = odd ? e.buf1 : e.buf0;
-    p.dst = odd ? e.buf0 : e.buf1;
-    p.k = e.k;
-    p.alpha = e.alpha;
-    tile_step<RULE, R, kBatchThreads>(lds, p, t.x << R, t.y << R);
-}
-
-// Find the instance owning tile id w: the last of entries [0, count) whose
-// range starts at or before w (entries are sorted by tile_begin).
+// Last of entries [0, count) whose range starts at or before w (entries are
+// sorted by tile_begin).
 __device__ __forceinline__ int find_instance(const BatchEntry *__restrict__ table, int count,
                                              uint64_t w)
 {
@@ -54,39 +38,45 @@ __device__ __forceinline__ int find_instance(const BatchEntry *__restrict__ tabl
     return lo;
 }
 
-__device__ __forceinline__ void batch_dispatch(uint8_t *lds, const BatchEntry &e, uint32_t L,
-                                               int local_step)
+template <int RULE, int R, int NT, int FL>
+__device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, uint32_t L,
+                                           int local_step)
 {
-    if (e.rule == RULE_CA) {
-        switch (e.r) {
-        case 0: batch_tile<RULE_CA, 0>(lds, e, L, local_step); break;
-        case 1: batch_tile<RULE_CA, 1>(lds, e, L, local_step); break;
-        case 2: batch_tile<RULE_CA, 2>(lds, e, L, local_step); break;
-        case 3: batch_tile<RULE_CA, 3>(lds, e, L, local_step); break;
-        case 4: batch_tile<RULE_CA, 4>(lds, e, L, local_step); break;
-        case 5: batch_tile<RULE_CA, 5>(lds, e, L, local_step); break;
-        default: batch_tile<RULE_CA, 6>(lds, e, L, local_step); break;
-        }
-    } else {
-        switch (e.r) {
-        case 0: batch_tile<RULE_HEAT, 0>(lds, e, L, local_step); break;
-        case 1: batch_tile<RULE_HEAT, 1>(lds, e, L, local_step); break;
-        case 2: batch_tile<RULE_HEAT, 2>(lds, e, L, local_step); break;
-        case 3: batch_tile<RULE_HEAT, 3>(lds, e, L, local_step); break;
-        case 4: batch_tile<RULE_HEAT, 4>(lds, e, L, local_step); break;
-        default: batch_tile<RULE_HEAT, 5>(lds, e, L, local_step); break;
-        }
-    }
+    const TileXY t = lambda_wave_curve(L, e.k - R);
+    const bool odd = ((e.phase + local_step) & 1) != 0;
+    StepParams p;
+    p.src = odd ? e.buf1 : e.buf0;
+    p.dst = odd ? e.buf0 : e.buf1;
+    p.k = e.k;
+    p.alpha = e.alpha;
+    tile_step<RULE, R, NT, FL>(lds, p, t.x << R, t.y << R);
 }
 
-// Persistent form: workgroup b handles the contiguous tile ids
+// One workgroup per tile of the class's work list, ids laid out per die in
+// contiguous ranges as in the lambda step kernels.  The grid is 2-D only to
+// stay inside launch limits; workgroups past the end return at once.
+template <int RULE, int R, int NT, int FL>
+__global__ __launch_bounds__(NT) void batch_tile_kernel(const BatchEntry *__restrict__ table,
+                                                        int count, uint32_t total,
+                                                        int local_step)
+{
+    __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
+    const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
+    if (lin >= total)
+        return;
+    const uint32_t w = xcd_chunk(lin, total);
+    const BatchEntry e = table[find_instance(table, count, w)];
+    batch_tile<RULE, R, NT, FL>(lds, e, (uint32_t)(w - e.tile_begin), local_step);
+}
+
+// Persistent form: workgroup b walks the contiguous tile ids
 // [b*per, (b+1)*per) in order, so tiles that are neighbours in the gasket's
-// self-similar order stay on one die and share its L2.  Entries [0, count)
-// are the active instances; `total` is the end of the last one's range.
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(
+// self-similar order stay on one die and share its L2.
+template <int RULE, int R, int NT, int FL>
+__global__ __launch_bounds__(NT) void batch_persistent_kernel(
     const BatchEntry *__restrict__ table, int count, uint64_t total, int local_step)
 {
-    __shared__ __align__(16) uint8_t lds[kBatchLds];
+    __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
     const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
     const uint64_t w0 = (uint64_t)blockIdx.x * per;
     const uint64_t w1 = w0 + per < total ? w0 + per : total;
@@ -100,68 +90,166 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(
             next = j + 1 < count ? table[j + 1].tile_begin : ~0ull;
         }
         const BatchEntry e = table[j];
-        __syncthreads(); // previous tile's LDS reads are done
-        batch_dispatch(lds, e, (uint32_t)(w - e.tile_begin), local_step);
+        __syncthreads(); // the previous tile's LDS reads are done
+        batch_tile<RULE, R, NT, FL>(lds, e, (uint32_t)(w - e.tile_begin), local_step);
     }
 }
 
-// One workgroup per tile of the combined work list (ids laid out per die in
-// contiguous ranges, as the lambda step kernels do).
-__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(
-    const BatchEntry *__restrict__ table, int count, uint32_t total, int local_step)
+typedef void (*TileFn)(const BatchEntry *, int, uint32_t, int);
+typedef void (*PersistFn)(const BatchEntry *, int, uint64_t, int);
+
+template <int RULE, int NT, int FL>
+static void pick_r(int r, TileFn *tf, PersistFn *pf)
 {
-    __shared__ __align__(16) uint8_t lds[kBatchLds];
-    const uint32_t w = xcd_chunk(blockIdx.x, total);
-    const BatchEntry e = table[find_instance(table, count, w)];
-    batch_dispatch(lds, e, (uint32_t)(w - e.tile_begin), local_step);
+    switch (r) {
+#define FRACTAL_BATCH_CASE(RR)                                                                     \
+    case RR:                                                                                       \
+        *tf = batch_tile_kernel<RULE, RR, NT, FL>;                                                 \
+        *pf = batch_persistent_kernel<RULE, RR, NT, FL>;                                           \
+        break;
+        FRACTAL_BATCH_CASE(0)
+        FRACTAL_BATCH_CASE(1)
+        FRACTAL_BATCH_CASE(2)
+        FRACTAL_BATCH_CASE(3)
+        FRACTAL_BATCH_CASE(4)
+        FRACTAL_BATCH_CASE(5)
+        FRACTAL_BATCH_CASE(6)
+#undef FRACTAL_BATCH_CASE
+    default:
+        *tf = nullptr;
+        *pf = nullptr;
+    }
 }
 
-int batch_supported_r(int rule, int r)
+template <int RULE, int FL>
+static void pick_threads(int r, int threads, TileFn *tf, PersistFn *pf)
 {
-    return r >= 0 && r <= (rule == FRACTAL_RULE_CA ? kBatchMaxRCa : kBatchMaxRHeat);
+    if (threads == 256)
+        pick_r<RULE, 256, FL>(r, tf, pf);
+    else
+        pick_r<RULE, 64, FL>(r, tf, pf);
 }
 
-int batch_default_r(int k, int rule)
+template <int RULE>
+static void pick_flags(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
 {
-    int r = default_tuning(k, rule).r;
-    const int rmax = rule == FRACTAL_RULE_CA ? kBatchMaxRCa : kBatchMaxRHeat;
-    if (r > rmax)
-        r = rmax;
-    if (r > k)
-        r = k;
-    if (k - r > kMaxBlockLevel)
-        r = k - kMaxBlockLevel;
-    return r;
+    switch (flags & 3) {
+    case 0: pick_threads<RULE, 0>(r, threads, tf, pf); break;
+    case 1: pick_threads<RULE, 1>(r, threads, tf, pf); break;
+    case 2: pick_threads<RULE, 2>(r, threads, tf, pf); break;
+    default: pick_threads<RULE, 3>(r, threads, tf, pf); break;
+    }
 }
 
-int batch_grid_size()
+static int batch_grid_size()
 {
     static int grid = 0;
     if (grid == 0) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = cus * 32; // enough resident single-wave workgroups to cover latency
+        grid = cus * 8; // resident workgroups per die-share of the chip
     }
     return grid;
 }
 
-int launch_batch(const BatchEntry *d_table, int count, uint64_t total_tiles, int local_step,
-                 int grid, hipStream_t s)
+fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
 {
-    if (count <= 0 || total_tiles == 0)
-        return FRACTAL_OK;
-    if (grid == 0 && total_tiles < 0x7FFFFFFFull) {
-        hipLaunchKernelGGL(batch_tile_kernel, dim3((unsigned)total_tiles), dim3(kBatchThreads), 0,
-                           s, d_table, count, (uint32_t)total_tiles, local_step);
-        return hip_error(hipGetLastError(), "batch kernel launch");
+    fractal_tuning t = default_tuning(k, rule);
+    if (forced) {
+        if (forced->r != FRACTAL_R_AUTO)
+            t = tuning_for_r(MAP_LAMBDA, k, rule, forced->r);
+        if (forced->threads == 64 || forced->threads == 256)
+            t.threads = forced->threads;
+        t.flags = forced->flags & (FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE);
     }
-    if (grid == 0)
-        grid = batch_grid_size();
-    const uint64_t g = total_tiles < (uint64_t)grid ? total_tiles : (uint64_t)grid;
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)g), dim3(kBatchThreads), 0, s, d_table,
-                       count, total_tiles, local_step);
-    return hip_error(hipGetLastError(), "batch kernel launch");
+    if (t.r > k)
+        t.r = k;
+    if (t.r > kMaxR)
+        t.r = kMaxR;
+    if (k - t.r > kMaxBlockLevel)
+        t.r = k - kMaxBlockLevel;
+    t.order = FRACTAL_ORDER_CURVE_XCD;
+    return t;
+}
+
+void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
+{
+    classes_.clear();
+    max_steps_ = 0;
+    std::map<std::tuple<int, int, int, int>, std::vector<size_t>> groups;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const BatchItem &it = items[i];
+        groups[std::make_tuple(it.rule, it.tuning.r, it.tuning.threads, it.tuning.flags & 3)]
+            .push_back(i);
+        max_steps_ = std::max(max_steps_, it.steps);
+    }
+    size_t at = 0;
+    for (auto &g : groups) {
+        std::vector<size_t> &ids = g.second;
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](size_t a, size_t b) { return items[a].steps > items[b].steps; });
+        Class c;
+        std::tie(c.rule, c.r, c.threads, c.flags) = g.first;
+        c.first = at;
+        uint64_t acc = 0;
+        for (size_t i : ids) {
+            const BatchItem &it = items[i];
+            BatchEntry &e = host[at++];
+            e.tile_begin = acc;
+            e.buf0 = it.buf0;
+            e.buf1 = it.buf1;
+            e.k = it.k;
+            e.r = c.r;
+            e.rule = it.rule;
+            e.phase = it.phase;
+            e.alpha = it.alpha;
+            e.pad = 0;
+            c.steps.push_back(it.steps);
+            c.prefix.push_back(acc);
+            acc += pow3_u64(it.k - c.r);
+        }
+        c.prefix.push_back(acc);
+        classes_.push_back(std::move(c));
+    }
+    entries_ = at;
+}
+
+int BatchPlan::launch_step(const BatchEntry *d_table, int j, bool persistent, hipStream_t s) const
+{
+    for (const Class &c : classes_) {
+        size_t active = c.steps.size();
+        while (active > 0 && c.steps[active - 1] <= j)
+            --active;
+        if (active == 0)
+            continue;
+        const uint64_t total = c.prefix[active];
+        TileFn tf = nullptr;
+        PersistFn pf = nullptr;
+        if (c.rule == FRACTAL_RULE_CA)
+            pick_flags<RULE_CA>(c.r, c.threads, c.flags, &tf, &pf);
+        else
+            pick_flags<RULE_HEAT>(c.r, c.threads, c.flags, &tf, &pf);
+        if (!tf || !pf)
+            return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d", c.r,
+                             c.threads);
+        const BatchEntry *tab = d_table + c.first;
+        if (!persistent && total < 0x7FFFFFFFull) {
+            const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
+            const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
+            hipLaunchKernelGGL(tf, dim3(gx, gy), dim3(c.threads), 0, s, tab, (int)active,
+                               (uint32_t)total, j);
+        } else {
+            const uint64_t grid = std::min<uint64_t>(total, (uint64_t)batch_grid_size() *
+                                                                (c.threads == 64 ? 4 : 1));
+            hipLaunchKernelGGL(pf, dim3((unsigned)grid), dim3(c.threads), 0, s, tab,
+                               (int)active, total, j);
+        }
+        int rc = hip_error(hipGetLastError(), "batch kernel launch");
+        if (rc)
+            return rc;
+    }
+    return FRACTAL_OK;
 }
 
 // Graphs whose launch may still be running, with what they keep alive.
@@ -173,13 +261,11 @@ struct PendingGraph {
 static std::mutex g_pending_mu;
 static std::vector<PendingGraph> g_pending;
 
-static void reap_pending(bool wait)
+static void reap_pending()
 {
     std::lock_guard<std::mutex> lk(g_pending_mu);
     std::vector<PendingGraph> keep;
     for (PendingGraph &p : g_pending) {
-        if (wait)
-            (void)hipEventSynchronize(p.done);
         if (hipEventQuery(p.done) == hipSuccess) {
             (void)hipGraphExecDestroy(p.exec);
             (void)hipEventDestroy(p.done);
@@ -204,29 +290,26 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         return FRACTAL_OK;
     if (!inst)
         return set_error(FRACTAL_E_INVAL, "null instance array");
-    if (tuning && tuning->r != FRACTAL_R_AUTO && (tuning->r < 0 || tuning->r > kMaxR))
-        return set_error(FRACTAL_E_INVAL, "tuning r=%d outside [0, %d]", tuning->r, kMaxR);
-    if (tuning && (tuning->flags & ~FRACTAL_FLAG_PERSISTENT))
-        return set_error(FRACTAL_E_INVAL, "batch tuning flags 0x%x (only PERSISTENT)",
-                         tuning->flags);
-    // validate every instance, pick its tile level
-    std::vector<int> rs(count);
-    int max_steps = 0;
+    if (tuning) {
+        if (tuning->r != FRACTAL_R_AUTO && (tuning->r < 0 || tuning->r > kMaxR))
+            return set_error(FRACTAL_E_INVAL, "tuning r=%d outside [0, %d]", tuning->r, kMaxR);
+        if (tuning->threads != 0 && tuning->threads != 64 && tuning->threads != 256)
+            return set_error(FRACTAL_E_INVAL, "tuning threads=%d (0, 64 or 256)",
+                             tuning->threads);
+        if (tuning->flags &
+            ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE))
+            return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
+    }
+    // validate every instance and pick its tile launch
+    std::vector<BatchItem> items(count);
     for (int i = 0; i < count; ++i) {
         const fractal_instance &q = inst[i];
-        int r = (tuning && tuning->r != FRACTAL_R_AUTO) ? tuning->r
-                                                        : batch_default_r(q.k < 0 ? 0 : q.k, q.rule);
-        if (q.k >= 0 && r > q.k)
-            r = q.k;
-        if (q.rule == FRACTAL_RULE_HEAT && r > kBatchMaxRHeat)
-            r = kBatchMaxRHeat;
-        if (q.k >= 0 && q.k - r > kMaxBlockLevel)
-            r = q.k - kMaxBlockLevel;
-        int rc = check_step_args(q.k, r, q.rule, q.alpha, q.d_buf0, q.d_buf1, q.steps);
+        const fractal_tuning t = batch_item_tuning(q.k < 0 ? 0 : q.k, q.rule, tuning);
+        int rc = check_step_args(q.k, t.r, q.rule, q.alpha, q.d_buf0, q.d_buf1, q.steps);
         if (rc)
             return set_error(rc, "instance %d: %s", i, fractal_last_error());
-        rs[i] = r;
-        max_steps = std::max(max_steps, q.steps);
+        items[i] = BatchItem{q.k,  q.rule, q.steps, 0, q.alpha, static_cast<uint8_t *>(q.d_buf0),
+                             static_cast<uint8_t *>(q.d_buf1), t};
     }
     // no two instances may share a buffer
     {
@@ -241,50 +324,26 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
             if (spans[i].first < spans[i - 1].second)
                 return set_error(FRACTAL_E_INVAL, "instance buffers overlap");
     }
+    int max_steps = 0;
+    for (const BatchItem &it : items)
+        max_steps = std::max(max_steps, it.steps);
     if (max_steps == 0)
         return FRACTAL_OK;
-
-    reap_pending(false);
+    const bool persistent = tuning && (tuning->flags & FRACTAL_FLAG_PERSISTENT);
+    reap_pending();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // order by steps (descending) so the instances still running at any step
-    // form a prefix of the table
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return inst[a].steps > inst[b].steps; });
     BatchEntry *host = nullptr;
-    int rc = hip_error(hipHostMalloc((void **)&host, sizeof(BatchEntry) * (count + 1)),
-                       "pinned table");
+    int rc = hip_error(hipHostMalloc((void **)&host, sizeof(BatchEntry) * count), "pinned table");
     if (rc)
         return rc;
-    uint64_t acc = 0;
-    std::vector<uint64_t> prefix(count + 1);
-    for (int i = 0; i < count; ++i) {
-        const int src = order[i];
-        const fractal_instance &q = inst[src];
-        BatchEntry &e = host[i];
-        e.tile_begin = acc;
-        e.buf0 = static_cast<uint8_t *>(q.d_buf0);
-        e.buf1 = static_cast<uint8_t *>(q.d_buf1);
-        e.k = q.k;
-        e.r = rs[src];
-        e.rule = q.rule;
-        e.phase = 0;
-        e.alpha = q.alpha;
-        e.pad = 0;
-        prefix[i] = acc;
-        acc += pow3_u64(q.k - rs[src]);
-    }
-    prefix[count] = acc;
-    host[count] = BatchEntry{acc, nullptr, nullptr, 0, 0, 0, 0, 0.0f, 0};
+    BatchPlan plan;
+    plan.build(items, host);
 
     BatchEntry *d_table = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     hipStream_t cs = nullptr;
-    // persistent workgroups when asked for, else one workgroup per tile
-    const int grid = (tuning && (tuning->flags & FRACTAL_FLAG_PERSISTENT)) ? batch_grid_size() : 0;
     auto fail = [&](int code) {
         if (cs) {
             hipGraph_t g2 = nullptr;
@@ -295,6 +354,7 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
                 (void)hipGraphDestroy(g2);
             (void)hipStreamDestroy(cs);
         }
+        (void)hipStreamSynchronize(s);
         if (graph)
             (void)hipGraphDestroy(graph);
         if (exec)
@@ -302,15 +362,14 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         if (done)
             (void)hipEventDestroy(done);
         if (d_table)
-            (void)hipFreeAsync(d_table, s);
-        (void)hipStreamSynchronize(s);
+            (void)hipFree(d_table);
         (void)hipHostFree(host);
         return code;
     };
-    if ((rc = hip_error(hipMallocAsync((void **)&d_table, sizeof(BatchEntry) * (count + 1), s),
+    if ((rc = hip_error(hipMallocAsync((void **)&d_table, sizeof(BatchEntry) * count, s),
                         "device table")))
         return fail(rc);
-    if ((rc = hip_error(hipMemcpyAsync(d_table, host, sizeof(BatchEntry) * (count + 1),
+    if ((rc = hip_error(hipMemcpyAsync(d_table, host, sizeof(BatchEntry) * count,
                                        hipMemcpyHostToDevice, s),
                         "table copy")))
         return fail(rc);
@@ -320,13 +379,9 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     if ((rc = hip_error(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal),
                         "begin capture")))
         return fail(rc);
-    int active = count;
-    for (int t = 0; t < max_steps; ++t) {
-        while (active > 0 && inst[order[active - 1]].steps <= t)
-            --active;
-        if ((rc = launch_batch(d_table, active, prefix[active], t, grid, cs)))
+    for (int t = 0; t < plan.max_steps(); ++t)
+        if ((rc = plan.launch_step(d_table, t, persistent, cs)))
             return fail(rc);
-    }
     if ((rc = hip_error(hipStreamEndCapture(cs, &graph), "end capture")))
         return fail(rc);
     (void)hipStreamDestroy(cs);

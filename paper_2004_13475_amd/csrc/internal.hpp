@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/fractal.h"
 
 namespace fractal {
@@ -58,9 +60,9 @@ int launch_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
 int launch_checksum(int k, int rule, const void *d_buf,
                     unsigned long long *d_out, hipStream_t s);
 
-// Batched persistent step: device table entry per instance.
+// Batched steps: device table entry per instance.
 struct BatchEntry {
-    uint64_t tile_begin; // prefix of 3^(k_j - r_j) over earlier entries
+    uint64_t tile_begin; // prefix of 3^(k_j - r) over earlier entries of the class
     uint8_t *buf0;
     uint8_t *buf1;
     int32_t k;
@@ -72,12 +74,42 @@ struct BatchEntry {
 };
 static_assert(sizeof(BatchEntry) == 48, "BatchEntry layout");
 
-// One batched launch over the first `count` table entries (sorted so that the
-// active ones form a prefix): tiles [0, total_tiles) of step `local_step`.
-int launch_batch(const BatchEntry *d_table, int count, uint64_t total_tiles,
-                 int local_step, int grid, hipStream_t s);
-int batch_supported_r(int rule, int r);
-int batch_default_r(int k, int rule);
-int batch_grid_size();
+// One gasket advanced by a batched launch sequence.
+struct BatchItem {
+    int k, rule;
+    int steps; // steps to run in this sequence (local steps 0..steps-1)
+    int phase; // steps done before (input is buf[phase & 1])
+    float alpha;
+    uint8_t *buf0, *buf1;
+    fractal_tuning tuning; // tile launch (r, threads, flags) for this item
+};
+
+// Instances grouped by launch class (rule, r, threads, step flags); each
+// class is a contiguous run of table entries sorted by steps (descending),
+// so the items still running at local step j form a prefix of the class.
+class BatchPlan {
+  public:
+    // Fills `host` (capacity >= items.size()) and records the classes.
+    void build(const std::vector<BatchItem> &items, BatchEntry *host);
+    // Launch local step j of every class whose prefix is non-empty.
+    int launch_step(const BatchEntry *d_table, int j, bool persistent, hipStream_t s) const;
+    int max_steps() const { return max_steps_; }
+    size_t entries() const { return entries_; }
+
+  private:
+    struct Class {
+        int rule, r, threads, flags;
+        size_t first;
+        std::vector<int> steps;       // per entry, descending
+        std::vector<uint64_t> prefix; // tile prefix, size steps.size() + 1
+    };
+    std::vector<Class> classes_;
+    int max_steps_ = 0;
+    size_t entries_ = 0;
+};
+
+// Tile launch used for one batched instance: `forced` (may be NULL) overrides
+// the per-level cached or default tuning.
+fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced);
 
 } // namespace fractal

@@ -48,7 +48,8 @@ struct Slot {
     bool busy = false;
     uint64_t ticket = 0;
     size_t offset = 0;
-    int k = 0, r = 0, rule = 0, steps = 0, done = 0;
+    int k = 0, rule = 0, steps = 0, done = 0;
+    fractal_tuning tuning = {0, 64, 0, 0};
     float alpha = 0.0f;
     uint8_t *buf0 = nullptr, *buf1 = nullptr;
 };
@@ -107,7 +108,6 @@ class Server {
         if ((rc = hip_error(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking),
                             "copy stream")))
             return rc;
-        grid_ = 0; // one workgroup per tile (see launch_batch)
         worker_ = std::thread([this] { run(); });
         retirer_ = std::thread([this] { retire_loop(); });
         return FRACTAL_OK;
@@ -241,7 +241,7 @@ class Server {
                     sl.offset = a.offset;
                     sl.k = tk.rq.k;
                     sl.rule = tk.rq.rule;
-                    sl.r = batch_default_r(sl.k, sl.rule);
+                    sl.tuning = batch_item_tuning(sl.k, sl.rule, nullptr);
                     sl.steps = tk.rq.steps;
                     sl.done = 0;
                     sl.alpha = tk.rq.alpha;
@@ -287,33 +287,20 @@ class Server {
                 (void)hipEventSynchronize(table_ev_[parity]);
                 BatchEntry *ht = host_table_[parity];
                 BatchEntry *dt = reinterpret_cast<BatchEntry *>(arena_ + table_off_[parity]);
-                uint64_t acc = 0;
-                std::vector<uint64_t> prefix(act.size() + 1);
-                for (size_t i = 0; i < act.size(); ++i) {
-                    const Slot &sl = act[i].second;
-                    BatchEntry &e = ht[i];
-                    e.tile_begin = acc;
-                    e.buf0 = sl.buf0;
-                    e.buf1 = sl.buf1;
-                    e.k = sl.k;
-                    e.r = sl.r;
-                    e.rule = sl.rule;
-                    e.phase = sl.done;
-                    e.alpha = sl.alpha;
-                    e.pad = 0;
-                    prefix[i] = acc;
-                    acc += pow3_u64(sl.k - sl.r);
+                std::vector<BatchItem> items;
+                items.reserve(act.size());
+                for (const auto &a : act) {
+                    const Slot &sl = a.second;
+                    items.push_back(BatchItem{sl.k, sl.rule, std::min(c, rem(sl)), sl.done, sl.alpha,
+                                              sl.buf0, sl.buf1, sl.tuning});
                 }
-                prefix[act.size()] = acc;
-                int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * act.size(),
+                BatchPlan plan;
+                plan.build(items, ht);
+                int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * plan.entries(),
                                                   hipMemcpyHostToDevice, stream_),
                                    "table upload");
-                size_t nact = act.size();
-                for (int j = 0; j < c && !rc; ++j) {
-                    while (nact > 0 && rem(act[nact - 1].second) <= j)
-                        --nact;
-                    rc = launch_batch(dt, (int)nact, prefix[nact], j, grid_, stream_);
-                }
+                for (int j = 0; j < c && !rc; ++j)
+                    rc = plan.launch_step(dt, j, false, stream_);
                 if (!rc)
                     rc = hip_error(hipEventRecord(table_ev_[parity], stream_), "event record");
                 parity ^= 1;
@@ -445,7 +432,7 @@ class Server {
     size_t arena_bytes_;
     int max_slots_, per_iter_;
     hipStream_t stream_, copy_stream_ = nullptr;
-    int device_ = 0, grid_ = 0;
+    int device_ = 0;
     size_t table_off_[2] = {0, 0}, sums_off_ = 0, state_base_ = 0;
     BatchEntry *host_table_[2] = {nullptr, nullptr};
     hipEvent_t table_ev_[2] = {nullptr, nullptr};

@@ -95,8 +95,10 @@ def test_batch_validation():
     with pytest.raises(F.FractalError):  # two instances share a buffer
         F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1),
                       (10, 0, 5, 0.2, FAKE1, FAKE1 + (1 << 22))], stream=0)
-    with pytest.raises(F.FractalError):  # step-only flags are refused
-        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 1), stream=0)
+    with pytest.raises(F.FractalError):  # unknown flag bits are refused
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 8), stream=0)
+    with pytest.raises(F.FractalError):  # bad thread count
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 128, 2, 0), stream=0)
     F.batch_step([], stream=0)
     F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], stream=0)  # no steps: no-op
 
