@@ -45,7 +45,7 @@ ALPHA = 0.2
 BYTES_PER_CELL = {0: 2.0 * (4.0 / 3.0) ** 6, 1: 8.0 * (4.0 / 3.0) ** 4}
 WORKLOADS = {"k14": 14, "k16": 16}
 RULE_NAME = {0: "ca", 1: "heat"}
-KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernels.hip"]
+KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip"]
 
 
 def kernel_hash() -> str:
@@ -123,12 +123,25 @@ class Gasket:
         self.torch.cuda.empty_cache()
 
 
-def roofline(rule, cells, sec_per_launch, traffic=None, kernel=""):
+def steps_per_launch(tuning):
+    """2 for two-step (fused) launches, else 1."""
+    return 2 if len(tuning) > 3 and (tuning[3] & 8) else 1
+
+
+def roofline(rule, cells, sec_per_step, tuning, traffic=None, kernel=""):
+    """Roofline of one launch.  A launch reads and writes every member
+    segment once whether it advances one step or two (the intermediate step
+    of a fused launch stays in LDS), so its algorithmic bytes are the
+    per-cell figure times 3^k either way; its duration is the per-step time
+    times the steps it advances."""
+    spl = steps_per_launch(tuning)
     alg = BYTES_PER_CELL[rule] * cells
-    achieved = alg / sec_per_launch / 1e9
+    launch = sec_per_step * spl
+    achieved = alg / launch / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-            "alg_bytes_per_launch": alg, "avg_launch_us": sec_per_launch * 1e6}
+            "steps_per_launch": spl, "alg_bytes_per_launch": alg,
+            "avg_launch_us": launch * 1e6}
 
 
 def bb_leg(g, per_launch, nsteps):
@@ -136,8 +149,9 @@ def bb_leg(g, per_launch, nsteps):
     out = {}
     for rule in (0, 1):
         res = {}
-        for r in range(max(2, g.k - 15), 7):
-            tb = (r, 256 if (r >= 5 and rule == 1) or r >= 6 else 64, F.ORDER_NATURAL)
+        for r in range(max(2, g.k - 15), 8):
+            fused = (1 << r) * (1 if rule == 0 else 4) >= 16
+            tb = (r, 256 if r >= 4 else 64, F.ORDER_NATURAL, 11 if fused else 3)
             g.run(rule, 2, F.MAP_BB, tb)
             res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
         lam = per_launch[rule]
@@ -161,7 +175,7 @@ def k16_leg(F, torch, steps):
     for rule in (0, 1):
         g.run(rule, 4)
         sec = g.time(rule, steps)
-        rf = roofline(rule, g.cells, sec, read_traffic("k16", RULE_NAME[rule]),
+        rf = roofline(rule, g.cells, sec, g.tunings[rule], read_traffic("k16", RULE_NAME[rule]),
                       f"lambda_step_{RULE_NAME[rule]}")
         out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]),
                                 "cells_per_s": g.cells / sec, "roofline": rf}
@@ -169,7 +183,7 @@ def k16_leg(F, torch, steps):
     for rule in (0, 1):
         r = g.tunings[rule][0]
         for rr in sorted({r, 5}):
-            tb = (rr, 256 if rr >= 5 else 64, F.ORDER_NATURAL)
+            tb = (rr, 256, F.ORDER_NATURAL, 11)
             g.run(rule, 2, F.MAP_BB, tb)
             sec = g.time(rule, max(4, steps // 4), F.MAP_BB, tb)
             out[RULE_NAME[rule]][f"bb_r{rr}_us"] = sec * 1e6
@@ -354,8 +368,8 @@ def main() -> int:
     value = 2.0 * g.cells * K / (total_ms / 1e3)
     per_launch = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}
     dom = 1 if per_launch[1] >= per_launch[0] else 0
-    rf = roofline(dom, g.cells, per_launch[dom], read_traffic(args.workload, RULE_NAME[dom]),
-                  f"lambda_step_{RULE_NAME[dom]}")
+    rf = roofline(dom, g.cells, per_launch[dom], g.tunings[dom],
+                  read_traffic(args.workload, RULE_NAME[dom]), f"lambda_step_{RULE_NAME[dom]}")
 
     bb = None if args.no_bb else bb_leg(g, per_launch, max(10, min(K, 200)))
     k, cells, tunings = g.k, g.cells, dict(g.tunings)
@@ -394,7 +408,8 @@ def main() -> int:
         "roofline": rf,
         "per_rule": {RULE_NAME[r]: {"us_per_step": per_launch[r] * 1e6,
                                     "cells_per_s": cells / per_launch[r],
-                                    "alg_GBs": BYTES_PER_CELL[r] * cells / per_launch[r] / 1e9}
+                                    "steps_per_launch": steps_per_launch(tunings[r]),
+                                    "roofline": roofline(r, cells, per_launch[r], tunings[r])}
                      for r in (0, 1)},
         "bb": bb, "k16": k16, "batch": batch, "serve": serve,
         "cpu_baseline": cpu,

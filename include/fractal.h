@@ -73,12 +73,16 @@ extern "C" {
                                    member (their member-free chunks are read
                                    and written as 0) instead of 16-byte chunks */
 #define FRACTAL_FLAG_NT_STORE 2 /* non-temporal hint on output stores */
+#define FRACTAL_FLAG_FUSE2 8    /* two steps per launch: a two-cell halo is
+                                   staged and the intermediate step stays in
+                                   LDS, halving state traffic per step (tiles
+                                   whose rows span >= 16 bytes) */
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
                                      contiguous ranges of the tile list, instead
                                      of one workgroup per tile */
 
 typedef struct fractal_tuning {
-    int r;       /* log2 of the tile side rho, 0..6 (rho <= 64)            */
+    int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */
     int threads; /* threads per workgroup: 64 or 256                        */
     int order;   /* FRACTAL_ORDER_*                                         */
     int flags;   /* FRACTAL_FLAG_*                                          */
@@ -115,7 +119,8 @@ int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
  * workgroups with the identity map omega -> tile; a workgroup whose tile
  * holds no member exits at once.  Runs `steps` synchronous steps of `rule`
  * ping-ponging between d_buf0 (input of step 0) and d_buf1.
- * 0 <= k <= 16, 0 <= r <= min(k, 6) or FRACTAL_R_AUTO, alpha ignored for the
+ * 0 <= k <= 16, 0 <= r <= min(k, 7) with k - r <= 15, or FRACTAL_R_AUTO;
+ * alpha ignored for the
  * automaton and 0 < alpha <= 0.25 for heat, steps >= 0. */
 int fractal_bb_step(int k, int r, int rule, float alpha, void *d_buf0,
                     void *d_buf1, int steps, void *stream);
@@ -175,8 +180,9 @@ typedef struct fractal_instance {
  * the graph is launched on `stream`.  Instances with fewer steps drop out of
  * later launches.  `tuning` may be NULL (per-level defaults / cached tuning);
  * otherwise tuning->r applies to every instance (clamped per level), or
- * FRACTAL_R_AUTO keeps the per-level defaults, and only
- * FRACTAL_FLAG_PERSISTENT is accepted in tuning->flags.
+ * FRACTAL_R_AUTO keeps the per-level defaults, tuning->threads 0 keeps the
+ * default thread count, and tuning->flags applies to every instance
+ * (FRACTAL_FLAG_FUSE2 falls back to single steps where tiles are too narrow).
  * Results are bit-identical to one fractal_lambda_step call per instance.
  * The call allocates a device table (freed when the graph has run) and
  * returns after enqueuing; it synchronises nothing else.  count <= 65536. */

@@ -26,7 +26,8 @@ HIP_FLAGS = [
     "-fno-gpu-flush-denormals-to-zero", "-ffp-contract=fast-honor-pragmas",
     "-Wall", "-Wno-unused-function",
 ]
-SOURCES = ["api.cpp", "step_kernels.hip", "seed.hip", "batch.hip", "serve.cpp"]
+SOURCES = ["api.cpp", "step_kernels.hip", "step_lambda.hip", "step_bb.hip", "step_mfma.hip",
+           "seed.hip", "batch.hip", "serve.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -101,15 +101,18 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured at level 16 on MI355X (64 x 64 automaton tiles moving
-// whole segments; 32 x 32 heat tiles moving whole segments with
-// non-temporal stores).
+// launches measured at level 16 on MI355X (128 x 128 automaton tiles, 64 x 64
+// heat tiles, 256 threads, omega in launch order, whole 64-byte segments,
+// non-temporal stores, two steps per launch).
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 6 : 5);
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 7 : 6);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
-    t.flags = rule == FRACTAL_RULE_CA ? FRACTAL_FLAG_SEGMENTS
-                                      : (FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE);
+    t.threads = r >= 3 ? 256 : 64;
+    t.order = FRACTAL_ORDER_NATURAL;
+    t.flags = FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE;
+    if ((1 << r) * (int)cell_bytes(rule) >= 16)
+        t.flags |= FRACTAL_FLAG_FUSE2;
     return t;
 }
 
@@ -145,9 +148,12 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "threads=%d must be 64 or 256", t->threads);
     if (t->order < FRACTAL_ORDER_NATURAL || t->order > FRACTAL_ORDER_CURVE_XCD)
         return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
-    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE))
+    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
-    (void)rule;
+    if ((t->flags & FRACTAL_FLAG_FUSE2) && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
+        return set_error(FRACTAL_E_INVAL, "two-step launches need tile rows of >= 16 bytes");
+    if (t->threads == 256 && t->r < 3)
+        return set_error(FRACTAL_E_INVAL, "256 threads need tiles of side >= 8");
     return FRACTAL_OK;
 }
 
@@ -298,7 +304,7 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         return rc;
     }
     // Few-step timings; enough launches that per-launch gaps are included.
-    const int reps = k >= 15 ? 4 : (k >= 12 ? 16 : 64);
+    const int reps = k >= 15 ? 8 : (k >= 12 ? 16 : 64); // multiples of 4 (fused pairs)
     fractal_tuning best{};
     float best_ms = 1e30f;
     std::vector<fractal_tuning> cands;
@@ -309,18 +315,20 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         if (row_bytes < 16 && k >= 8)
             continue; // tiles below one 16-byte chunk per row are never faster here
         for (int th : {64, 256}) {
-            if (th == 256 && default_threads(rule, r) == 64 && r < 5)
+            if (th == 256 && r < 4)
                 continue;
             for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE_XCD})
-                for (int fl = 0; fl < 4; ++fl) {
+                for (int fl : {0, 1, 3, 9, 11}) {
                     fractal_tuning t{r, th, order, fl};
+                    if ((fl & FRACTAL_FLAG_FUSE2) && row_bytes < 16)
+                        continue;
                     cands.push_back(t);
                 }
         }
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)
-        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 2, t, s);
+        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 4, t, s);
         if (!rc)
             rc = hip_error(hipEventRecord(e0, s), "event record");
         if (!rc)

@@ -4,9 +4,9 @@
 // level r, threads, step flags).  The tiles of a class form one work list:
 // instance j owns tile ids [tile_begin_j, tile_begin_j + 3^(k_j - r)); a tile
 // id is turned into (instance, local omega) with the per-instance offset
-// table and then into a tile by that instance's lambda.  Each step is one
-// launch per class; the launches of a fractal_batch_step call are captured
-// once into a HIP graph.
+// table and then into a tile by that instance's lambda.  Each launch slot is
+// one launch per class (one or two steps each); the launches of a
+// fractal_batch_step call are captured once into a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,12 +38,15 @@ __device__ __forceinline__ int find_instance(const BatchEntry *__restrict__ tabl
     return lo;
 }
 
+// `slot` is the index of this launch within the item's two-step launches
+// (fused kernels) or within its single steps; every launch flips the buffers.
 template <int RULE, int R, int NT, int FL>
 __device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, uint32_t L,
-                                           int local_step)
+                                           int slot)
 {
     const TileXY t = lambda_wave_curve(L, e.k - R);
-    const bool odd = ((e.phase + local_step) & 1) != 0;
+    const int flips = (FL & TILE_FUSE2) ? slot : e.fused + slot;
+    const bool odd = ((e.phase + flips) & 1) != 0;
     StepParams p;
     p.src = odd ? e.buf1 : e.buf0;
     p.dst = odd ? e.buf0 : e.buf1;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(NT) void batch_tile_kernel(const BatchEntry *__rest
                                                         int count, uint32_t total,
                                                         int local_step)
 {
-    __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
+    __shared__ __align__(16) uint8_t lds[tile_lds_bytes<RULE, R, FL>()];
     const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (lin >= total)
         return;
@@ -76,7 +79,7 @@ template <int RULE, int R, int NT, int FL>
 __global__ __launch_bounds__(NT) void batch_persistent_kernel(
     const BatchEntry *__restrict__ table, int count, uint64_t total, int local_step)
 {
-    __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
+    __shared__ __align__(16) uint8_t lds[tile_lds_bytes<RULE, R, FL>()];
     const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
     const uint64_t w0 = (uint64_t)blockIdx.x * per;
     const uint64_t w1 = w0 + per < total ? w0 + per : total;
@@ -101,11 +104,15 @@ typedef void (*PersistFn)(const BatchEntry *, int, uint64_t, int);
 template <int RULE, int NT, int FL>
 static void pick_r(int r, TileFn *tf, PersistFn *pf)
 {
+    *tf = nullptr;
+    *pf = nullptr;
     switch (r) {
 #define FRACTAL_BATCH_CASE(RR)                                                                     \
     case RR:                                                                                       \
-        *tf = batch_tile_kernel<RULE, RR, NT, FL>;                                                 \
-        *pf = batch_persistent_kernel<RULE, RR, NT, FL>;                                           \
+        if constexpr (!((FL & TILE_FUSE2) && !Geom<RULE, RR>::FUSABLE) && !(NT == 256 && RR < 3)) { \
+            *tf = batch_tile_kernel<RULE, RR, NT, FL>;                                             \
+            *pf = batch_persistent_kernel<RULE, RR, NT, FL>;                                       \
+        }                                                                                          \
         break;
         FRACTAL_BATCH_CASE(0)
         FRACTAL_BATCH_CASE(1)
@@ -114,10 +121,9 @@ static void pick_r(int r, TileFn *tf, PersistFn *pf)
         FRACTAL_BATCH_CASE(4)
         FRACTAL_BATCH_CASE(5)
         FRACTAL_BATCH_CASE(6)
+        FRACTAL_BATCH_CASE(7)
 #undef FRACTAL_BATCH_CASE
-    default:
-        *tf = nullptr;
-        *pf = nullptr;
+    default: break;
     }
 }
 
@@ -133,11 +139,18 @@ static void pick_threads(int r, int threads, TileFn *tf, PersistFn *pf)
 template <int RULE>
 static void pick_flags(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
 {
-    switch (flags & 3) {
+    switch (flags) {
     case 0: pick_threads<RULE, 0>(r, threads, tf, pf); break;
     case 1: pick_threads<RULE, 1>(r, threads, tf, pf); break;
     case 2: pick_threads<RULE, 2>(r, threads, tf, pf); break;
-    default: pick_threads<RULE, 3>(r, threads, tf, pf); break;
+    case 3: pick_threads<RULE, 3>(r, threads, tf, pf); break;
+    case 8: pick_threads<RULE, 8>(r, threads, tf, pf); break;
+    case 9: pick_threads<RULE, 9>(r, threads, tf, pf); break;
+    case 10: pick_threads<RULE, 10>(r, threads, tf, pf); break;
+    case 11: pick_threads<RULE, 11>(r, threads, tf, pf); break;
+    default:
+        *tf = nullptr;
+        *pf = nullptr;
     }
 }
 
@@ -161,14 +174,19 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
             t = tuning_for_r(MAP_LAMBDA, k, rule, forced->r);
         if (forced->threads == 64 || forced->threads == 256)
             t.threads = forced->threads;
-        t.flags = forced->flags & (FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE);
+        t.flags = forced->flags;
     }
+    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2;
     if (t.r > k)
         t.r = k;
     if (t.r > kMaxR)
         t.r = kMaxR;
     if (k - t.r > kMaxBlockLevel)
         t.r = k - kMaxBlockLevel;
+    if (t.threads == 256 && t.r < 3)
+        t.threads = 64;
+    if ((t.flags & FRACTAL_FLAG_FUSE2) && ((1 << t.r) * (int)cell_bytes(rule)) < 16)
+        t.flags &= ~FRACTAL_FLAG_FUSE2; // two-step launches need 16-byte rows
     t.order = FRACTAL_ORDER_CURVE_XCD;
     return t;
 }
@@ -176,64 +194,78 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
 void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
 {
     classes_.clear();
-    max_steps_ = 0;
+    slots_ = 0;
     std::map<std::tuple<int, int, int, int>, std::vector<size_t>> groups;
     for (size_t i = 0; i < items.size(); ++i) {
         const BatchItem &it = items[i];
-        groups[std::make_tuple(it.rule, it.tuning.r, it.tuning.threads, it.tuning.flags & 3)]
+        groups[std::make_tuple(it.rule, it.tuning.r, it.tuning.threads, it.tuning.flags)]
             .push_back(i);
-        max_steps_ = std::max(max_steps_, it.steps);
     }
     size_t at = 0;
     for (auto &g : groups) {
-        std::vector<size_t> &ids = g.second;
-        std::stable_sort(ids.begin(), ids.end(),
-                         [&](size_t a, size_t b) { return items[a].steps > items[b].steps; });
         Class c;
         std::tie(c.rule, c.r, c.threads, c.flags) = g.first;
-        c.first = at;
-        uint64_t acc = 0;
-        for (size_t i : ids) {
-            const BatchItem &it = items[i];
-            BatchEntry &e = host[at++];
-            e.tile_begin = acc;
-            e.buf0 = it.buf0;
-            e.buf1 = it.buf1;
-            e.k = it.k;
-            e.r = c.r;
-            e.rule = it.rule;
-            e.phase = it.phase;
-            e.alpha = it.alpha;
-            e.pad = 0;
-            c.steps.push_back(it.steps);
-            c.prefix.push_back(acc);
-            acc += pow3_u64(it.k - c.r);
-        }
-        c.prefix.push_back(acc);
+        const bool fuse = (c.flags & FRACTAL_FLAG_FUSE2) != 0;
+        auto fused_of = [&](size_t i) { return fuse ? 2 * (items[i].steps / 4) : 0; };
+        auto single_of = [&](size_t i) { return items[i].steps - 2 * fused_of(i); };
+        auto emit = [&](List &list, std::vector<size_t> ids, auto count_of) {
+            std::stable_sort(ids.begin(), ids.end(),
+                             [&](size_t a, size_t b) { return count_of(a) > count_of(b); });
+            list.first = at;
+            uint64_t acc = 0;
+            for (size_t i : ids) {
+                if (count_of(i) <= 0)
+                    break;
+                const BatchItem &it = items[i];
+                BatchEntry &e = host[at++];
+                e.tile_begin = acc;
+                e.buf0 = it.buf0;
+                e.buf1 = it.buf1;
+                e.k = it.k;
+                e.r = c.r;
+                e.rule = it.rule;
+                e.phase = it.phase & 1;
+                e.alpha = it.alpha;
+                e.fused = fused_of(i);
+                list.count.push_back(count_of(i));
+                list.prefix.push_back(acc);
+                acc += pow3_u64(it.k - c.r);
+            }
+            list.prefix.push_back(acc);
+        };
+        emit(c.fused, g.second, fused_of);
+        emit(c.single, g.second, single_of);
+        c.fmax = c.fused.count.empty() ? 0 : c.fused.count[0];
+        const int smax = c.single.count.empty() ? 0 : c.single.count[0];
+        slots_ = std::max(slots_, c.fmax + smax);
         classes_.push_back(std::move(c));
     }
     entries_ = at;
 }
 
-int BatchPlan::launch_step(const BatchEntry *d_table, int j, bool persistent, hipStream_t s) const
+int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hipStream_t s) const
 {
     for (const Class &c : classes_) {
-        size_t active = c.steps.size();
-        while (active > 0 && c.steps[active - 1] <= j)
+        const bool in_fused = t < c.fmax;
+        const List &list = in_fused ? c.fused : c.single;
+        const int j = in_fused ? t : t - c.fmax; // launch index within the list
+        size_t active = list.count.size();
+        while (active > 0 && list.count[active - 1] <= j)
             --active;
         if (active == 0)
             continue;
-        const uint64_t total = c.prefix[active];
+        const uint64_t total = list.prefix[active];
+        const int flags = in_fused ? c.flags : (c.flags & ~FRACTAL_FLAG_FUSE2);
         TileFn tf = nullptr;
         PersistFn pf = nullptr;
         if (c.rule == FRACTAL_RULE_CA)
-            pick_flags<RULE_CA>(c.r, c.threads, c.flags, &tf, &pf);
+            pick_flags<RULE_CA>(c.r, c.threads, flags, &tf, &pf);
         else
-            pick_flags<RULE_HEAT>(c.r, c.threads, c.flags, &tf, &pf);
+            pick_flags<RULE_HEAT>(c.r, c.threads, flags, &tf, &pf);
         if (!tf || !pf)
-            return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d", c.r,
-                             c.threads);
-        const BatchEntry *tab = d_table + c.first;
+            return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d flags=%d", c.r,
+                             c.threads, flags);
+        const BatchEntry *tab = d_table + list.first;
         if (!persistent && total < 0x7FFFFFFFull) {
             const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
             const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
@@ -297,7 +329,8 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
             return set_error(FRACTAL_E_INVAL, "tuning threads=%d (0, 64 or 256)",
                              tuning->threads);
         if (tuning->flags &
-            ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE))
+            ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE |
+              FRACTAL_FLAG_FUSE2))
             return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
     }
     // validate every instance and pick its tile launch
@@ -333,7 +366,8 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     reap_pending();
     hipStream_t s = static_cast<hipStream_t>(stream);
     BatchEntry *host = nullptr;
-    int rc = hip_error(hipHostMalloc((void **)&host, sizeof(BatchEntry) * count), "pinned table");
+    const size_t cap = 2 * (size_t)count; // an item can sit in both lists of its class
+    int rc = hip_error(hipHostMalloc((void **)&host, sizeof(BatchEntry) * cap), "pinned table");
     if (rc)
         return rc;
     BatchPlan plan;
@@ -366,10 +400,10 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         (void)hipHostFree(host);
         return code;
     };
-    if ((rc = hip_error(hipMallocAsync((void **)&d_table, sizeof(BatchEntry) * count, s),
+    if ((rc = hip_error(hipMallocAsync((void **)&d_table, sizeof(BatchEntry) * cap, s),
                         "device table")))
         return fail(rc);
-    if ((rc = hip_error(hipMemcpyAsync(d_table, host, sizeof(BatchEntry) * count,
+    if ((rc = hip_error(hipMemcpyAsync(d_table, host, sizeof(BatchEntry) * plan.entries(),
                                        hipMemcpyHostToDevice, s),
                         "table copy")))
         return fail(rc);
@@ -379,8 +413,8 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     if ((rc = hip_error(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal),
                         "begin capture")))
         return fail(rc);
-    for (int t = 0; t < plan.max_steps(); ++t)
-        if ((rc = plan.launch_step(d_table, t, persistent, cs)))
+    for (int t = 0; t < plan.slots(); ++t)
+        if ((rc = plan.launch_slot(d_table, t, persistent, cs)))
             return fail(rc);
     if ((rc = hip_error(hipStreamEndCapture(cs, &graph), "end capture")))
         return fail(rc);

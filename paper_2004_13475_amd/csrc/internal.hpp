@@ -16,7 +16,7 @@ enum : int { MAP_LAMBDA = 0, MAP_BB = 1, MAP_MFMA = 2 };
 
 constexpr int kMaxStepLevel = 16; // k for step calls (64-bit offsets inside)
 constexpr int kMaxBlockLevel = 15; // k - r for step calls (grid limits)
-constexpr int kMaxR = 6;           // rho <= 64
+constexpr int kMaxR = 7;           // rho <= 128
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator dies, 32 CUs each
 
 // Error reporting (thread-local message).
@@ -45,6 +45,22 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t);
 fractal_tuning default_tuning(int k, int rule);
 fractal_tuning tuning_for_r(int map, int k, int rule, int r);
 
+// Arguments of one step-kernel launch.
+struct StepLaunchArgs {
+    const uint8_t *src; // state read by this launch
+    uint8_t *dst;       // state written by this launch
+    int k;              // level
+    float alpha;        // heat coefficient
+    int rb;             // block-space level k - r
+    int order;          // FRACTAL_ORDER_*
+    uint32_t total;     // workgroups in the grid
+};
+typedef void (*StepFn)(StepLaunchArgs);
+StepFn pick_step(int map, int rule, int r, int threads, int flags);
+StepFn pick_step_lambda(int rule, int r, int threads, int flags);
+StepFn pick_step_bb(int rule, int r, int threads, int flags);
+StepFn pick_step_mfma(int rule, int r, int threads, int flags);
+
 // Launch `steps` step kernels (validated arguments).
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s);
@@ -62,49 +78,58 @@ int launch_checksum(int k, int rule, const void *d_buf,
 
 // Batched steps: device table entry per instance.
 struct BatchEntry {
-    uint64_t tile_begin; // prefix of 3^(k_j - r) over earlier entries of the class
+    uint64_t tile_begin; // prefix of 3^(k_j - r) over earlier entries of the list
     uint8_t *buf0;
     uint8_t *buf1;
     int32_t k;
     int32_t r;
     int32_t rule;
-    int32_t phase; // steps already done by this instance (parity source)
+    int32_t phase; // buffer holding the state at the start (its parity)
     float alpha;
-    int32_t pad;
+    int32_t fused; // two-step launches this instance makes in this sequence
 };
 static_assert(sizeof(BatchEntry) == 48, "BatchEntry layout");
 
 // One gasket advanced by a batched launch sequence.
 struct BatchItem {
     int k, rule;
-    int steps; // steps to run in this sequence (local steps 0..steps-1)
-    int phase; // steps done before (input is buf[phase & 1])
+    int steps; // steps to run in this sequence
+    int phase; // input is buf[phase & 1]
     float alpha;
     uint8_t *buf0, *buf1;
     fractal_tuning tuning; // tile launch (r, threads, flags) for this item
 };
 
-// Instances grouped by launch class (rule, r, threads, step flags); each
-// class is a contiguous run of table entries sorted by steps (descending),
-// so the items still running at local step j form a prefix of the class.
+// Instances grouped by launch class (rule, r, threads, step flags).  A class
+// with two-step launches gives each item f = 2 floor(steps / 4) of them (an
+// even number, so the result lands in buf[steps & 1]) and then steps - 2f
+// single steps.  Each class keeps a list for its two-step launches (items
+// sorted by f) and one for its single steps (sorted by count), so the items
+// taking part in any launch form a prefix of the list.  Launch slot t runs,
+// per class, its two-step launch t or single-step launch t - F (F = the
+// class's largest f).
 class BatchPlan {
   public:
-    // Fills `host` (capacity >= items.size()) and records the classes.
+    // Fills `host` (capacity >= 2 * items.size()) and records the classes.
     void build(const std::vector<BatchItem> &items, BatchEntry *host);
-    // Launch local step j of every class whose prefix is non-empty.
-    int launch_step(const BatchEntry *d_table, int j, bool persistent, hipStream_t s) const;
-    int max_steps() const { return max_steps_; }
+    // Launch slot t of every class that has work in it.
+    int launch_slot(const BatchEntry *d_table, int t, bool persistent, hipStream_t s) const;
+    int slots() const { return slots_; }
     size_t entries() const { return entries_; }
 
   private:
+    struct List {
+        size_t first = 0;
+        std::vector<int> count;       // per entry: launches it takes part in (descending)
+        std::vector<uint64_t> prefix; // tile prefix, size count.size() + 1
+    };
     struct Class {
         int rule, r, threads, flags;
-        size_t first;
-        std::vector<int> steps;       // per entry, descending
-        std::vector<uint64_t> prefix; // tile prefix, size steps.size() + 1
+        List fused, single;
+        int fmax = 0;
     };
     std::vector<Class> classes_;
-    int max_steps_ = 0;
+    int slots_ = 0;
     size_t entries_ = 0;
 };
 

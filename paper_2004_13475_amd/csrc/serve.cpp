@@ -81,7 +81,7 @@ class Server {
         device_ = dev;
         // header of the arena: two device tables (double-buffered) and the
         // per-slot checksums; the rest holds request states
-        const size_t table_bytes = sizeof(BatchEntry) * (size_t)(max_slots_ + 1);
+        const size_t table_bytes = sizeof(BatchEntry) * 2 * (size_t)(max_slots_ + 1);
         table_off_[0] = 0;
         table_off_[1] = align(table_bytes);
         sums_off_ = table_off_[1] + align(table_bytes);
@@ -299,8 +299,8 @@ class Server {
                 int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * plan.entries(),
                                                   hipMemcpyHostToDevice, stream_),
                                    "table upload");
-                for (int j = 0; j < c && !rc; ++j)
-                    rc = plan.launch_step(dt, j, false, stream_);
+                for (int j = 0; j < plan.slots() && !rc; ++j)
+                    rc = plan.launch_slot(dt, j, false, stream_);
                 if (!rc)
                     rc = hip_error(hipEventRecord(table_ev_[parity], stream_), "event record");
                 parity ^= 1;

@@ -1,9 +1,8 @@
-// step_kernels.hip -- lambda(omega) map kernels and the lambda / bounding-box
-// step kernels for gfx950, with their host launchers.
+// step_kernels.hip -- lambda(omega) map kernels and the host launcher of the
+// lambda / bounding-box / matrix-core step kernels.
 #include <hip/hip_runtime.h>
 
 #include "device_map.hpp"
-#include "device_tile.hpp"
 #include "internal.hpp"
 
 namespace fractal {
@@ -49,130 +48,52 @@ int launch_lambda_map(int k, int r, uint32_t *d_xy, bool mfma, hipStream_t s)
     return hip_error(hipGetLastError(), "lambda map launch");
 }
 
-// ------------------------------------------------------------------ steps
-struct LaunchArgs {
-    StepParams p;
-    int rb;         // block-space level k - r
-    int order;      // FRACTAL_ORDER_*
-    uint32_t total; // workgroups in the grid
-};
-
-// One workgroup per tile.  lambda maps: the grid is the compact 3^ceil(rb/2)
-// x 3^floor(rb/2) orthotope.  Bounding box: the grid is n_b x n_b and a
-// workgroup on an empty tile returns before touching memory.
-template <int RULE, int R, int NT, int MAP, int FL>
-__global__ __launch_bounds__(NT) void step_kernel(LaunchArgs a)
-{
-    __shared__ __align__(16) uint8_t lds[Geom<RULE, R>::LDS_BYTES];
-    const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
-    TileXY t;
-    if constexpr (MAP == MAP_BB) {
-        const uint32_t id = a.order != FRACTAL_ORDER_NATURAL ? xcd_chunk(lin, a.total) : lin;
-        t.x = id & ((1u << a.rb) - 1u);
-        t.y = id >> a.rb;
-        if ((t.x & t.y) != 0u)
-            return; // empty block: nothing of the gasket here
-    } else if (a.order == FRACTAL_ORDER_NATURAL) {
-        const uint32_t wx = blockIdx.x, wy = blockIdx.y;
-        if constexpr (MAP == MAP_MFMA)
-            t = lambda_mfma([&](uint32_t mu) { return beta_of_omega(wx, wy, mu); }, a.rb);
-        else
-            t = lambda_wave(wx, wy, a.rb);
-    } else {
-        const uint32_t L = a.order == FRACTAL_ORDER_CURVE_XCD ? xcd_chunk(lin, a.total) : lin;
-        if constexpr (MAP == MAP_MFMA)
-            t = lambda_mfma(
-                [&](uint32_t mu) {
-                    const uint32_t q = L / pow3_u32(mu - 1u);
-                    return q - 3u * (q / 3u);
-                },
-                a.rb);
-        else
-            t = lambda_wave_curve(L, a.rb);
-    }
-    tile_step<RULE, R, NT, FL>(lds, a.p, t.x << R, t.y << R);
-}
-
-typedef void (*StepFn)(LaunchArgs);
-
-template <int MAP, int RULE, int NT, int FL>
-static StepFn pick_r(int r)
-{
-    switch (r) {
-    case 0: return step_kernel<RULE, 0, NT, MAP, FL>;
-    case 1: return step_kernel<RULE, 1, NT, MAP, FL>;
-    case 2: return step_kernel<RULE, 2, NT, MAP, FL>;
-    case 3: return step_kernel<RULE, 3, NT, MAP, FL>;
-    case 4: return step_kernel<RULE, 4, NT, MAP, FL>;
-    case 5: return step_kernel<RULE, 5, NT, MAP, FL>;
-    case 6: return step_kernel<RULE, 6, NT, MAP, FL>;
-    default: return nullptr;
-    }
-}
-
-template <int MAP, int RULE, int FL>
-static StepFn pick_threads(int r, int threads)
-{
-    return threads == 256 ? pick_r<MAP, RULE, 256, FL>(r) : pick_r<MAP, RULE, 64, FL>(r);
-}
-
-template <int MAP, int FL>
-static StepFn pick_rule(int rule, int r, int threads)
-{
-    return rule == FRACTAL_RULE_CA ? pick_threads<MAP, RULE_CA, FL>(r, threads)
-                                   : pick_threads<MAP, RULE_HEAT, FL>(r, threads);
-}
-
-template <int MAP>
-static StepFn pick_flags(int rule, int r, int threads, int flags)
-{
-    switch (flags & 3) {
-    case 0: return pick_rule<MAP, 0>(rule, r, threads);
-    case 1: return pick_rule<MAP, 1>(rule, r, threads);
-    case 2: return pick_rule<MAP, 2>(rule, r, threads);
-    default: return pick_rule<MAP, 3>(rule, r, threads);
-    }
-}
-
-static StepFn pick(int map, int rule, int r, int threads, int flags)
-{
-    switch (map) {
-    case MAP_LAMBDA: return pick_flags<MAP_LAMBDA>(rule, r, threads, flags);
-    case MAP_BB: return pick_flags<MAP_BB>(rule, r, threads, flags);
-    case MAP_MFMA: return pick_flags<MAP_MFMA>(rule, r, threads, flags);
-    default: return nullptr;
-    }
-}
-
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s)
 {
-    StepFn fn = pick(map, rule, t.r, t.threads, t.flags);
-    if (!fn)
-        return set_error(FRACTAL_E_INVAL, "no kernel for map %d rule %d r %d threads %d",
-                         map, rule, t.r, t.threads);
+    // Two-step launches come in pairs so that the result still lands in
+    // buf[steps & 1]; the remaining 0..3 steps run one step per launch.
+    const bool fuse = (t.flags & FRACTAL_FLAG_FUSE2) != 0;
+    const int fused = fuse ? 2 * (steps / 4) : 0;
+    StepFn fn1 = pick_step(map, rule, t.r, t.threads, t.flags & ~FRACTAL_FLAG_FUSE2);
+    StepFn fn2 = fuse ? pick_step(map, rule, t.r, t.threads, t.flags) : nullptr;
+    if (!fn1 || (fuse && !fn2))
+        return set_error(FRACTAL_E_INVAL, "no kernel for map %d rule %d r %d threads %d flags %d",
+                         map, rule, t.r, t.threads, t.flags);
     const int rb = k - t.r;
     dim3 grid;
     if (map == MAP_BB)
         grid = dim3(1u << rb, 1u << rb);
     else
         grid = dim3((unsigned)pow3_u64((rb + 1) / 2), (unsigned)pow3_u64(rb / 2));
-    LaunchArgs a;
-    a.p.k = k;
-    a.p.alpha = alpha;
+    StepLaunchArgs a;
+    a.k = k;
+    a.alpha = alpha;
     a.rb = rb;
     a.order = t.order;
     a.total = grid.x * grid.y;
     uint8_t *bufs[2] = {static_cast<uint8_t *>(b0), static_cast<uint8_t *>(b1)};
-    for (int i = 0; i < steps; ++i) {
-        a.p.src = bufs[i & 1];
-        a.p.dst = bufs[(i + 1) & 1];
+    const int launches = fused + (steps - 2 * fused);
+    for (int i = 0; i < launches; ++i) {
+        a.src = bufs[i & 1];
+        a.dst = bufs[(i + 1) & 1];
         void *args[] = {&a};
-        hipError_t e = hipLaunchKernel((const void *)fn, grid, dim3(t.threads), args, 0, s);
+        hipError_t e = hipLaunchKernel((const void *)(i < fused ? fn2 : fn1), grid,
+                                       dim3(t.threads), args, 0, s);
         if (e != hipSuccess)
             return hip_error(e, "step kernel launch");
     }
     return hip_error(hipGetLastError(), "step kernel launch");
+}
+
+StepFn pick_step(int map, int rule, int r, int threads, int flags)
+{
+    switch (map) {
+    case MAP_LAMBDA: return pick_step_lambda(rule, r, threads, flags);
+    case MAP_BB: return pick_step_bb(rule, r, threads, flags);
+    case MAP_MFMA: return pick_step_mfma(rule, r, threads, flags);
+    default: return nullptr;
+    }
 }
 
 } // namespace fractal

@@ -98,8 +98,8 @@ def _run(map_, k, r, rule, b0, b1, steps, flags=None):
 def test_steps_small_levels_every_r(rule, map_, flags):
     """Every tile size and launch flag on small gaskets, checked after each
     of 6 steps."""
-    for k in range(0, 8):
-        for r in range(0, min(k, 6) + 1):
+    for k in range(0, 9):
+        for r in range(0, min(k, 7) + 1):
             init = fi.window_values(k, rule, 100 + k)
             b0 = to_device(init)
             b1 = zeros_state(k, rule)
@@ -115,7 +115,7 @@ def test_steps_small_levels_every_r(rule, map_, flags):
 
 
 @pytest.mark.parametrize("rule", RULES)
-@pytest.mark.parametrize("r", [3, 4, 5, 6])
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
 def test_steps_k10_checkpoints(rule, r):
     """Level 10 (n = 1024, 59049 cells): every step up to 32, then 100, for
     lambda and bounding box, against the whole-array oracle."""
@@ -145,7 +145,8 @@ def test_lambda_bb_mfma_bit_identical_k12(rule):
     outs = []
     for m in MAPS:
         for (r, th, order, fl) in [(3, 64, 0, 0), (4, 64, 2, 1), (5, 256, 1, 2), (6, 256, 2, 3),
-                                   (5, 64, 0, 1), (2, 64, 2, 3), (1, 64, 0, 1)]:
+                                   (5, 64, 0, 1), (2, 64, 2, 3), (1, 64, 0, 1), (7, 256, 0, 3),
+                                   (7, 64, 2, 1)]:
             b0, b1 = to_device(init), zeros_state(k, rule)
             F.step_tuned(m, k, rule, ALPHA, b0, b1, steps, r, th, order, fl)
             _sync()
@@ -155,6 +156,66 @@ def test_lambda_bb_mfma_bit_identical_k12(rule):
         assert np.array_equal(o.view(np.uint8), base.view(np.uint8)), f"{cfg} differs"
     ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), steps)
     assert_match(k, rule, base, ref, "k12")
+    del torch
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("map_", MAPS)
+def test_fused_two_step_launches(rule, map_):
+    """Two steps per launch (two-cell halo, intermediate step in LDS) give
+    the same bits as one step per launch, for every fusable tile size and
+    step counts that exercise the paired launches and the 0..3 single-step
+    tail; small levels also against the oracle."""
+    torch = torch_dev()
+    cell = 1 if rule == fi.RULE_CA else 4
+    for k in (5, 8, 11):
+        init = fi.window_values(k, rule, 60 + k)
+        for r in range(0, min(k, 7) + 1):
+            if (1 << r) * cell < 16 or k - r > 15:
+                continue
+            th = 256 if r >= 4 else 64
+            for steps in (1, 4, 5, 8, 11):
+                for fl in (9, 11):
+                    a0, a1 = to_device(init), zeros_state(k, rule)
+                    F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, th, 2, fl)
+                    b0, b1 = to_device(init), zeros_state(k, rule)
+                    F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, th, 2, fl & ~8)
+                    _sync()
+                    fa = a0 if steps % 2 == 0 else a1
+                    fb = b0 if steps % 2 == 0 else b1
+                    assert torch.equal(fa.view(torch.uint8), fb.view(torch.uint8)), \
+                        (k, r, steps, fl)
+                    if k <= 8 and fl == 11:
+                        ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64),
+                                           steps)
+                        assert_match(k, rule, fa.cpu().numpy(), ref, f"fused k={k} r={r} t={steps}")
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_fused_full_size_k16_sampled(rule):
+    """Level 16 with two-step launches, 200 steps, sampled against the
+    oracle's light-cone windows."""
+    k = 16
+    n = 1 << k
+    r = 7 if rule == fi.RULE_CA else 6
+    torch = torch_dev()
+    b0, b1 = zeros_state(k, rule), zeros_state(k, rule)
+    F.seed_fill(k, rule, 3, b0)
+    boxes = [(0, 0, 32, 32), (n - 32, 0, 32, 32), (30000, 20000, 32, 32)]
+    plans = []
+    for (cx, cy, w, h) in boxes:
+        x0, y0, ww, hh = window_plan(k, 200, w, h, cx, cy)
+        win = fi.window_values(k, rule, 3, x0, y0, ww, hh)
+        plans.append(((x0, y0, ww, hh), win if rule == 0 else win.astype(np.float64)))
+    F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, 200, r, 256, 0, 11)
+    _sync()
+    for (x0, y0, ww, hh), state in plans:
+        ref = oracle_steps(k, rule, state, 200, x0, y0)
+        rs, cs = oracle.valid_interior(k, x0, y0, ww, hh, 200)
+        ref = ref[rs, cs]
+        gy0, gx0 = y0 + rs.start, x0 + cs.start
+        got = b0[gy0:gy0 + ref.shape[0], gx0:gx0 + ref.shape[1]].cpu().numpy()
+        assert_match(k, rule, got, ref, f"fused k16 box=({x0},{y0})")
     del torch
 
 

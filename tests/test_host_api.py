@@ -41,7 +41,7 @@ def test_grid_dims_match_lemma2():
 
 @pytest.mark.parametrize("args,frag", [
     ((17, 4, 0, 0.2, FAKE0, FAKE1, 1), "level"),
-    ((10, 7, 0, 0.2, FAKE0, FAKE1, 1), "tile level"),
+    ((10, 8, 0, 0.2, FAKE0, FAKE1, 1), "tile level"),
     ((16, 0, 0, 0.2, FAKE0, FAKE1, 1), "block level"),
     ((10, 4, 2, 0.2, FAKE0, FAKE1, 1), "rule"),
     ((10, 4, 1, 0.3, FAKE0, FAKE1, 1), "alpha"),
@@ -77,10 +77,10 @@ def test_tuning_defaults_and_validation():
     for k in range(0, 17):
         for rule in (0, 1):
             r, th, order, flags = F.get_tuning(k, rule)
-            assert 0 <= r <= min(k, 6) and k - r <= 15
-            assert th in (64, 256) and order in (0, 1, 2) and flags in (0, 1, 2, 3)
+            assert 0 <= r <= min(k, 7) and k - r <= 15
+            assert th in (64, 256) and order in (0, 1, 2) and flags in (0, 1, 2, 3, 9, 10, 11)
     with pytest.raises(F.FractalError):
-        F.set_tuning(10, 0, 7, 64, 0)
+        F.set_tuning(10, 0, 8, 64, 0)
     with pytest.raises(F.FractalError):
         F.set_tuning(10, 0, 4, 128, 0)
     with pytest.raises(F.FractalError):
