@@ -124,8 +124,9 @@ class Gasket:
 
 
 def steps_per_launch(tuning):
-    """2 for two-step (fused) launches, else 1."""
-    return 2 if len(tuning) > 3 and (tuning[3] & 8) else 1
+    """Steps one launch advances: 4 or 2 for fused launches, else 1."""
+    fl = tuning[3] if len(tuning) > 3 else 0
+    return 4 if fl & 16 else (2 if fl & 8 else 1)
 
 
 def roofline(rule, cells, sec_per_step, tuning, traffic=None, kernel=""):
@@ -151,7 +152,7 @@ def bb_leg(g, per_launch, nsteps):
         res = {}
         for r in range(max(2, g.k - 15), 8):
             fused = (1 << r) * (1 if rule == 0 else 4) >= 16
-            tb = (r, 256 if r >= 4 else 64, F.ORDER_NATURAL, 11 if fused else 3)
+            tb = (r, 256 if r >= 4 else 64, F.ORDER_NATURAL, 19 if fused else 3)
             g.run(rule, 2, F.MAP_BB, tb)
             res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
         lam = per_launch[rule]
@@ -183,7 +184,7 @@ def k16_leg(F, torch, steps):
     for rule in (0, 1):
         r = g.tunings[rule][0]
         for rr in sorted({r, 5}):
-            tb = (rr, 256, F.ORDER_NATURAL, 11)
+            tb = (rr, 256, F.ORDER_NATURAL, 19)
             g.run(rule, 2, F.MAP_BB, tb)
             sec = g.time(rule, max(4, steps // 4), F.MAP_BB, tb)
             out[RULE_NAME[rule]][f"bb_r{rr}_us"] = sec * 1e6

@@ -73,10 +73,15 @@ extern "C" {
                                    member (their member-free chunks are read
                                    and written as 0) instead of 16-byte chunks */
 #define FRACTAL_FLAG_NT_STORE 2 /* non-temporal hint on output stores */
-#define FRACTAL_FLAG_FUSE2 8    /* two steps per launch: a two-cell halo is
+#define FRACTAL_FLAG_FUSE2 8    /* two steps per launch: T = 2 halo rows and
+                                   one extra 16-byte chunk column per side are
                                    staged and the intermediate step stays in
-                                   LDS, halving state traffic per step (tiles
-                                   whose rows span >= 16 bytes) */
+                                   LDS, halving state traffic per step.  Needs
+                                   FRACTAL_FLAG_SEGMENTS and tile rows of >= 16
+                                   bytes.  Launches come in pairs; the last
+                                   steps - 2T*floor(steps/2T) steps run one per
+                                   launch */
+#define FRACTAL_FLAG_FUSE4 16   /* as FUSE2 with four steps per launch */
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
                                      contiguous ranges of the tile list, instead
                                      of one workgroup per tile */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfractal.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_AGAIN = 0, 1, 2, 3, 4
 RULE_CA, RULE_HEAT = 0, 1
 ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
-FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2 = 1, 2, 4, 8
+FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2, FLAG_FUSE4 = 1, 2, 4, 8, 16
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 

@@ -101,18 +101,19 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured at level 16 on MI355X (128 x 128 automaton tiles, 64 x 64
-// heat tiles, 256 threads, omega in launch order, whole 64-byte segments,
-// non-temporal stores, two steps per launch).
+// launches measured at level 16 on MI355X: automaton 128 x 128 tiles, two
+// steps per launch, non-temporal stores; heat 32 x 32 tiles, four steps per
+// launch; both 256 threads, omega in launch order, whole 64-byte segments.
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 7 : 6);
+    const bool ca = rule == FRACTAL_RULE_CA;
+    const int r = clamp_r(k, ca ? 7 : 5);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
     t.threads = r >= 3 ? 256 : 64;
     t.order = FRACTAL_ORDER_NATURAL;
-    t.flags = FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE;
+    t.flags = FRACTAL_FLAG_SEGMENTS;
     if ((1 << r) * (int)cell_bytes(rule) >= 16)
-        t.flags |= FRACTAL_FLAG_FUSE2;
+        t.flags |= ca ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE) : FRACTAL_FLAG_FUSE4;
     return t;
 }
 
@@ -148,10 +149,16 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "threads=%d must be 64 or 256", t->threads);
     if (t->order < FRACTAL_ORDER_NATURAL || t->order > FRACTAL_ORDER_CURVE_XCD)
         return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
-    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2))
+    const int fuse = t->flags & (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4);
+    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2 |
+                     FRACTAL_FLAG_FUSE4))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
-    if ((t->flags & FRACTAL_FLAG_FUSE2) && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
-        return set_error(FRACTAL_E_INVAL, "two-step launches need tile rows of >= 16 bytes");
+    if (fuse == (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4))
+        return set_error(FRACTAL_E_INVAL, "FUSE2 and FUSE4 are exclusive");
+    if (fuse && !(t->flags & FRACTAL_FLAG_SEGMENTS))
+        return set_error(FRACTAL_E_INVAL, "fused launches need FRACTAL_FLAG_SEGMENTS");
+    if (fuse && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
+        return set_error(FRACTAL_E_INVAL, "fused launches need tile rows of >= 16 bytes");
     if (t->threads == 256 && t->r < 3)
         return set_error(FRACTAL_E_INVAL, "256 threads need tiles of side >= 8");
     return FRACTAL_OK;
@@ -304,7 +311,7 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         return rc;
     }
     // Few-step timings; enough launches that per-launch gaps are included.
-    const int reps = k >= 15 ? 8 : (k >= 12 ? 16 : 64); // multiples of 4 (fused pairs)
+    const int reps = k >= 15 ? 8 : (k >= 12 ? 16 : 64); // multiples of 8 (fused pairs)
     fractal_tuning best{};
     float best_ms = 1e30f;
     std::vector<fractal_tuning> cands;
@@ -318,9 +325,9 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
             if (th == 256 && r < 4)
                 continue;
             for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE_XCD})
-                for (int fl : {0, 1, 3, 9, 11}) {
+                for (int fl : {0, 1, 3, 9, 11, 17, 19}) {
                     fractal_tuning t{r, th, order, fl};
-                    if ((fl & FRACTAL_FLAG_FUSE2) && row_bytes < 16)
+                    if (fl > 3 && row_bytes < 16)
                         continue;
                     cands.push_back(t);
                 }
@@ -328,7 +335,7 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)
-        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 4, t, s);
+        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 8, t, s);
         if (!rc)
             rc = hip_error(hipEventRecord(e0, s), "event record");
         if (!rc)

@@ -45,7 +45,7 @@ __device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, ui
                                            int slot)
 {
     const TileXY t = lambda_wave_curve(L, e.k - R);
-    const int flips = (FL & TILE_FUSE2) ? slot : e.fused + slot;
+    const int flips = fused_steps<FL>() > 1 ? slot : e.fused + slot;
     const bool odd = ((e.phase + flips) & 1) != 0;
     StepParams p;
     p.src = odd ? e.buf1 : e.buf0;
@@ -109,7 +109,7 @@ static void pick_r(int r, TileFn *tf, PersistFn *pf)
     switch (r) {
 #define FRACTAL_BATCH_CASE(RR)                                                                     \
     case RR:                                                                                       \
-        if constexpr (!((FL & TILE_FUSE2) && !Geom<RULE, RR>::FUSABLE) && !(NT == 256 && RR < 3)) { \
+        if constexpr (!(fused_steps<FL>() > 1 && !Geom<RULE, RR>::FUSABLE) && !(NT == 256 && RR < 3)) { \
             *tf = batch_tile_kernel<RULE, RR, NT, FL>;                                             \
             *pf = batch_persistent_kernel<RULE, RR, NT, FL>;                                       \
         }                                                                                          \
@@ -144,10 +144,10 @@ static void pick_flags(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
     case 1: pick_threads<RULE, 1>(r, threads, tf, pf); break;
     case 2: pick_threads<RULE, 2>(r, threads, tf, pf); break;
     case 3: pick_threads<RULE, 3>(r, threads, tf, pf); break;
-    case 8: pick_threads<RULE, 8>(r, threads, tf, pf); break;
     case 9: pick_threads<RULE, 9>(r, threads, tf, pf); break;
-    case 10: pick_threads<RULE, 10>(r, threads, tf, pf); break;
     case 11: pick_threads<RULE, 11>(r, threads, tf, pf); break;
+    case 17: pick_threads<RULE, 17>(r, threads, tf, pf); break;
+    case 19: pick_threads<RULE, 19>(r, threads, tf, pf); break;
     default:
         *tf = nullptr;
         *pf = nullptr;
@@ -176,7 +176,10 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
             t.threads = forced->threads;
         t.flags = forced->flags;
     }
-    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2;
+    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2 |
+               FRACTAL_FLAG_FUSE4;
+    if (t.flags & (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4))
+        t.flags |= FRACTAL_FLAG_SEGMENTS; // fused launches move whole segments
     if (t.r > k)
         t.r = k;
     if (t.r > kMaxR)
@@ -185,8 +188,8 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         t.r = k - kMaxBlockLevel;
     if (t.threads == 256 && t.r < 3)
         t.threads = 64;
-    if ((t.flags & FRACTAL_FLAG_FUSE2) && ((1 << t.r) * (int)cell_bytes(rule)) < 16)
-        t.flags &= ~FRACTAL_FLAG_FUSE2; // two-step launches need 16-byte rows
+    if ((1 << t.r) * (int)cell_bytes(rule) < 16) // fused launches need 16-byte rows
+        t.flags &= ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4);
     t.order = FRACTAL_ORDER_CURVE_XCD;
     return t;
 }
@@ -205,9 +208,9 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
     for (auto &g : groups) {
         Class c;
         std::tie(c.rule, c.r, c.threads, c.flags) = g.first;
-        const bool fuse = (c.flags & FRACTAL_FLAG_FUSE2) != 0;
-        auto fused_of = [&](size_t i) { return fuse ? 2 * (items[i].steps / 4) : 0; };
-        auto single_of = [&](size_t i) { return items[i].steps - 2 * fused_of(i); };
+        const int T = launch_steps_of(c.flags);
+        auto fused_of = [&](size_t i) { return T > 1 ? 2 * (items[i].steps / (2 * T)) : 0; };
+        auto single_of = [&](size_t i) { return items[i].steps - T * fused_of(i); };
         auto emit = [&](List &list, std::vector<size_t> ids, auto count_of) {
             std::stable_sort(ids.begin(), ids.end(),
                              [&](size_t a, size_t b) { return count_of(a) > count_of(b); });
@@ -255,7 +258,8 @@ int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hi
         if (active == 0)
             continue;
         const uint64_t total = list.prefix[active];
-        const int flags = in_fused ? c.flags : (c.flags & ~FRACTAL_FLAG_FUSE2);
+        const int flags =
+            in_fused ? c.flags : (c.flags & ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4));
         TileFn tf = nullptr;
         PersistFn pf = nullptr;
         if (c.rule == FRACTAL_RULE_CA)
@@ -330,7 +334,8 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
                              tuning->threads);
         if (tuning->flags &
             ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE |
-              FRACTAL_FLAG_FUSE2))
+              FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4) ||
+            ((tuning->flags & FRACTAL_FLAG_FUSE2) && (tuning->flags & FRACTAL_FLAG_FUSE4)))
             return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
     }
     // validate every instance and pick its tile launch

@@ -5,14 +5,17 @@
 // them back with one vector store per chunk.  Only chunks that contain a
 // gasket member are read or written: off-gasket cells are 0 in both buffers
 // by contract, so a chunk without members is 0 on input and stays 0.
-// The fused form stages a two-cell halo, computes the intermediate step on
-// the tile plus a one-cell ring into a second LDS buffer, and from there the
-// final step: two steps for one read and one write of the state.
+// The fused form advances T steps per launch: it stages T halo rows and one
+// extra 16-byte chunk column on each side, runs the T-1 intermediate steps
+// between two LDS buffers over that whole region (cells near its edge go
+// wrong, but the damage moves inward one cell per step and T is at most the
+// cells of one chunk, so it never reaches the tile), and computes the last
+// step on the tile itself: T steps for one read and one write of the state.
 //
-// LDS row layout (bytes): cell x0 + dx of a staged row sits at byte
-// 16 + dx * S for dx in [-H, rho + H) (H = halo width); for uint8 tiles
-// narrower than a word the right halo cell sits directly after the tile
-// bytes.  Rows 0 .. H-1 and the last H rows are the halo rows.
+// One-step LDS row layout (bytes): cell x0 + dx of a staged row sits at byte
+// 16 + dx * S for dx in [-1, rho + 1); for uint8 tiles narrower than a word
+// the right halo cell sits directly after the tile bytes.  Rows 0 and
+// rho + 1 are the halo rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,12 +44,8 @@ struct Geom {
     static constexpr int ROWS = RHO + 2;
     static constexpr int SPARE = ROWS * PITCH;               // sink for idle lanes
     static constexpr int LDS_BYTES = SPARE + 16;
-    // fused two-step form: RHO + 4 staged rows, then RHO + 2 intermediate rows
+    // the fused form needs whole 16-byte chunks per row
     static constexpr bool FUSABLE = RB >= 16;
-    static constexpr int ROWS2 = RHO + 4;
-    static constexpr int MID = ROWS2 * PITCH;                 // intermediate buffer
-    static constexpr int SPARE2 = MID + ROWS * PITCH;
-    static constexpr int LDS2_BYTES = SPARE2 + 16;
     static constexpr int OFFW = OFF / 4;
     static constexpr int PITCHW = PITCH / 4;
     static constexpr int RIGHTW = OFFW + CPR * W;             // right halo word
@@ -61,6 +60,30 @@ enum : int {
                        // member (chunks of them without members carry 0s)
     TILE_NT_STORE = 2, // non-temporal hint on output stores
     TILE_FUSE2 = 8,    // two steps per launch (tiles with rows of >= 16 bytes)
+    TILE_FUSE4 = 16,   // four steps per launch (same condition)
+};
+
+template <int FL>
+constexpr int fused_steps()
+{
+    return (FL & TILE_FUSE4) ? 4 : ((FL & TILE_FUSE2) ? 2 : 1);
+}
+
+// Layout of the fused form: chunk columns -1 .. CPR (column c at byte
+// OFF + (c + 1) * CB), a zero guard word on either side, RHO + 2T rows, two
+// buffers.
+template <int RULE, int R, int T>
+struct FGeom {
+    using G = Geom<RULE, R>;
+    static constexpr int NC = G::CPR + 2;
+    static constexpr int OFF = 16;
+    static constexpr int PITCH = OFF + NC * G::CB + 16;
+    static constexpr int PITCHW = PITCH / 4;
+    static constexpr int B0W = (OFF + G::CB) / 4; // word of tile chunk 0
+    static constexpr int ROWS = G::RHO + 2 * T;
+    static constexpr int BUF = ROWS * PITCH;
+    static constexpr int SPARE = 2 * BUF;
+    static constexpr int LDS_BYTES = SPARE + 16;
 };
 
 template <int BYTES>
@@ -204,38 +227,35 @@ struct StepParams {
     float alpha;        // heat coefficient
 };
 
-// Stage rows y0-H .. y0+RHO+H-1 and columns x0-H .. x0+RHO+H-1 of the input
-// into LDS (cells outside the array or off the gasket read as 0).  Every load
-// of this thread is issued before its first LDS write.
-template <int RULE, int R, int NT, int FL, int H>
+// Stage rows y0-1 .. y0+RHO and columns x0-1 .. x0+RHO of the input into LDS
+// (cells outside the array or off the gasket read as 0).  Every load of this
+// thread is issued before its first LDS write.
+template <int RULE, int R, int NT, int FL>
 __device__ __forceinline__ void stage_tile(uint8_t *lds, const StepParams &p, uint32_t x0,
                                            uint32_t y0)
 {
     using G = Geom<RULE, R>;
-    static_assert(H == 1 || (H == 2 && G::FUSABLE), "two-cell halo needs 16-byte rows");
     constexpr int PLOG = (FL & TILE_SEGMENTS) ? G::SLOG : G::CLOG;
-    constexpr int NROWS = G::RHO + 2 * H;
-    constexpr int SPARE = H == 1 ? G::SPARE : G::SPARE2;
     using V = typename VecT<G::CB>::T;
     const uint32_t n = 1u << p.k;
     const uint32_t pitch = n * G::S; // bytes per state row (<= 2^18)
     const uint32_t tid = threadIdx.x;
-    // resource based at row y0 - H (possibly before the buffer; such rows are
-    // never addressed), spanning the staged rows
-    const rsrc_t src = make_rsrc(p.src + ((int64_t)y0 - H) * (int64_t)pitch,
-                                 (uint32_t)NROWS * pitch);
-    constexpr int NCHUNK = NROWS * G::CPR;
+    // resource based at row y0 - 1 (possibly before the buffer; that row is
+    // then never addressed), spanning the staged rows
+    const rsrc_t src = make_rsrc(p.src + ((int64_t)y0 - 1) * (int64_t)pitch,
+                                 (uint32_t)G::ROWS * pitch);
+    constexpr int NCHUNK = G::ROWS * G::CPR;
     constexpr int NIT = (NCHUNK + NT - 1) / NT;
-    constexpr int NHALO = 2 * NROWS;
+    constexpr int NHALO = 2 * G::ROWS;
     constexpr int NHIT = (NHALO + NT - 1) / NT;
     using LV = typename std::conditional<G::TINY, uint32_t, V>::type;
     LV vals[NIT];
-    uint32_t hvals[NHIT][H];
+    uint32_t hvals[NHIT];
 #pragma unroll
     for (int q = 0; q < NIT; ++q) {
         const int it = (int)tid + q * NT;
         const int ry = it / G::CPR, c = it % G::CPR;
-        const int64_t y = (int64_t)y0 - H + ry;
+        const int64_t y = (int64_t)y0 - 1 + ry;
         const uint32_t xc = x0 + (uint32_t)c * G::CCELLS;
         const bool rowok = it < NCHUNK && y >= 0 && y < (int64_t)n;
         const bool live = rowok && (((xc >> PLOG) & ((uint32_t)y >> PLOG)) == 0u);
@@ -257,42 +277,22 @@ __device__ __forceinline__ void stage_tile(uint8_t *lds, const StepParams &p, ui
             vals[q] = buf_load<G::CB>(src, live ? roff + xc * G::S : kOff);
         }
     }
-    // halo columns: item 2*ry is the left run x0-H .. x0-1, item 2*ry+1 the
-    // right run x0+rho .. x0+rho+H-1
+    // halo columns: item 2*ry is cell x0-1, item 2*ry+1 cell x0+rho
 #pragma unroll
     for (int q = 0; q < NHIT; ++q) {
         const int it = (int)tid + q * NT;
         const int ry = it >> 1;
         const bool right = it & 1;
-        const int64_t y = (int64_t)y0 - H + ry;
-        const int64_t xa = right ? (int64_t)x0 + G::RHO : (int64_t)x0 - H; // first cell of run
-        bool want = it < NHALO && !(right && G::TINY) && xa >= 0 && xa + H <= (int64_t)n &&
-                    y >= 0 && y < (int64_t)n;
-        if (want) {
-            bool anym = false;
-#pragma unroll
-            for (int h = 0; h < H; ++h)
-                anym |= ((((uint32_t)xa + h) & (uint32_t)y) == 0u);
-            want = anym;
-        }
-        const uint32_t off = want ? (uint32_t)ry * pitch + (uint32_t)xa * G::S : kOff;
+        const int64_t y = (int64_t)y0 - 1 + ry;
+        const int64_t x = right ? (int64_t)x0 + G::RHO : (int64_t)x0 - 1;
+        const bool want = it < NHALO && !(right && G::TINY) && x >= 0 && x < (int64_t)n &&
+                          y >= 0 && y < (int64_t)n && ((((uint32_t)x) & (uint32_t)y) == 0u);
+        const uint32_t off = want ? (uint32_t)ry * pitch + (uint32_t)x * G::S : kOff;
         if constexpr (G::S == 1) {
-            if constexpr (H == 1) {
-                const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(src, off, 0, 0);
-                hvals[q][0] = right ? b : (b << 24);
-            } else {
-                const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(src, off, 0, 0);
-                hvals[q][0] = right ? b : (b << 16);
-                hvals[q][1] = 0u;
-            }
+            const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(src, off, 0, 0);
+            hvals[q] = right ? b : (b << 24);
         } else {
-            if constexpr (H == 1) {
-                hvals[q][0] = __builtin_amdgcn_raw_buffer_load_b32(src, off, 0, 0);
-            } else {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b64(src, off, 0, 0);
-                hvals[q][0] = v[0];
-                hvals[q][1] = v[1];
-            }
+            hvals[q] = __builtin_amdgcn_raw_buffer_load_b32(src, off, 0, 0);
         }
     }
     // LDS writes are unconditional (idle lanes write a spare slot) so that
@@ -302,37 +302,30 @@ __device__ __forceinline__ void stage_tile(uint8_t *lds, const StepParams &p, ui
         const int it = (int)tid + q * NT;
         const int ry = it / G::CPR, c = it % G::CPR;
         const int slot = (NCHUNK % NT == 0 || it < NCHUNK) ? ry * G::PITCH + G::OFF + c * G::CB
-                                                          : SPARE;
+                                                          : G::SPARE;
         *reinterpret_cast<LV *>(lds + slot) = vals[q];
     }
 #pragma unroll
     for (int q = 0; q < NHIT; ++q) {
         const int it = (int)tid + q * NT;
-        const bool ok = NHALO % NT == 0 || it < NHALO;
-        const int rowb = (it >> 1) * G::PITCH;
-        if constexpr (H == 1 || G::S == 1) {
-            // one word: uint8 cells packed at its top (left) or bottom
-            // (right) bytes, or one float32
-            const int slot = ok ? rowb + 4 * ((it & 1) ? G::RIGHTW : G::OFFW - 1) : SPARE;
-            *reinterpret_cast<uint32_t *>(lds + slot) = hvals[q][0];
-        } else {
-            const int slot = ok ? rowb + 4 * ((it & 1) ? G::RIGHTW : G::OFFW - 2) : SPARE;
-            *reinterpret_cast<uint2 *>(lds + slot) = uint2{hvals[q][0], hvals[q][1]};
-        }
+        const int slot = (NHALO % NT == 0 || it < NHALO)
+                             ? (it >> 1) * G::PITCH + 4 * ((it & 1) ? G::RIGHTW : G::OFFW - 1)
+                             : G::SPARE;
+        *reinterpret_cast<uint32_t *>(lds + slot) = hvals[q];
     }
 }
 
-// New value of the output chunk at LDS row `rmd` (rows rmd-1 and rmd+1 above
-// and below), chunk c, for global row y, masked to gasket members.
-template <int RULE, int R>
-__device__ __forceinline__ void chunk_update(const uint32_t *lw, int rmd, int c, uint32_t xc,
+// New value of the output chunk whose first word is `base` in LDS row `rmd`
+// (rows rmd-1 and rmd+1 above and below, PW words per row), for global row
+// y and first cell xc, masked to gasket members.
+template <int RULE, int R, int PW>
+__device__ __forceinline__ void chunk_update(const uint32_t *lw, int rmd, int base, uint32_t xc,
                                              uint32_t y, float alpha, float c1,
                                              uint32_t (&out)[Geom<RULE, R>::W])
 {
     using G = Geom<RULE, R>;
     using V = typename VecT<G::CB>::T;
-    const int base = G::OFFW + c * G::W;
-    const int r_up = (rmd - 1) * G::PITCHW, r_md = rmd * G::PITCHW, r_dn = (rmd + 1) * G::PITCHW;
+    const int r_up = (rmd - 1) * PW, r_md = rmd * PW, r_dn = (rmd + 1) * PW;
     uint32_t up[G::W], md[G::W], dn[G::W];
     unpack<G::W>(*reinterpret_cast<const V *>(lw + r_up + base), up);
     unpack<G::W>(*reinterpret_cast<const V *>(lw + r_md + base), md);
@@ -371,9 +364,10 @@ __device__ __forceinline__ void chunk_update(const uint32_t *lw, int rmd, int c,
     }
 }
 
-// Compute the tile's rows from an LDS buffer holding rows y0-1 .. y0+rho
-// (layout as staged with H = 1) and store the chunks that hold a member.
-template <int RULE, int R, int NT, int FL>
+// Compute the tile's rows from an LDS buffer (PW words per row, tile row j
+// in LDS row j + ROW0, tile chunk 0 starting at word B0W) and store the
+// chunks that hold a member.
+template <int RULE, int R, int NT, int FL, int PW, int B0W, int ROW0>
 __device__ __forceinline__ void store_tile(const uint8_t *lds, const StepParams &p, uint32_t x0,
                                            uint32_t y0)
 {
@@ -407,7 +401,7 @@ __device__ __forceinline__ void store_tile(const uint8_t *lds, const StepParams 
             continue;
         }
         uint32_t out[G::W];
-        chunk_update<RULE, R>(lw, j + 1, c, xc, y, alpha, c1, out);
+        chunk_update<RULE, R, PW>(lw, j + ROW0, B0W + c * G::W, xc, y, alpha, c1, out);
         if constexpr (G::TINY) {
             // x0 is not word-aligned here: mask and store each cell on its own
 #pragma unroll
@@ -422,109 +416,112 @@ __device__ __forceinline__ void store_tile(const uint8_t *lds, const StepParams 
     }
 }
 
-// Value of one cell after a step, from a buffer staged with H = 2 (LDS row
-// sr holds global row y, column offset dx from x0); 0 off the gasket.
-template <int RULE, int R>
-__device__ __forceinline__ uint32_t cell_update(const uint8_t *lds, int sr, int dx, uint32_t x,
-                                                uint32_t y, float alpha, float c1)
+// Fused form, staging: rows y0-T .. y0+rho+T-1, chunk columns -1 .. CPR of
+// the input into buffer 0 (cells outside the array or in segments without
+// members read as 0), and zero guard words in both buffers.
+template <int RULE, int R, int NT, int FL, int T>
+__device__ __forceinline__ void stage_fused(uint8_t *lds, const StepParams &p, uint32_t x0,
+                                            uint32_t y0)
 {
     using G = Geom<RULE, R>;
-    if ((x & y) != 0u)
-        return 0u;
-    auto at = [&](int row, int d) -> uint32_t {
-        const uint8_t *q = lds + row * G::PITCH + G::OFF + d * G::S;
-        if constexpr (G::S == 1)
-            return *q;
-        else
-            return *reinterpret_cast<const uint32_t *>(q);
-    };
-    if constexpr (RULE == RULE_CA) {
-        const uint32_t self = at(sr, dx);
-        uint32_t cnt = 0;
+    using FG = FGeom<RULE, R, T>;
+    using V = typename VecT<G::CB>::T;
+    constexpr int PLOG = (FL & TILE_SEGMENTS) ? G::SLOG : G::CLOG;
+    const uint32_t n = 1u << p.k;
+    const uint32_t pitch = n * G::S;
+    const uint32_t tid = threadIdx.x;
+    const rsrc_t src = make_rsrc(p.src + ((int64_t)y0 - T) * (int64_t)pitch,
+                                 (uint32_t)FG::ROWS * pitch);
+    constexpr int NCHUNK = FG::ROWS * FG::NC;
+    constexpr int NIT = (NCHUNK + NT - 1) / NT;
+    V vals[NIT];
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+    for (int q = 0; q < NIT; ++q) {
+        const int it = (int)tid + q * NT;
+        const int ry = it / FG::NC, c = it % FG::NC - 1;
+        const int64_t y = (int64_t)y0 - T + ry;
+        const int64_t xc = (int64_t)x0 + (int64_t)c * G::CCELLS;
+        const bool ok = it < NCHUNK && y >= 0 && y < (int64_t)n && xc >= 0 && xc < (int64_t)n &&
+                        ((((uint32_t)xc >> PLOG) & ((uint32_t)y >> PLOG)) == 0u);
+        vals[q] = buf_load<G::CB>(src, ok ? (uint32_t)ry * pitch + (uint32_t)xc * G::S : kOff);
+    }
+    for (int it = (int)tid; it < FG::ROWS; it += NT) {
+        uint32_t *row = reinterpret_cast<uint32_t *>(lds + it * FG::PITCH);
+        row[FG::OFF / 4 - 1] = 0u;
+        row[(FG::OFF + FG::NC * G::CB) / 4] = 0u;
+        row += FG::BUF / 4;
+        row[FG::OFF / 4 - 1] = 0u;
+        row[(FG::OFF + FG::NC * G::CB) / 4] = 0u;
+    }
 #pragma unroll
-            for (int ddx = -1; ddx <= 1; ++ddx)
-                cnt += at(sr + dy, dx + ddx);
-        cnt -= self; // the 8 neighbours
-        return (cnt == 3u || (self == 1u && cnt == 2u)) ? 1u : 0u;
-    } else {
-        const float v = heat_cell(__uint_as_float(at(sr, dx)), __uint_as_float(at(sr - 1, dx)),
-                                  __uint_as_float(at(sr + 1, dx)), __uint_as_float(at(sr, dx - 1)),
-                                  __uint_as_float(at(sr, dx + 1)), alpha, c1);
-        return __float_as_uint(v);
+    for (int q = 0; q < NIT; ++q) {
+        const int it = (int)tid + q * NT;
+        const int ry = it / FG::NC, c = it % FG::NC;
+        const int slot = (NCHUNK % NT == 0 || it < NCHUNK) ? ry * FG::PITCH + FG::OFF + c * G::CB
+                                                          : FG::SPARE;
+        *reinterpret_cast<V *>(lds + slot) = vals[q];
     }
 }
 
-// Intermediate step of the fused form: from the H = 2 staging (rows
-// y0-2 .. y0+rho+1) compute rows y0-1 .. y0+rho and columns x0-1 .. x0+rho
-// into the intermediate buffer, laid out as an H = 1 staging.
-template <int RULE, int R, int NT>
-__device__ __forceinline__ void mid_step(uint8_t *lds, const StepParams &p, uint32_t x0,
-                                         uint32_t y0)
+// Fused form, intermediate step t (1 <= t < T): from the buffer holding step
+// t-1 into the other one, rows t .. rho+2T-1-t, every chunk column.  Cells
+// outside the array and chunks without members are written as 0.
+template <int RULE, int R, int NT, int T>
+__device__ __forceinline__ void fused_step(uint8_t *lds, const StepParams &p, uint32_t x0,
+                                           uint32_t y0, int t)
 {
     using G = Geom<RULE, R>;
+    using FG = FGeom<RULE, R, T>;
     using V = typename VecT<G::CB>::T;
     const uint32_t n = 1u << p.k;
-    const uint32_t tid = threadIdx.x;
     const float alpha = p.alpha;
     const float c1 = 1.0f - 4.0f * alpha;
-    const uint32_t *lw = reinterpret_cast<const uint32_t *>(lds);
-    uint8_t *mid = lds + G::MID;
-    constexpr int NMID = G::ROWS * G::CPR;
-#pragma unroll
-    for (int q = 0; q < (NMID + NT - 1) / NT; ++q) {
-        const int it = (int)tid + q * NT;
-        if (NMID % NT != 0 && it >= NMID)
-            break;
-        const int by = it / G::CPR, c = it % G::CPR; // intermediate row, chunk
-        const int64_t yy = (int64_t)y0 - 1 + by;
-        const uint32_t xc = x0 + (uint32_t)c * G::CCELLS;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(lds + ((t - 1) & 1) * FG::BUF);
+    uint8_t *dst = lds + (t & 1) * FG::BUF;
+    const int rows = FG::ROWS - 2 * t;
+    const int items = rows * FG::NC;
+    for (int it = (int)threadIdx.x; it < items; it += NT) {
+        const int ry = t + it / FG::NC, c = it % FG::NC - 1;
+        const int64_t y = (int64_t)y0 - T + ry;
+        const int64_t xc = (int64_t)x0 + (int64_t)c * G::CCELLS;
         uint32_t out[G::W];
-        if (yy < 0 || yy >= (int64_t)n || ((xc >> G::CLOG) & ((uint32_t)yy >> G::CLOG)) != 0u) {
+        if (y < 0 || y >= (int64_t)n || xc < 0 || xc >= (int64_t)n ||
+            ((((uint32_t)xc >> G::CLOG) & ((uint32_t)y >> G::CLOG)) != 0u)) {
 #pragma unroll
             for (int w = 0; w < G::W; ++w)
                 out[w] = 0u;
         } else {
-            chunk_update<RULE, R>(lw, by + 1, c, xc, (uint32_t)yy, alpha, c1, out);
+            chunk_update<RULE, R, FG::PITCHW>(src, ry, FG::B0W + c * G::W, (uint32_t)xc,
+                                              (uint32_t)y, alpha, c1, out);
         }
-        *reinterpret_cast<V *>(mid + by * G::PITCH + G::OFF + c * G::CB) = pack<G::W>(out);
-    }
-    // the one-cell ring's left and right columns
-    for (int it = (int)tid; it < 2 * G::ROWS; it += NT) {
-        const int by = it >> 1;
-        const bool right = it & 1;
-        const int64_t yy = (int64_t)y0 - 1 + by;
-        const int64_t xx = right ? (int64_t)x0 + G::RHO : (int64_t)x0 - 1;
-        uint32_t v = 0u;
-        if (yy >= 0 && yy < (int64_t)n && xx >= 0 && xx < (int64_t)n)
-            v = cell_update<RULE, R>(lds, by + 1, right ? G::RHO : -1, (uint32_t)xx,
-                                     (uint32_t)yy, alpha, c1);
-        uint32_t *wrow = reinterpret_cast<uint32_t *>(mid + by * G::PITCH);
-        if constexpr (G::S == 1)
-            wrow[right ? G::RIGHTW : G::OFFW - 1] = right ? v : (v << 24);
-        else
-            wrow[right ? G::RIGHTW : G::OFFW - 1] = v;
+        *reinterpret_cast<V *>(dst + ry * FG::PITCH + FG::OFF + (c + 1) * G::CB) = pack<G::W>(out);
     }
 }
 
-// Process the tile whose top-left cell is (x0, y0): one step, or two with
-// TILE_FUSE2.  All NT threads of the workgroup must call it (it contains
-// workgroup barriers).
+// Process the tile whose top-left cell is (x0, y0): one step, or T steps
+// with a fused flag.  All NT threads of the workgroup must call it (it
+// contains workgroup barriers).
 template <int RULE, int R, int NT, int FL = 0>
 __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
                                           uint32_t x0, uint32_t y0)
 {
-    if constexpr ((FL & TILE_FUSE2) != 0 && Geom<RULE, R>::FUSABLE) {
-        stage_tile<RULE, R, NT, FL, 2>(lds, p, x0, y0);
+    using G = Geom<RULE, R>;
+    constexpr int T = fused_steps<FL>();
+    if constexpr (T > 1 && G::FUSABLE) {
+        using FG = FGeom<RULE, R, T>;
+        stage_fused<RULE, R, NT, FL, T>(lds, p, x0, y0);
         __syncthreads();
-        mid_step<RULE, R, NT>(lds, p, x0, y0);
-        __syncthreads();
-        store_tile<RULE, R, NT, FL>(lds + Geom<RULE, R>::MID, p, x0, y0);
+#pragma unroll
+        for (int t = 1; t < T; ++t) {
+            fused_step<RULE, R, NT, T>(lds, p, x0, y0, t);
+            __syncthreads();
+        }
+        store_tile<RULE, R, NT, FL, FG::PITCHW, FG::B0W, T>(lds + ((T - 1) & 1) * FG::BUF, p, x0,
+                                                            y0);
     } else {
-        stage_tile<RULE, R, NT, FL, 1>(lds, p, x0, y0);
+        stage_tile<RULE, R, NT, FL>(lds, p, x0, y0);
         __syncthreads();
-        store_tile<RULE, R, NT, FL>(lds, p, x0, y0);
+        store_tile<RULE, R, NT, FL, G::PITCHW, G::OFFW, 1>(lds, p, x0, y0);
     }
 }
 
@@ -532,8 +529,9 @@ __device__ __forceinline__ void tile_step(uint8_t *lds, const StepParams &p,
 template <int RULE, int R, int FL>
 constexpr int tile_lds_bytes()
 {
-    return ((FL & TILE_FUSE2) != 0 && Geom<RULE, R>::FUSABLE) ? Geom<RULE, R>::LDS2_BYTES
-                                                              : Geom<RULE, R>::LDS_BYTES;
+    return (fused_steps<FL>() > 1 && Geom<RULE, R>::FUSABLE)
+               ? FGeom<RULE, R, fused_steps<FL>()>::LDS_BYTES
+               : Geom<RULE, R>::LDS_BYTES;
 }
 
 } // namespace fractal

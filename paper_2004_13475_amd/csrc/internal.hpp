@@ -61,6 +61,12 @@ StepFn pick_step_lambda(int rule, int r, int threads, int flags);
 StepFn pick_step_bb(int rule, int r, int threads, int flags);
 StepFn pick_step_mfma(int rule, int r, int threads, int flags);
 
+// Steps one launch advances under these flags (1, 2 or 4).
+inline int launch_steps_of(int flags)
+{
+    return (flags & FRACTAL_FLAG_FUSE4) ? 4 : ((flags & FRACTAL_FLAG_FUSE2) ? 2 : 1);
+}
+
 // Launch `steps` step kernels (validated arguments).
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s);
@@ -101,9 +107,9 @@ struct BatchItem {
 };
 
 // Instances grouped by launch class (rule, r, threads, step flags).  A class
-// with two-step launches gives each item f = 2 floor(steps / 4) of them (an
-// even number, so the result lands in buf[steps & 1]) and then steps - 2f
-// single steps.  Each class keeps a list for its two-step launches (items
+// with T-step launches (T = 2 or 4) gives each item f = 2 floor(steps / 2T)
+// of them (an even number, so the result lands in buf[steps & 1]) and then
+// steps - T f single steps.  Each class keeps a list for its two-step launches (items
 // sorted by f) and one for its single steps (sorted by count), so the items
 // taking part in any launch form a prefix of the list.  Launch slot t runs,
 // per class, its two-step launch t or single-step launch t - F (F = the

@@ -59,7 +59,7 @@ static StepFn pick_r(int r)
     switch (r) {
 #define FRACTAL_STEP_CASE(RR)                                                                      \
     case RR:                                                                                       \
-        if constexpr ((FL & TILE_FUSE2) && !Geom<RULE, RR>::FUSABLE)                               \
+        if constexpr (fused_steps<FL>() > 1 && !Geom<RULE, RR>::FUSABLE)                           \
             return nullptr;                                                                        \
         else if constexpr (NT == 256 && RR < 3)                                                    \
             return nullptr;                                                                        \
@@ -99,10 +99,10 @@ static StepFn pick_step_kernel(int rule, int r, int threads, int flags)
     case 1: return pick_rule<MAP, 1>(rule, r, threads);
     case 2: return pick_rule<MAP, 2>(rule, r, threads);
     case 3: return pick_rule<MAP, 3>(rule, r, threads);
-    case 8: return pick_rule<MAP, 8>(rule, r, threads);
     case 9: return pick_rule<MAP, 9>(rule, r, threads);
-    case 10: return pick_rule<MAP, 10>(rule, r, threads);
     case 11: return pick_rule<MAP, 11>(rule, r, threads);
+    case 17: return pick_rule<MAP, 17>(rule, r, threads);
+    case 19: return pick_rule<MAP, 19>(rule, r, threads);
     default: return nullptr;
     }
 }

@@ -51,11 +51,13 @@ int launch_lambda_map(int k, int r, uint32_t *d_xy, bool mfma, hipStream_t s)
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s)
 {
-    // Two-step launches come in pairs so that the result still lands in
-    // buf[steps & 1]; the remaining 0..3 steps run one step per launch.
-    const bool fuse = (t.flags & FRACTAL_FLAG_FUSE2) != 0;
-    const int fused = fuse ? 2 * (steps / 4) : 0;
-    StepFn fn1 = pick_step(map, rule, t.r, t.threads, t.flags & ~FRACTAL_FLAG_FUSE2);
+    // T-step launches come in pairs so that the result still lands in
+    // buf[steps & 1]; the remaining 0..2T-1 steps run one step per launch.
+    const int T = launch_steps_of(t.flags);
+    const bool fuse = T > 1;
+    const int fused = fuse ? 2 * (steps / (2 * T)) : 0;
+    StepFn fn1 = pick_step(map, rule, t.r, t.threads,
+                           t.flags & ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4));
     StepFn fn2 = fuse ? pick_step(map, rule, t.r, t.threads, t.flags) : nullptr;
     if (!fn1 || (fuse && !fn2))
         return set_error(FRACTAL_E_INVAL, "no kernel for map %d rule %d r %d threads %d flags %d",
@@ -73,7 +75,7 @@ int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
     a.order = t.order;
     a.total = grid.x * grid.y;
     uint8_t *bufs[2] = {static_cast<uint8_t *>(b0), static_cast<uint8_t *>(b1)};
-    const int launches = fused + (steps - 2 * fused);
+    const int launches = fused + (steps - T * fused);
     for (int i = 0; i < launches; ++i) {
         a.src = bufs[i & 1];
         a.dst = bufs[(i + 1) & 1];

@@ -34,7 +34,8 @@ def _mix(count, seed, kmin, kmax, max_steps):
 
 
 @pytest.mark.parametrize("tuning", [None, (4, 64, 2, 0), (5, 64, 2, F.FLAG_PERSISTENT),
-                                    (2, 64, 0, F.FLAG_PERSISTENT)])
+                                    (2, 64, 0, F.FLAG_PERSISTENT), (5, 256, 0, 11), (6, 0, 0, 19),
+                                    (5, 64, 0, 19 | F.FLAG_PERSISTENT)])
 def test_batch_alone_equals_in_mix(tuning):
     torch = torch_dev()
     specs = _mix(40, 3, 1, 11, 37)

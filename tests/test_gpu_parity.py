@@ -146,7 +146,8 @@ def test_lambda_bb_mfma_bit_identical_k12(rule):
     for m in MAPS:
         for (r, th, order, fl) in [(3, 64, 0, 0), (4, 64, 2, 1), (5, 256, 1, 2), (6, 256, 2, 3),
                                    (5, 64, 0, 1), (2, 64, 2, 3), (1, 64, 0, 1), (7, 256, 0, 3),
-                                   (7, 64, 2, 1)]:
+                                   (7, 64, 2, 1), (5, 256, 0, 11), (6, 64, 2, 19),
+                                   (7, 256, 1, 17)]:
             b0, b1 = to_device(init), zeros_state(k, rule)
             F.step_tuned(m, k, rule, ALPHA, b0, b1, steps, r, th, order, fl)
             _sync()
@@ -161,11 +162,12 @@ def test_lambda_bb_mfma_bit_identical_k12(rule):
 
 @pytest.mark.parametrize("rule", RULES)
 @pytest.mark.parametrize("map_", MAPS)
-def test_fused_two_step_launches(rule, map_):
-    """Two steps per launch (two-cell halo, intermediate step in LDS) give
-    the same bits as one step per launch, for every fusable tile size and
-    step counts that exercise the paired launches and the 0..3 single-step
-    tail; small levels also against the oracle."""
+def test_fused_launches(rule, map_):
+    """Two or four steps per launch (halo rows and an extra chunk column
+    staged, intermediate steps in LDS) give the same bits as one step per
+    launch, for every fusable tile size and step counts that exercise the
+    paired launches and the single-step tail; small levels also against the
+    oracle."""
     torch = torch_dev()
     cell = 1 if rule == fi.RULE_CA else 4
     for k in (5, 8, 11):
@@ -174,8 +176,8 @@ def test_fused_two_step_launches(rule, map_):
             if (1 << r) * cell < 16 or k - r > 15:
                 continue
             th = 256 if r >= 4 else 64
-            for steps in (1, 4, 5, 8, 11):
-                for fl in (9, 11):
+            for steps in (1, 4, 5, 8, 11, 16, 19):
+                for fl in (9, 11, 17, 19):
                     a0, a1 = to_device(init), zeros_state(k, rule)
                     F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, th, 2, fl)
                     b0, b1 = to_device(init), zeros_state(k, rule)
@@ -185,14 +187,15 @@ def test_fused_two_step_launches(rule, map_):
                     fb = b0 if steps % 2 == 0 else b1
                     assert torch.equal(fa.view(torch.uint8), fb.view(torch.uint8)), \
                         (k, r, steps, fl)
-                    if k <= 8 and fl == 11:
+                    if k <= 8 and fl in (11, 19):
                         ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64),
                                            steps)
                         assert_match(k, rule, fa.cpu().numpy(), ref, f"fused k={k} r={r} t={steps}")
 
 
+@pytest.mark.parametrize("flags", [11, 19])
 @pytest.mark.parametrize("rule", RULES)
-def test_fused_full_size_k16_sampled(rule):
+def test_fused_full_size_k16_sampled(rule, flags):
     """Level 16 with two-step launches, 200 steps, sampled against the
     oracle's light-cone windows."""
     k = 16
@@ -207,7 +210,7 @@ def test_fused_full_size_k16_sampled(rule):
         x0, y0, ww, hh = window_plan(k, 200, w, h, cx, cy)
         win = fi.window_values(k, rule, 3, x0, y0, ww, hh)
         plans.append(((x0, y0, ww, hh), win if rule == 0 else win.astype(np.float64)))
-    F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, 200, r, 256, 0, 11)
+    F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, 200, r, 256, 0, flags)
     _sync()
     for (x0, y0, ww, hh), state in plans:
         ref = oracle_steps(k, rule, state, 200, x0, y0)

@@ -78,7 +78,7 @@ def test_tuning_defaults_and_validation():
         for rule in (0, 1):
             r, th, order, flags = F.get_tuning(k, rule)
             assert 0 <= r <= min(k, 7) and k - r <= 15
-            assert th in (64, 256) and order in (0, 1, 2) and flags in (0, 1, 2, 3, 9, 10, 11)
+            assert th in (64, 256) and order in (0, 1, 2) and flags in (0, 1, 2, 3, 9, 11, 17, 19)
     with pytest.raises(F.FractalError):
         F.set_tuning(10, 0, 8, 64, 0)
     with pytest.raises(F.FractalError):
