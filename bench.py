@@ -142,7 +142,8 @@ def roofline(rule, cells, sec_per_step, tuning, traffic=None, kernel=""):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
             "steps_per_launch": spl, "alg_bytes_per_launch": alg,
-            "avg_launch_us": launch * 1e6}
+            "avg_launch_us": launch * 1e6,
+            "per_step_equivalent_GBs": alg / sec_per_step / 1e9}
 
 
 def bb_leg(g, per_launch, nsteps):
@@ -166,6 +167,22 @@ def bb_leg(g, per_launch, nsteps):
             "speedup_best": res[best] / lam,
             "bb_us_by_r": {str(r): v * 1e6 for r, v in res.items()},
         }
+    return out
+
+
+def mfma_leg(g, steps):
+    """lambda computed by two ballots vs by the matrix-core product
+    (Variant 1), same tile launch, same level."""
+    F = g.F
+    out = {}
+    for rule in (0, 1):
+        t = g.tunings[rule]
+        g.run(rule, 8, F.MAP_MFMA, t)
+        mf = g.time(rule, steps, F.MAP_MFMA, t)
+        g.run(rule, 8, F.MAP_LAMBDA, t)
+        lb = g.time(rule, steps, F.MAP_LAMBDA, t)
+        out[RULE_NAME[rule]] = {"ballot_us_per_step": lb * 1e6, "mfma_us_per_step": mf * 1e6,
+                                "mfma_speedup": lb / mf}
     return out
 
 
@@ -373,6 +390,7 @@ def main() -> int:
                   read_traffic(args.workload, RULE_NAME[dom]), f"lambda_step_{RULE_NAME[dom]}")
 
     bb = None if args.no_bb else bb_leg(g, per_launch, max(10, min(K, 200)))
+    mfma = None if args.no_bb else mfma_leg(g, max(16, min(K, 400)))
     k, cells, tunings = g.k, g.cells, dict(g.tunings)
     g.free()
     k16 = None if (args.no_k16 or k == 16) else k16_leg(F, torch, 50)
@@ -387,7 +405,7 @@ def main() -> int:
         import oracle
         ck = 14
         states = {0: fi.full_state(ck, 0, 1), 1: fi.full_state(ck, 1, 1, dtype=np.float64)}
-        nsteps = {0: 40, 1: 10}
+        nsteps = {0: 160, 1: 50}
         tc = time.perf_counter()
         oracle.ca_run(ck, states[0], nsteps[0])
         oracle.heat_run(ck, states[1], g.alpha, nsteps[1])
@@ -412,7 +430,7 @@ def main() -> int:
                                     "steps_per_launch": steps_per_launch(tunings[r]),
                                     "roofline": roofline(r, cells, per_launch[r], tunings[r])}
                      for r in (0, 1)},
-        "bb": bb, "k16": k16, "batch": batch, "serve": serve,
+        "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_hash(),
     }

@@ -120,6 +120,13 @@ int fractal_lambda_map_mfma(int k, int r, uint32_t *d_xy, void *stream);
 int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
                       void *stream);
 
+/* Launches of the step entry points below without an explicit tuning use,
+ * for an explicit r, 64 or 256 threads (one 16-byte chunk per lane), the
+ * die-aware curve order for lambda and launch order for the bounding box,
+ * whole segments, and where tile rows span >= 16 bytes two (automaton) or
+ * four (heat) steps per launch; for FRACTAL_R_AUTO, the cached autotuned
+ * launch or a built-in default. */
+
 /* Bounding-box step (Section 1; Section 6.2): a grid of all (n/rho)^2
  * workgroups with the identity map omega -> tile; a workgroup whose tile
  * holds no member exits at once.  Runs `steps` synchronous steps of `rule`

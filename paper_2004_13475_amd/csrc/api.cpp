@@ -80,6 +80,18 @@ static int default_threads(int rule, int r)
     return chunks >= 256 ? 256 : 64;
 }
 
+// Fastest launch flags measured for a tile level: whole segments always;
+// where tile rows span 16 bytes, the automaton fuses two steps per launch
+// with non-temporal stores and heat fuses four.
+static int default_flags(int rule, int r)
+{
+    int fl = FRACTAL_FLAG_SEGMENTS;
+    if ((1 << r) * (int)cell_bytes(rule) >= 16)
+        fl |= rule == FRACTAL_RULE_CA ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE)
+                                      : FRACTAL_FLAG_FUSE4;
+    return fl;
+}
+
 fractal_tuning tuning_for_r(int map, int k, int rule, int r)
 {
     (void)k;
@@ -87,7 +99,7 @@ fractal_tuning tuning_for_r(int map, int k, int rule, int r)
     t.r = r;
     t.threads = default_threads(rule, r);
     t.order = map == MAP_BB ? FRACTAL_ORDER_NATURAL : FRACTAL_ORDER_CURVE_XCD;
-    t.flags = 0;
+    t.flags = default_flags(rule, r);
     return t;
 }
 
@@ -101,19 +113,15 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured at level 16 on MI355X: automaton 128 x 128 tiles, two
-// steps per launch, non-temporal stores; heat 32 x 32 tiles, four steps per
-// launch; both 256 threads, omega in launch order, whole 64-byte segments.
+// launches measured at level 16 on MI355X: automaton 128 x 128 tiles (two
+// steps per launch, non-temporal stores), heat 32 x 32 tiles (four steps per
+// launch); 256 threads, omega in launch order, whole 64-byte segments.
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const bool ca = rule == FRACTAL_RULE_CA;
-    const int r = clamp_r(k, ca ? 7 : 5);
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 7 : 5);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
     t.threads = r >= 3 ? 256 : 64;
     t.order = FRACTAL_ORDER_NATURAL;
-    t.flags = FRACTAL_FLAG_SEGMENTS;
-    if ((1 << r) * (int)cell_bytes(rule) >= 16)
-        t.flags |= ca ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE) : FRACTAL_FLAG_FUSE4;
     return t;
 }
 

@@ -139,6 +139,13 @@ class BatchPlan {
     size_t entries_ = 0;
 };
 
+// Batched step kernels of one rule for (r, threads, flags): one workgroup
+// per tile (tf) and persistent (pf); nullptr if not instantiated.
+typedef void (*TileFn)(const BatchEntry *, int, uint32_t, int);
+typedef void (*PersistFn)(const BatchEntry *, int, uint64_t, int);
+void pick_batch_ca(int r, int threads, int flags, TileFn *tf, PersistFn *pf);
+void pick_batch_heat(int r, int threads, int flags, TileFn *tf, PersistFn *pf);
+
 // Tile launch used for one batched instance: `forced` (may be NULL) overrides
 // the per-level cached or default tuning.
 fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced);

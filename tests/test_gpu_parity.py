@@ -279,7 +279,7 @@ def test_full_size_k14(rule):
     clipped by the array edge) and two interior boxes at early steps."""
     k = 14
     n = 1 << k
-    r = F.get_tuning(k, rule)[0]
+    r = F.R_AUTO  # the default launch the benchmark starts from
     _full_size_check(k, rule, r, list(range(1, 9)) + [32, 100, 1000],
                      [(0, 0, 48, 48), (n - 48, 0, 48, 48), (0, n - 48, 48, 48)])
     _full_size_check(k, rule, r, [1, 2, 3, 10, 40],
@@ -292,10 +292,20 @@ def test_full_size_k16(rule):
     200 steps, sampled boxes at corners and inside."""
     k = 16
     n = 1 << k
-    r = F.get_tuning(k, rule)[0]
+    r = F.R_AUTO
     _full_size_check(k, rule, r, [1, 2, 50, 200],
                      [(0, 0, 32, 32), (n - 32, 0, 32, 32), (0, n - 32, 32, 32),
                       (40000, 20000, 32, 32), (32768 - 16, 32768 - 16, 32, 32)])
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_max_block_level_k16(rule):
+    """The largest block-space level a step accepts: k = 16 with 2 x 2 tiles
+    (k - r = 15, 3^15 = 14,348,907 workgroups), two steps, sampled."""
+    k, r = 16, 1
+    n = 1 << k
+    _full_size_check(k, rule, r, [1, 2],
+                     [(0, 0, 24, 24), (n - 24, n - 24, 24, 24), (12345, 54321, 24, 24)])
 
 
 def test_heat_error_metric_sane():
