@@ -19,7 +19,7 @@ Also on the same JSON line:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
                     [--no-cpu] [--no-bb] [--no-k16] [--no-batch]
-                    [--serve SECONDS] [--copy-calibration]
+                    [--serve SECONDS] [--sweep-k] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -45,7 +45,8 @@ ALPHA = 0.2
 BYTES_PER_CELL = {0: 2.0 * (4.0 / 3.0) ** 6, 1: 8.0 * (4.0 / 3.0) ** 4}
 WORKLOADS = {"k14": 14, "k16": 16}
 RULE_NAME = {0: "ca", 1: "heat"}
-KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip"]
+KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
+              "device_march.hpp", "step_march.hip"]
 
 
 def kernel_hash() -> str:
@@ -124,26 +125,52 @@ class Gasket:
 
 
 def steps_per_launch(tuning):
-    """Steps one launch advances: 4 or 2 for fused launches, else 1."""
+    """Steps one launch advances: 8, 4 or 2 for fused launches, else 1."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    return 4 if fl & 16 else (2 if fl & 8 else 1)
+    return 8 if fl & 64 else (4 if fl & 16 else (2 if fl & 8 else 1))
 
 
-def roofline(rule, cells, sec_per_step, tuning, traffic=None, kernel=""):
+def kernel_name(tuning):
+    """Name of the step kernel template a tuning launches."""
+    fl = tuning[3] if len(tuning) > 3 else 0
+    return "march_kernel" if fl & 32 else "step_kernel"
+
+
+def roofline(rule, cells, sec_per_launch, tuning, traffic=None, kernel=""):
     """Roofline of one launch.  A launch reads and writes every member
-    segment once whether it advances one step or two (the intermediate step
-    of a fused launch stays in LDS), so its algorithmic bytes are the
-    per-cell figure times 3^k either way; its duration is the per-step time
-    times the steps it advances."""
+    segment once however many steps it advances (intermediate steps stay in
+    LDS or registers), so its algorithmic bytes are the per-cell figure
+    times 3^k; `sec_per_launch` is the measured average duration of a launch
+    of the tuned step count."""
     spl = steps_per_launch(tuning)
     alg = BYTES_PER_CELL[rule] * cells
-    launch = sec_per_step * spl
-    achieved = alg / launch / 1e9
+    achieved = alg / sec_per_launch / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
             "steps_per_launch": spl, "alg_bytes_per_launch": alg,
-            "avg_launch_us": launch * 1e6,
-            "per_step_equivalent_GBs": alg / sec_per_step / 1e9}
+            "avg_launch_us": sec_per_launch * 1e6,
+            "per_step_equivalent_GBs": alg * spl / sec_per_launch / 1e9}
+
+
+def launch_time(g, rule, steps, map_=None, tuning=None):
+    """Average launch duration of the tuned T-step kernel: HIP events around
+    a run of 2T * floor(steps / 2T) steps, which the library issues as T-step
+    launches only."""
+    t = tuning or g.tunings[rule]
+    T = steps_per_launch(t)
+    n = 2 * T * max(1, steps // (2 * T))
+    return g.time(rule, n, map_, t) * T
+
+
+def bb_tuning(g, rule, r, lam=None):
+    """The bounding-box launch compared with lambda's: lambda's engine and
+    flags at tile size r where that tile size takes them, else one step per
+    launch with whole segments."""
+    t = lam or g.tunings[rule]
+    fl = t[3]
+    if (1 << r) * (1 if rule == 0 else 4) < 16:
+        fl = 3
+    return (r, 256 if (r >= 3 or fl & 32) else 64, g.F.ORDER_NATURAL, fl)
 
 
 def bb_leg(g, per_launch, nsteps):
@@ -151,11 +178,18 @@ def bb_leg(g, per_launch, nsteps):
     out = {}
     for rule in (0, 1):
         res = {}
+        lds = {}
         for r in range(max(2, g.k - 15), 8):
-            fused = (1 << r) * (1 if rule == 0 else 4) >= 16
-            tb = (r, 256 if r >= 4 else 64, F.ORDER_NATURAL, 19 if fused else 3)
-            g.run(rule, 2, F.MAP_BB, tb)
+            tb = bb_tuning(g, rule, r)
+            g.run(rule, 2 * steps_per_launch(tb), F.MAP_BB, tb)
             res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
+            if tb[3] & F.FLAG_MARCH:
+                # the LDS engine (one workgroup per block, empty blocks exit
+                # at once) may suit the bounding box better
+                tl = (r, 256 if r >= 3 else 64, F.ORDER_NATURAL, 19 if rule == 1 else 11)
+                g.run(rule, 8, F.MAP_BB, tl)
+                lds[r] = g.time(rule, nsteps, F.MAP_BB, tl)
+                res[r] = min(res[r], lds[r])
         lam = per_launch[rule]
         best = min(res, key=res.get)
         same = res.get(g.tunings[rule][0])
@@ -166,17 +200,69 @@ def bb_leg(g, per_launch, nsteps):
             "speedup_same_r": None if same is None else same / lam,
             "speedup_best": res[best] / lam,
             "bb_us_by_r": {str(r): v * 1e6 for r, v in res.items()},
+            "bb_lds_engine_us_by_r": {str(r): v * 1e6 for r, v in lds.items()},
         }
+    return out
+
+
+def copy_ceiling(torch, nbytes=1 << 32, reps=5):
+    """Device-to-device copy rate (read + write bytes per second): the
+    practical ceiling for a one-step stencil, which moves copy-like traffic."""
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / sec / 1e9
+
+
+def sweep_k_leg(F, torch, kmin=8, kmax=16):
+    """lambda vs bounding box per level, each at its best launch: lambda
+    autotuned, the bounding box over tile sizes 16..128 (launch order, whole
+    segments, fused steps where allowed).  Seconds per step."""
+    out = {}
+    for k in range(kmin, kmax + 1):
+        g = Gasket(F, torch, k)
+        g.autotune()
+        steps = 64 if k >= 15 else 256
+        row = {}
+        for rule in (0, 1):
+            g.run(rule, 8)
+            lam = g.time(rule, steps)
+            bbs = {}
+            for r in range(4, min(k, 7) + 1):
+                if k - r > 15:
+                    continue
+                tb = bb_tuning(g, rule, r)
+                g.run(rule, 16, F.MAP_BB, tb)
+                bbs[r] = g.time(rule, steps, F.MAP_BB, tb)
+            best = min(bbs, key=bbs.get)
+            row[RULE_NAME[rule]] = {"lambda_us": lam * 1e6, "lambda_tuning": list(g.tunings[rule]),
+                                    "bb_us": bbs[best] * 1e6, "bb_r": best,
+                                    "speedup": bbs[best] / lam}
+        out[str(k)] = row
+        g.free()
     return out
 
 
 def mfma_leg(g, steps):
     """lambda computed by two ballots vs by the matrix-core product
-    (Variant 1), same tile launch, same level."""
+    (Variant 1), same tile launch (the LDS engine: the matrix-core map has no
+    march form), same level."""
     F = g.F
     out = {}
     for rule in (0, 1):
         t = g.tunings[rule]
+        if t[3] & F.FLAG_MARCH:
+            t = (t[0], 256 if t[0] >= 3 else 64, t[2], 11 if rule == 0 else 17)
         g.run(rule, 8, F.MAP_MFMA, t)
         mf = g.time(rule, steps, F.MAP_MFMA, t)
         g.run(rule, 8, F.MAP_LAMBDA, t)
@@ -191,19 +277,19 @@ def k16_leg(F, torch, steps):
     g.autotune()
     out = {"k": 16, "cells": g.cells, "steps": steps}
     for rule in (0, 1):
-        g.run(rule, 4)
+        g.run(rule, 16)
         sec = g.time(rule, steps)
-        rf = roofline(rule, g.cells, sec, g.tunings[rule], read_traffic("k16", RULE_NAME[rule]),
-                      f"lambda_step_{RULE_NAME[rule]}")
+        rf = roofline(rule, g.cells, launch_time(g, rule, steps), g.tunings[rule],
+                      read_traffic("k16", RULE_NAME[rule]), kernel_name(g.tunings[rule]))
         out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]),
                                 "cells_per_s": g.cells / sec, "roofline": rf}
     # bounding box at lambda's tile size and at rho = 32 (the paper's best)
     for rule in (0, 1):
         r = g.tunings[rule][0]
         for rr in sorted({r, 5}):
-            tb = (rr, 256, F.ORDER_NATURAL, 19)
-            g.run(rule, 2, F.MAP_BB, tb)
-            sec = g.time(rule, max(4, steps // 4), F.MAP_BB, tb)
+            tb = bb_tuning(g, rule, rr)
+            g.run(rule, 16, F.MAP_BB, tb)
+            sec = g.time(rule, max(16, steps // 2), F.MAP_BB, tb)
             out[RULE_NAME[rule]][f"bb_r{rr}_us"] = sec * 1e6
         out[RULE_NAME[rule]]["lambda_us"] = 1e6 * g.cells / out[RULE_NAME[rule]]["cells_per_s"]
     g.free()
@@ -344,6 +430,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-gasket batch leg")
     ap.add_argument("--serve", type=float, default=0.0,
                     help="seconds of Poisson arrivals for the serving leg (0 = skip)")
+    ap.add_argument("--sweep-k", action="store_true",
+                    help="add lambda vs bounding box for levels 8..16 (about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB with a plain device copy (counter calibration)")
     args = ap.parse_args()
@@ -384,18 +472,23 @@ def main() -> int:
     ms_ca, ms_heat = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     total_ms = ms_ca + ms_heat
     value = 2.0 * g.cells * K / (total_ms / 1e3)
-    per_launch = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}
+    per_launch = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}  # seconds per step
     dom = 1 if per_launch[1] >= per_launch[0] else 0
-    rf = roofline(dom, g.cells, per_launch[dom], g.tunings[dom],
-                  read_traffic(args.workload, RULE_NAME[dom]), f"lambda_step_{RULE_NAME[dom]}")
+    launch_sec = {r: launch_time(g, r, K) for r in (0, 1)}
+    rfs = {r: roofline(r, g.cells, launch_sec[r], g.tunings[r],
+                       read_traffic(args.workload, RULE_NAME[r]), kernel_name(g.tunings[r]))
+           for r in (0, 1)}
+    rf = rfs[dom]
 
     bb = None if args.no_bb else bb_leg(g, per_launch, max(10, min(K, 200)))
     mfma = None if args.no_bb else mfma_leg(g, max(16, min(K, 400)))
     k, cells, tunings = g.k, g.cells, dict(g.tunings)
     g.free()
-    k16 = None if (args.no_k16 or k == 16) else k16_leg(F, torch, 50)
+    k16 = None if (args.no_k16 or k == 16) else k16_leg(F, torch, 64)
     batch = None if args.no_batch else batch_leg(F, torch)
     serve = serve_leg(F, torch, args.serve) if args.serve > 0 else None
+    sweep = sweep_k_leg(F, torch) if args.sweep_k else None
+    ceiling = None if args.no_bb else copy_ceiling(torch)
 
     cpu = None
     if not args.no_cpu:
@@ -428,9 +521,11 @@ def main() -> int:
         "per_rule": {RULE_NAME[r]: {"us_per_step": per_launch[r] * 1e6,
                                     "cells_per_s": cells / per_launch[r],
                                     "steps_per_launch": steps_per_launch(tunings[r]),
-                                    "roofline": roofline(r, cells, per_launch[r], tunings[r])}
+                                    "roofline": rfs[r]}
                      for r in (0, 1)},
         "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
+        "lambda_vs_bb_by_k": sweep,
+        "device_copy_GBs": ceiling,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_hash(),
     }

@@ -82,6 +82,19 @@ extern "C" {
                                    steps - 2T*floor(steps/2T) steps run one per
                                    launch */
 #define FRACTAL_FLAG_FUSE4 16   /* as FUSE2 with four steps per launch */
+#define FRACTAL_FLAG_MARCH 32   /* register-march engine (lambda and BB maps):
+                                   a wavefront takes several tiles side by
+                                   side, one 16-byte chunk column per lane
+                                   plus halo lanes, and walks down the tile
+                                   rows computing T = 1, 2, 4 or 8 steps
+                                   (FUSE2 / FUSE4 / FUSE8) in registers, with
+                                   no LDS.  Needs FRACTAL_FLAG_SEGMENTS and
+                                   tile rows of >= 16 bytes.  Steps are
+                                   split into launches of T steps, then
+                                   smaller powers of two, with a launch count
+                                   of the parity of steps */
+#define FRACTAL_FLAG_FUSE8 64   /* eight steps per launch (with
+                                   FRACTAL_FLAG_MARCH only) */
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
                                      contiguous ranges of the tile list, instead
                                      of one workgroup per tile */

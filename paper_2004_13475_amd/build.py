@@ -27,7 +27,9 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 SOURCES = ["api.cpp", "step_kernels.hip", "step_lambda.hip", "step_bb.hip", "step_mfma.hip",
-           "seed.hip", "batch.hip", "batch_ca.hip", "batch_heat.hip", "serve.cpp"]
+           "step_march.hip",
+           "seed.hip", "batch.hip", "batch_ca.hip", "batch_heat.hip", "batch_march.hip",
+           "serve.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -80,26 +80,30 @@ static int default_threads(int rule, int r)
     return chunks >= 256 ? 256 : 64;
 }
 
-// Fastest launch flags measured for a tile level: whole segments always;
-// where tile rows span 16 bytes, the automaton fuses two steps per launch
-// with non-temporal stores and heat fuses four.
-static int default_flags(int rule, int r)
+// Launch flags for an explicit tile size: where tile rows span 16 bytes,
+// the register-march engine with four steps per launch (non-temporal stores
+// once the state is far beyond the caches, level >= 15); the matrix-core map
+// and narrower tiles use the LDS engine with whole segments.
+static int default_flags(int map, int k, int rule, int r)
 {
     int fl = FRACTAL_FLAG_SEGMENTS;
-    if ((1 << r) * (int)cell_bytes(rule) >= 16)
-        fl |= rule == FRACTAL_RULE_CA ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE)
-                                      : FRACTAL_FLAG_FUSE4;
+    if ((1 << r) * (int)cell_bytes(rule) >= 16) {
+        if (map == MAP_MFMA)
+            fl |= rule == FRACTAL_RULE_CA ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE)
+                                          : FRACTAL_FLAG_FUSE4;
+        else
+            fl |= FRACTAL_FLAG_MARCH | FRACTAL_FLAG_FUSE4 | (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
+    }
     return fl;
 }
 
 fractal_tuning tuning_for_r(int map, int k, int rule, int r)
 {
-    (void)k;
     fractal_tuning t;
     t.r = r;
-    t.threads = default_threads(rule, r);
+    t.flags = default_flags(map, k, rule, r);
+    t.threads = (t.flags & FRACTAL_FLAG_MARCH) ? 256 : default_threads(rule, r);
     t.order = map == MAP_BB ? FRACTAL_ORDER_NATURAL : FRACTAL_ORDER_CURVE_XCD;
-    t.flags = default_flags(rule, r);
     return t;
 }
 
@@ -113,15 +117,18 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured at level 16 on MI355X: automaton 128 x 128 tiles (two
-// steps per launch, non-temporal stores), heat 32 x 32 tiles (four steps per
-// launch); 256 threads, omega in launch order, whole 64-byte segments.
+// launches measured on MI355X, all on the register-march engine with omega
+// in the curve order split over the dies.  Level >= 15: automaton 64 x 64
+// tiles, eight steps per launch; heat 16 x 16 tiles, four steps; both with
+// non-temporal stores.  Below: automaton 128 x 128 and heat 32 x 32 tiles,
+// four steps, plain stores (the state stays in the last-level cache).
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? 7 : 5);
+    const bool big = k >= 15;
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? (big ? 6 : 7) : (big ? 4 : 5));
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
-    t.threads = r >= 3 ? 256 : 64;
-    t.order = FRACTAL_ORDER_NATURAL;
+    if ((t.flags & FRACTAL_FLAG_MARCH) && big && rule == FRACTAL_RULE_CA)
+        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8;
     return t;
 }
 
@@ -157,17 +164,22 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "threads=%d must be 64 or 256", t->threads);
     if (t->order < FRACTAL_ORDER_NATURAL || t->order > FRACTAL_ORDER_CURVE_XCD)
         return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
-    const int fuse = t->flags & (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4);
-    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2 |
-                     FRACTAL_FLAG_FUSE4))
+    const int fuse = t->flags & kFuseFlags;
+    const bool march = (t->flags & FRACTAL_FLAG_MARCH) != 0;
+    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
-    if (fuse == (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4))
-        return set_error(FRACTAL_E_INVAL, "FUSE2 and FUSE4 are exclusive");
-    if (fuse && !(t->flags & FRACTAL_FLAG_SEGMENTS))
-        return set_error(FRACTAL_E_INVAL, "fused launches need FRACTAL_FLAG_SEGMENTS");
-    if (fuse && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
-        return set_error(FRACTAL_E_INVAL, "fused launches need tile rows of >= 16 bytes");
-    if (t->threads == 256 && t->r < 3)
+    if (fuse & (fuse - 1))
+        return set_error(FRACTAL_E_INVAL, "FUSE2, FUSE4 and FUSE8 are exclusive");
+    if ((fuse & FRACTAL_FLAG_FUSE8) && !march)
+        return set_error(FRACTAL_E_INVAL, "FUSE8 needs FRACTAL_FLAG_MARCH");
+    if ((fuse || march) && !(t->flags & FRACTAL_FLAG_SEGMENTS))
+        return set_error(FRACTAL_E_INVAL, "fused and march launches need FRACTAL_FLAG_SEGMENTS");
+    if ((fuse || march) && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
+        return set_error(FRACTAL_E_INVAL,
+                         "fused and march launches need tile rows of >= 16 bytes");
+    if (march && map == MAP_MFMA)
+        return set_error(FRACTAL_E_INVAL, "the matrix-core map has no march form");
+    if (t->threads == 256 && t->r < 3 && !march)
         return set_error(FRACTAL_E_INVAL, "256 threads need tiles of side >= 8");
     return FRACTAL_OK;
 }
@@ -319,7 +331,7 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         return rc;
     }
     // Few-step timings; enough launches that per-launch gaps are included.
-    const int reps = k >= 15 ? 8 : (k >= 12 ? 16 : 64); // multiples of 8 (fused pairs)
+    const int reps = k >= 15 ? 16 : (k >= 12 ? 32 : 64); // multiples of 16 (fused pairs)
     fractal_tuning best{};
     float best_ms = 1e30f;
     std::vector<fractal_tuning> cands;
@@ -340,10 +352,19 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                     cands.push_back(t);
                 }
         }
+        // register march: 1, 2, 4 or 8 steps per launch, with and without
+        // non-temporal stores
+        if (row_bytes >= 16)
+            for (int fuse : {0, (int)FRACTAL_FLAG_FUSE2, (int)FRACTAL_FLAG_FUSE4,
+                             (int)FRACTAL_FLAG_FUSE8})
+                for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
+                    cands.push_back(fractal_tuning{
+                        r, 256, FRACTAL_ORDER_CURVE_XCD,
+                        FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse});
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)
-        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 8, t, s);
+        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 16, t, s);
         if (!rc)
             rc = hip_error(hipEventRecord(e0, s), "event record");
         if (!rc)

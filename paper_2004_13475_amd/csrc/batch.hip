@@ -5,11 +5,12 @@
 // instance j owns tile ids [tile_begin_j, tile_begin_j + 3^(k_j - r)); a tile
 // id is turned into (instance, local omega) with the per-instance offset
 // table and then into a tile by that instance's lambda.  Each launch slot is
-// one launch per class (one or two steps each); the launches of a
+// one launch per class (of 1, 2, 4 or 8 steps); the launches of a
 // fractal_batch_step call are captured once into a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -42,20 +43,23 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
             t.threads = forced->threads;
         t.flags = forced->flags;
     }
-    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_FUSE2 |
-               FRACTAL_FLAG_FUSE4;
-    if (t.flags & (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4))
-        t.flags |= FRACTAL_FLAG_SEGMENTS; // fused launches move whole segments
+    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags;
+    if (t.flags & (FRACTAL_FLAG_MARCH | kFuseFlags))
+        t.flags |= FRACTAL_FLAG_SEGMENTS; // fused and march launches move whole segments
     if (t.r > k)
         t.r = k;
     if (t.r > kMaxR)
         t.r = kMaxR;
     if (k - t.r > kMaxBlockLevel)
         t.r = k - kMaxBlockLevel;
-    if (t.threads == 256 && t.r < 3)
+    if ((1 << t.r) * (int)cell_bytes(rule) < 16) // fused and march launches need 16-byte rows
+        t.flags &= ~(kFuseFlags | FRACTAL_FLAG_MARCH);
+    if (!(t.flags & FRACTAL_FLAG_MARCH) && (t.flags & FRACTAL_FLAG_FUSE8))
+        t.flags = (t.flags & ~FRACTAL_FLAG_FUSE8) | FRACTAL_FLAG_FUSE4; // LDS engine: 4 at most
+    if (t.flags & FRACTAL_FLAG_MARCH)
+        t.threads = 256;
+    else if (t.threads == 256 && t.r < 3)
         t.threads = 64;
-    if ((1 << t.r) * (int)cell_bytes(rule) < 16) // fused launches need 16-byte rows
-        t.flags &= ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4);
     t.order = FRACTAL_ORDER_CURVE_XCD;
     return t;
 }
@@ -75,15 +79,32 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
         Class c;
         std::tie(c.rule, c.r, c.threads, c.flags) = g.first;
         const int T = launch_steps_of(c.flags);
-        auto fused_of = [&](size_t i) { return T > 1 ? 2 * (items[i].steps / (2 * T)) : 0; };
-        auto single_of = [&](size_t i) { return items[i].steps - T * fused_of(i); };
-        auto emit = [&](List &list, std::vector<size_t> ids, auto count_of) {
-            std::stable_sort(ids.begin(), ids.end(),
-                             [&](size_t a, size_t b) { return count_of(a) > count_of(b); });
+        const bool march = (c.flags & FRACTAL_FLAG_MARCH) != 0;
+        // launches per size: counts[j] of T >> j steps (LDS engine: T and 1 only)
+        std::vector<std::array<int, kMaxListsPerItem>> counts(items.size());
+        for (size_t i : g.second) {
+            int cnt[kMaxListsPerItem] = {0, 0, 0, 0};
+            const int steps = items[i].steps;
+            if (march) {
+                march_split(steps, T, cnt);
+            } else {
+                const int f = T > 1 ? 2 * (steps / (2 * T)) : 0;
+                cnt[0] = f;
+                cnt[T > 1 ? (T == 2 ? 1 : 2) : 0] += steps - T * f;
+            }
+            std::copy(cnt, cnt + kMaxListsPerItem, counts[i].begin());
+        }
+        std::vector<int> before(items.size(), 0); // launches in earlier lists
+        for (int j = 0; j < kMaxListsPerItem && (T >> j) >= 1; ++j) {
+            List list;
+            list.T = T >> j;
             list.first = at;
+            std::vector<size_t> ids = g.second;
+            std::stable_sort(ids.begin(), ids.end(),
+                             [&](size_t a, size_t b) { return counts[a][j] > counts[b][j]; });
             uint64_t acc = 0;
             for (size_t i : ids) {
-                if (count_of(i) <= 0)
+                if (counts[i][j] <= 0)
                     break;
                 const BatchItem &it = items[i];
                 BatchEntry &e = host[at++];
@@ -95,18 +116,21 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
                 e.rule = it.rule;
                 e.phase = it.phase & 1;
                 e.alpha = it.alpha;
-                e.fused = fused_of(i);
-                list.count.push_back(count_of(i));
+                e.flip0 = before[i];
+                list.count.push_back(counts[i][j]);
                 list.prefix.push_back(acc);
                 acc += pow3_u64(it.k - c.r);
             }
             list.prefix.push_back(acc);
-        };
-        emit(c.fused, g.second, fused_of);
-        emit(c.single, g.second, single_of);
-        c.fmax = c.fused.count.empty() ? 0 : c.fused.count[0];
-        const int smax = c.single.count.empty() ? 0 : c.single.count[0];
-        slots_ = std::max(slots_, c.fmax + smax);
+            for (size_t i : g.second)
+                before[i] += counts[i][j];
+            if (!list.count.empty())
+                c.lists.push_back(std::move(list));
+        }
+        int total = 0;
+        for (const List &l : c.lists)
+            total += l.slots();
+        slots_ = std::max(slots_, total);
         classes_.push_back(std::move(c));
     }
     entries_ = at;
@@ -115,37 +139,59 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
 int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hipStream_t s) const
 {
     for (const Class &c : classes_) {
-        const bool in_fused = t < c.fmax;
-        const List &list = in_fused ? c.fused : c.single;
-        const int j = in_fused ? t : t - c.fmax; // launch index within the list
+        const List *lp = nullptr;
+        int j = t; // launch index within the list
+        for (const List &l : c.lists) {
+            if (j < l.slots()) {
+                lp = &l;
+                break;
+            }
+            j -= l.slots();
+        }
+        if (!lp)
+            continue;
+        const List &list = *lp;
         size_t active = list.count.size();
         while (active > 0 && list.count[active - 1] <= j)
             --active;
         if (active == 0)
             continue;
         const uint64_t total = list.prefix[active];
-        const int flags =
-            in_fused ? c.flags : (c.flags & ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4));
-        TileFn tf = nullptr;
-        PersistFn pf = nullptr;
-        if (c.rule == FRACTAL_RULE_CA)
-            pick_batch_ca(c.r, c.threads, flags, &tf, &pf);
-        else
-            pick_batch_heat(c.r, c.threads, flags, &tf, &pf);
-        if (!tf || !pf)
-            return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d flags=%d", c.r,
-                             c.threads, flags);
         const BatchEntry *tab = d_table + list.first;
-        if (!persistent && total < 0x7FFFFFFFull) {
-            const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
-            const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
-            hipLaunchKernelGGL(tf, dim3(gx, gy), dim3(c.threads), 0, s, tab, (int)active,
-                               (uint32_t)total, j);
+        if (c.flags & FRACTAL_FLAG_MARCH) {
+            const bool nt = (c.flags & FRACTAL_FLAG_NT_STORE) != 0;
+            BatchMarchFn fn = pick_batch_march(c.rule, c.r, list.T, nt);
+            const int P = march_tiles_per_wave(c.rule, c.r, list.T);
+            if (!fn || P < 1)
+                return set_error(FRACTAL_E_INVAL, "no batch march kernel for rule %d r %d T %d",
+                                 c.rule, c.r, list.T);
+            const int bl = march_band_log(c.rule, c.r, list.T, total);
+            const uint64_t waves = ((total << bl) + (uint64_t)P - 1) / (uint64_t)P;
+            const uint64_t grid = (waves + 3) / 4;
+            hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), 0, s, tab, (int)active, total,
+                               bl, j);
         } else {
-            const uint64_t grid = std::min<uint64_t>(total, (uint64_t)batch_grid_size() *
-                                                                (c.threads == 64 ? 4 : 1));
-            hipLaunchKernelGGL(pf, dim3((unsigned)grid), dim3(c.threads), 0, s, tab,
-                               (int)active, total, j);
+            const int flags = list.T > 1 ? c.flags : (c.flags & ~kFuseFlags);
+            TileFn tf = nullptr;
+            PersistFn pf = nullptr;
+            if (c.rule == FRACTAL_RULE_CA)
+                pick_batch_ca(c.r, c.threads, flags, &tf, &pf);
+            else
+                pick_batch_heat(c.r, c.threads, flags, &tf, &pf);
+            if (!tf || !pf)
+                return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d flags=%d",
+                                 c.r, c.threads, flags);
+            if (!persistent && total < 0x7FFFFFFFull) {
+                const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
+                const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
+                hipLaunchKernelGGL(tf, dim3(gx, gy), dim3(c.threads), 0, s, tab, (int)active,
+                                   (uint32_t)total, j);
+            } else {
+                const uint64_t grid = std::min<uint64_t>(
+                    total, (uint64_t)batch_grid_size() * (c.threads == 64 ? 4 : 1));
+                hipLaunchKernelGGL(pf, dim3((unsigned)grid), dim3(c.threads), 0, s, tab,
+                                   (int)active, total, j);
+            }
         }
         int rc = hip_error(hipGetLastError(), "batch kernel launch");
         if (rc)
@@ -198,10 +244,10 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         if (tuning->threads != 0 && tuning->threads != 64 && tuning->threads != 256)
             return set_error(FRACTAL_E_INVAL, "tuning threads=%d (0, 64 or 256)",
                              tuning->threads);
-        if (tuning->flags &
-            ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE |
-              FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4) ||
-            ((tuning->flags & FRACTAL_FLAG_FUSE2) && (tuning->flags & FRACTAL_FLAG_FUSE4)))
+        const int fuse = tuning->flags & kFuseFlags;
+        if ((tuning->flags & ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS |
+                               FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags)) ||
+            (fuse & (fuse - 1)))
             return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
     }
     // validate every instance and pick its tile launch
@@ -237,7 +283,7 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     reap_pending();
     hipStream_t s = static_cast<hipStream_t>(stream);
     BatchEntry *host = nullptr;
-    const size_t cap = 2 * (size_t)count; // an item can sit in both lists of its class
+    const size_t cap = kMaxListsPerItem * (size_t)count; // one entry per list of its class
     int rc = hip_error(hipHostMalloc((void **)&host, sizeof(BatchEntry) * cap), "pinned table");
     if (rc)
         return rc;

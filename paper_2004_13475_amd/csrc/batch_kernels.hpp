@@ -27,14 +27,14 @@ __device__ __forceinline__ int find_instance(const BatchEntry *__restrict__ tabl
     return lo;
 }
 
-// `slot` is the index of this launch within the item's two-step launches
-// (fused kernels) or within its single steps; every launch flips the buffers.
+// `slot` is the index of this launch within the item's launches of this
+// list's size; every launch flips the buffers.
 template <int RULE, int R, int NT, int FL>
 __device__ __forceinline__ void batch_tile(uint8_t *lds, const BatchEntry &e, uint32_t L,
                                            int slot)
 {
     const TileXY t = lambda_wave_curve(L, e.k - R);
-    const int flips = fused_steps<FL>() > 1 ? slot : e.fused + slot;
+    const int flips = e.flip0 + slot;
     const bool odd = ((e.phase + flips) & 1) != 0;
     StepParams p;
     p.src = odd ? e.buf1 : e.buf0;

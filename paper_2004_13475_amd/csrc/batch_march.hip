@@ -1,0 +1,90 @@
+// batch_march.hip -- the register-march engine over a batch work list: each
+// lane group finds its instance by the tile prefix, then walks that
+// instance's tile as the single-gasket march kernel does.
+#include <hip/hip_runtime.h>
+
+#include "batch_kernels.hpp"
+#include "device_march.hpp"
+#include "internal.hpp"
+
+namespace fractal {
+
+// Items (tile, band) of the list in order, P per wavefront; tile id w of the
+// list is local tile w - tile_begin of its instance, taken along the
+// gasket's self-similar order.  `slot` is the index of this launch within
+// the list (the entry's flip0 + slot launches precede it).
+template <int RULE, int R, int T, int HL, int FL, int WPE, int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+void batch_march_kernel(const BatchEntry *__restrict__ table, int count, uint64_t total,
+                        int band_log, int slot)
+{
+    using M = MGeom<RULE, R, T, HL>;
+    static_assert(M::VALID, "march shape");
+    const MarchLane<RULE, R, T, HL> ln;
+    const uint32_t wg = xcd_chunk(blockIdx.x, gridDim.x);
+    const uint32_t wave = wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t item = (uint64_t)wave * M::P + ln.grp;
+    const uint64_t w = item >> band_log;
+    const int band = (int)(item & ((1u << band_log) - 1u));
+    const bool active = ln.grp < (uint32_t)M::P && w < total;
+    if (__builtin_amdgcn_ballot_w64(active) == 0u)
+        return;
+    const uint8_t *src = nullptr;
+    uint8_t *dst = nullptr;
+    int k = R;
+    float alpha = 0.0f;
+    TileXY t{0u, 0u};
+    if (active) {
+        const BatchEntry e = table[find_instance(table, count, w)];
+        t = lambda_lane((uint32_t)(w - e.tile_begin), e.k - R, FRACTAL_ORDER_CURVE);
+        const bool odd = ((e.phase + e.flip0 + slot) & 1) != 0;
+        src = odd ? e.buf1 : e.buf0;
+        dst = odd ? e.buf0 : e.buf1;
+        k = e.k;
+        alpha = e.alpha;
+    }
+    march_walk<RULE, R, T, HL, FL, D>(src, dst, k, alpha, t, band, band_log, active, ln.col);
+}
+
+template <int RULE, int R, int T, int FL>
+static BatchMarchFn bm_fn()
+{
+    constexpr int HL = march_hl(RULE, T);
+    if constexpr (MGeom<RULE, R, T, HL>::VALID)
+        return batch_march_kernel<RULE, R, T, HL, FL, march_wpe(T), march_depth(RULE, T)>;
+    else
+        return nullptr;
+}
+
+template <int RULE, int FL>
+static BatchMarchFn bm_pick(int r, int T)
+{
+    switch (r) {
+#define FRACTAL_BM_R(RR)                                                                           \
+    case RR:                                                                                       \
+        switch (T) {                                                                               \
+        case 1: return bm_fn<RULE, RR, 1, FL>();                                                   \
+        case 2: return bm_fn<RULE, RR, 2, FL>();                                                   \
+        case 4: return bm_fn<RULE, RR, 4, FL>();                                                   \
+        case 8: return bm_fn<RULE, RR, 8, FL>();                                                   \
+        default: return nullptr;                                                                   \
+        }
+        FRACTAL_BM_R(2)
+        FRACTAL_BM_R(3)
+        FRACTAL_BM_R(4)
+        FRACTAL_BM_R(5)
+        FRACTAL_BM_R(6)
+        FRACTAL_BM_R(7)
+#undef FRACTAL_BM_R
+    default: return nullptr;
+    }
+}
+
+BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt)
+{
+    if (rule == FRACTAL_RULE_CA)
+        return nt ? bm_pick<RULE_CA, TILE_NT_STORE>(r, T) : bm_pick<RULE_CA, 0>(r, T);
+    return nt ? bm_pick<RULE_HEAT, TILE_NT_STORE>(r, T) : bm_pick<RULE_HEAT, 0>(r, T);
+}
+
+} // namespace fractal

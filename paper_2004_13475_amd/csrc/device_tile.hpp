@@ -487,6 +487,10 @@ __device__ __forceinline__ void fused_step(uint8_t *lds, const StepParams &p, ui
         uint32_t out[G::W];
         if (y < 0 || y >= (int64_t)n || xc < 0 || xc >= (int64_t)n ||
             ((((uint32_t)xc >> G::CLOG) & ((uint32_t)y >> G::CLOG)) != 0u)) {
+            // 0 in the staged buffer already, and in the other one from
+            // step 1 on
+            if (t > 1)
+                continue;
 #pragma unroll
             for (int w = 0; w < G::W; ++w)
                 out[w] = 0u;

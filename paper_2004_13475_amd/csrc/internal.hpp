@@ -61,11 +61,35 @@ StepFn pick_step_lambda(int rule, int r, int threads, int flags);
 StepFn pick_step_bb(int rule, int r, int threads, int flags);
 StepFn pick_step_mfma(int rule, int r, int threads, int flags);
 
-// Steps one launch advances under these flags (1, 2 or 4).
+// Steps one launch advances under these flags (1, 2, 4 or 8).
 inline int launch_steps_of(int flags)
 {
-    return (flags & FRACTAL_FLAG_FUSE4) ? 4 : ((flags & FRACTAL_FLAG_FUSE2) ? 2 : 1);
+    return (flags & FRACTAL_FLAG_FUSE8)   ? 8
+           : (flags & FRACTAL_FLAG_FUSE4) ? 4
+           : (flags & FRACTAL_FLAG_FUSE2) ? 2
+                                          : 1;
 }
+constexpr int kFuseFlags = FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8;
+
+// Arguments of one register-march launch (FRACTAL_FLAG_MARCH).
+struct MarchArgs {
+    const uint8_t *src;
+    uint8_t *dst;
+    int k;
+    float alpha;
+    int rb;         // block level k - r
+    int order;      // FRACTAL_ORDER_*
+    uint32_t total; // tiles in the map's id space (3^rb, or 4^rb for BB)
+    int band_log;   // log2 of the bands each tile is cut into
+};
+typedef void (*MarchFn)(MarchArgs);
+// Kernel for (map, rule, r, T steps, non-temporal stores); nullptr if none.
+MarchFn pick_march(int map, int rule, int r, int T, bool nt);
+// Tiles one wavefront handles (0: no march kernel for this shape).
+int march_tiles_per_wave(int rule, int r, int T);
+int march_band_log(int rule, int r, int T, uint64_t tiles);
+int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
+                 const fractal_tuning &t, hipStream_t s);
 
 // Launch `steps` step kernels (validated arguments).
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
@@ -92,9 +116,11 @@ struct BatchEntry {
     int32_t rule;
     int32_t phase; // buffer holding the state at the start (its parity)
     float alpha;
-    int32_t fused; // two-step launches this instance makes in this sequence
+    int32_t flip0; // launches this instance makes before this list's first
 };
 static_assert(sizeof(BatchEntry) == 48, "BatchEntry layout");
+// An instance sits in at most one list per launch size (8, 4, 2, 1 steps).
+constexpr int kMaxListsPerItem = 4;
 
 // One gasket advanced by a batched launch sequence.
 struct BatchItem {
@@ -107,16 +133,20 @@ struct BatchItem {
 };
 
 // Instances grouped by launch class (rule, r, threads, step flags).  A class
-// with T-step launches (T = 2 or 4) gives each item f = 2 floor(steps / 2T)
-// of them (an even number, so the result lands in buf[steps & 1]) and then
-// steps - T f single steps.  Each class keeps a list for its two-step launches (items
-// sorted by f) and one for its single steps (sorted by count), so the items
-// taking part in any launch form a prefix of the list.  Launch slot t runs,
-// per class, its two-step launch t or single-step launch t - F (F = the
-// class's largest f).
+// splits each item's steps into launches of T steps (the class's largest),
+// then smaller ones: LDS-engine classes give an item 2 floor(steps / 2T)
+// T-step launches and single steps for the rest; march classes (which have
+// every power of two up to T) take as many T-step launches as fit, the rest
+// in powers of two, and split the largest launch in two where the count's
+// parity differs from the steps' (so the result lands in buf[steps & 1]).
+// A class keeps one list per launch size, largest first, each sorted by how
+// many launches of that size an item makes, so the items taking part in any
+// launch form a prefix of the list.  Launch slot t runs, per class, launch
+// t - (slots of the earlier lists) of the list it falls in.
 class BatchPlan {
   public:
-    // Fills `host` (capacity >= 2 * items.size()) and records the classes.
+    // Fills `host` (capacity >= kMaxListsPerItem * items.size()) and records
+    // the classes.
     void build(const std::vector<BatchItem> &items, BatchEntry *host);
     // Launch slot t of every class that has work in it.
     int launch_slot(const BatchEntry *d_table, int t, bool persistent, hipStream_t s) const;
@@ -125,19 +155,28 @@ class BatchPlan {
 
   private:
     struct List {
+        int T = 1;                    // steps per launch
         size_t first = 0;
         std::vector<int> count;       // per entry: launches it takes part in (descending)
         std::vector<uint64_t> prefix; // tile prefix, size count.size() + 1
+        int slots() const { return count.empty() ? 0 : count[0]; }
     };
     struct Class {
         int rule, r, threads, flags;
-        List fused, single;
-        int fmax = 0;
+        std::vector<List> lists;
     };
     std::vector<Class> classes_;
     int slots_ = 0;
     size_t entries_ = 0;
 };
+
+// Launch sizes of `steps` steps on the march engine with at most Tmax steps
+// per launch: counts[j] launches of Tmax >> j steps.
+void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem]);
+
+// Batched march kernel for (rule, r, T steps, non-temporal stores).
+typedef void (*BatchMarchFn)(const BatchEntry *, int, uint64_t, int, int);
+BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt);
 
 // Batched step kernels of one rule for (r, threads, flags): one workgroup
 // per tile (tf) and persistent (pf); nullptr if not instantiated.

@@ -81,7 +81,7 @@ class Server {
         device_ = dev;
         // header of the arena: two device tables (double-buffered) and the
         // per-slot checksums; the rest holds request states
-        const size_t table_bytes = sizeof(BatchEntry) * 2 * (size_t)(max_slots_ + 1);
+        const size_t table_bytes = sizeof(BatchEntry) * kMaxListsPerItem * (size_t)(max_slots_ + 1);
         table_off_[0] = 0;
         table_off_[1] = align(table_bytes);
         sums_off_ = table_off_[1] + align(table_bytes);

@@ -53,11 +53,13 @@ int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
 {
     // T-step launches come in pairs so that the result still lands in
     // buf[steps & 1]; the remaining 0..2T-1 steps run one step per launch.
+    if (t.flags & FRACTAL_FLAG_MARCH)
+        return launch_march(map, k, rule, alpha, b0, b1, steps, t, s);
     const int T = launch_steps_of(t.flags);
     const bool fuse = T > 1;
     const int fused = fuse ? 2 * (steps / (2 * T)) : 0;
     StepFn fn1 = pick_step(map, rule, t.r, t.threads,
-                           t.flags & ~(FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4));
+                           t.flags & ~kFuseFlags);
     StepFn fn2 = fuse ? pick_step(map, rule, t.r, t.threads, t.flags) : nullptr;
     if (!fn1 || (fuse && !fn2))
         return set_error(FRACTAL_E_INVAL, "no kernel for map %d rule %d r %d threads %d flags %d",

@@ -33,9 +33,17 @@ def _mix(count, seed, kmin, kmax, max_steps):
     return specs
 
 
+MARCH = F.FLAG_MARCH | F.FLAG_SEGMENTS
+
+
 @pytest.mark.parametrize("tuning", [None, (4, 64, 2, 0), (5, 64, 2, F.FLAG_PERSISTENT),
                                     (2, 64, 0, F.FLAG_PERSISTENT), (5, 256, 0, 11), (6, 0, 0, 19),
-                                    (5, 64, 0, 19 | F.FLAG_PERSISTENT)])
+                                    (5, 64, 0, 19 | F.FLAG_PERSISTENT),
+                                    (F.R_AUTO, 0, 0, MARCH | F.FLAG_FUSE8),
+                                    (5, 0, 0, MARCH | F.FLAG_NT_STORE | F.FLAG_FUSE4),
+                                    (4, 256, 0, MARCH | F.FLAG_FUSE2),
+                                    (7, 64, 0, MARCH),
+                                    (6, 0, 0, MARCH | F.FLAG_FUSE8 | F.FLAG_PERSISTENT)])
 def test_batch_alone_equals_in_mix(tuning):
     torch = torch_dev()
     specs = _mix(40, 3, 1, 11, 37)

@@ -181,7 +181,7 @@ def test_fused_launches(rule, map_):
                     a0, a1 = to_device(init), zeros_state(k, rule)
                     F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, th, 2, fl)
                     b0, b1 = to_device(init), zeros_state(k, rule)
-                    F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, th, 2, fl & ~8)
+                    F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, th, 2, fl & ~24)
                     _sync()
                     fa = a0 if steps % 2 == 0 else a1
                     fb = b0 if steps % 2 == 0 else b1
@@ -193,11 +193,74 @@ def test_fused_launches(rule, map_):
                         assert_match(k, rule, fa.cpu().numpy(), ref, f"fused k={k} r={r} t={steps}")
 
 
-@pytest.mark.parametrize("flags", [11, 19])
+MARCH_FUSE = (0, F.FLAG_FUSE2, F.FLAG_FUSE4, F.FLAG_FUSE8)
+
+
+@pytest.mark.parametrize("map_", [F.MAP_LAMBDA, F.MAP_BB])
+@pytest.mark.parametrize("rule", RULES)
+def test_march_launches(rule, map_):
+    """The register-march engine (1, 2, 4 or 8 steps per launch, tiles side
+    by side in a wavefront, bands of rows) gives the same bits as one step
+    per launch of the LDS engine, for every tile size it takes, every order,
+    both workgroup sizes and step counts that exercise the power-of-two tail
+    and the parity split; small levels also against the oracle."""
+    torch = torch_dev()
+    cell = 1 if rule == fi.RULE_CA else 4
+    for k in (4, 6, 8, 11):
+        init = fi.window_values(k, rule, 70 + k)
+        for r in range(0, min(k, 7) + 1):
+            if (1 << r) * cell < 16 or k - r > 15:
+                continue
+            ref_by_steps = {}
+            for steps in (1, 2, 3, 7, 8, 13, 16, 19):
+                b0, b1 = to_device(init), zeros_state(k, rule)
+                F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, 64, 2, F.FLAG_SEGMENTS)
+                _sync()
+                ref_by_steps[steps] = (b0 if steps % 2 == 0 else b1).view(torch.uint8).clone()
+            for fuse in MARCH_FUSE:
+                for (th, order, nt) in ((256, 2, 2), (64, 0, 0), (256, 1, 0)):
+                    fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | nt | fuse
+                    for steps in (1, 2, 3, 7, 8, 13, 16, 19):
+                        a0, a1 = to_device(init), zeros_state(k, rule)
+                        F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, th, order, fl)
+                        _sync()
+                        fa = a0 if steps % 2 == 0 else a1
+                        assert torch.equal(fa.view(torch.uint8), ref_by_steps[steps]), \
+                            (k, r, steps, fl, th, order)
+            if k <= 8:
+                fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_NT_STORE | F.FLAG_FUSE8
+                a0, a1 = to_device(init), zeros_state(k, rule)
+                F.step_tuned(map_, k, rule, ALPHA, a0, a1, 19, r, 256, 2, fl)
+                _sync()
+                ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 19)
+                assert_match(k, rule, a1.cpu().numpy(), ref, f"march k={k} r={r}")
+
+
+def test_march_rejects_bad_tunings():
+    """March launches need whole segments, rows of >= 16 bytes and a lambda
+    or BB map; FUSE8 needs the march engine."""
+    torch = torch_dev()
+    b0, b1 = zeros_state(6, fi.RULE_CA), zeros_state(6, fi.RULE_CA)
+    bad = [
+        (F.MAP_LAMBDA, 4, F.FLAG_MARCH),                                   # no SEGMENTS
+        (F.MAP_LAMBDA, 3, F.FLAG_MARCH | F.FLAG_SEGMENTS),                 # 8-byte rows
+        (F.MAP_MFMA, 4, F.FLAG_MARCH | F.FLAG_SEGMENTS),                   # no march form
+        (F.MAP_LAMBDA, 4, F.FLAG_SEGMENTS | F.FLAG_FUSE8),                 # FUSE8 without march
+        (F.MAP_LAMBDA, 4, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE2 | F.FLAG_FUSE8),
+    ]
+    for map_, r, fl in bad:
+        with pytest.raises(F.FractalError) as e:
+            F.step_tuned(map_, 6, fi.RULE_CA, ALPHA, b0, b1, 4, r, 64, 0, fl)
+        assert e.value.code == F.E_INVAL, (map_, r, fl)
+    del torch
+
+
+@pytest.mark.parametrize("flags", [11, 19, 35 | 16, 35 | 64])
 @pytest.mark.parametrize("rule", RULES)
 def test_fused_full_size_k16_sampled(rule, flags):
-    """Level 16 with two-step launches, 200 steps, sampled against the
-    oracle's light-cone windows."""
+    """Level 16 with two-, four- and eight-step launches (LDS and register
+    march engines), 200 steps, sampled against the oracle's light-cone
+    windows."""
     k = 16
     n = 1 << k
     r = 7 if rule == fi.RULE_CA else 6
