@@ -3,7 +3,8 @@
 Default workload (the one `value` is quoted on): a level-14 Sierpinski
 gasket (n = 16384, 4,782,969 cells); one benchmark step = one uint8 B3/S23
 automaton step plus one float32 heat step (alpha = 0.2), both through the
-lambda kernels at their autotuned launch.  `value` = gasket cells updated per
+lambda kernels at the library's default launch for the level (the measured
+fastest; --autotune times every candidate first instead).  `value` = gasket cells updated per
 second over the timed K steps (both rules), state resident in HBM, timed with
 HIP events on the stream the kernels run on.
 
@@ -44,6 +45,7 @@ ALPHA = 0.2
 #   float32: 8 * (4/3)^4 = 25.284 B per member cell
 BYTES_PER_CELL = {0: 2.0 * (4.0 / 3.0) ** 6, 1: 8.0 * (4.0 / 3.0) ** 4}
 WORKLOADS = {"k14": 14, "k16": 16}
+AUTOTUNE = False  # set by --autotune
 RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
               "device_march.hpp", "step_march.hip"]
@@ -93,10 +95,16 @@ class Gasket:
         self.F.seed_fill(self.k, rule, seed, self.bufs[rule][0])
         self.bufs[rule][1].zero_()
 
-    def autotune(self):
+    def autotune(self, search=None):
+        """Launch parameters per rule: the library default for the level, or
+        (search, or --autotune) the autotuner's pick."""
+        search = AUTOTUNE if search is None else search
         for rule in (0, 1):
-            self.tunings[rule] = self.F.autotune(self.k, rule, self.alpha, *self.bufs[rule])
-            self.reseed(rule)
+            if search:
+                self.tunings[rule] = self.F.autotune(self.k, rule, self.alpha, *self.bufs[rule])
+                self.reseed(rule)
+            else:
+                self.tunings[rule] = self.F.get_tuning(self.k, rule)
         self.torch.cuda.synchronize()
 
     def run(self, rule, steps, map_=None, tuning=None):
@@ -125,9 +133,9 @@ class Gasket:
 
 
 def steps_per_launch(tuning):
-    """Steps one launch advances: 8, 4 or 2 for fused launches, else 1."""
+    """Steps one launch advances: 16, 8, 4 or 2 for fused launches, else 1."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    return 8 if fl & 64 else (4 if fl & 16 else (2 if fl & 8 else 1))
+    return 16 if fl & 128 else (8 if fl & 64 else (4 if fl & 16 else (2 if fl & 8 else 1)))
 
 
 def kernel_name(tuning):
@@ -231,7 +239,7 @@ def sweep_k_leg(F, torch, kmin=8, kmax=16):
     out = {}
     for k in range(kmin, kmax + 1):
         g = Gasket(F, torch, k)
-        g.autotune()
+        g.autotune(search=True)
         steps = 64 if k >= 15 else 256
         row = {}
         for rule in (0, 1):
@@ -432,6 +440,8 @@ def main() -> int:
                     help="seconds of Poisson arrivals for the serving leg (0 = skip)")
     ap.add_argument("--sweep-k", action="store_true",
                     help="add lambda vs bounding box for levels 8..16 (about a minute)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every launch candidate first instead of the library defaults")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB with a plain device copy (counter calibration)")
     args = ap.parse_args()
@@ -454,6 +464,8 @@ def main() -> int:
         del src, dst
         torch.cuda.empty_cache()
 
+    global AUTOTUNE
+    AUTOTUNE = args.autotune
     K, W = args.steps, args.warmup
     g = Gasket(F, torch, WORKLOADS[args.workload])
     g.autotune()

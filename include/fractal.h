@@ -86,8 +86,8 @@ extern "C" {
                                    a wavefront takes several tiles side by
                                    side, one 16-byte chunk column per lane
                                    plus halo lanes, and walks down the tile
-                                   rows computing T = 1, 2, 4 or 8 steps
-                                   (FUSE2 / FUSE4 / FUSE8) in registers, with
+                                   rows computing T = 1, 2, 4, 8 or 16 steps
+                                   (FUSE2 / 4 / 8 / 16) in registers, with
                                    no LDS.  Needs FRACTAL_FLAG_SEGMENTS and
                                    tile rows of >= 16 bytes.  Steps are
                                    split into launches of T steps, then
@@ -95,6 +95,8 @@ extern "C" {
                                    of the parity of steps */
 #define FRACTAL_FLAG_FUSE8 64   /* eight steps per launch (with
                                    FRACTAL_FLAG_MARCH only) */
+#define FRACTAL_FLAG_FUSE16 128 /* sixteen steps per launch (with
+                                   FRACTAL_FLAG_MARCH, automaton only) */
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
                                      contiguous ranges of the tile list, instead
                                      of one workgroup per tile */

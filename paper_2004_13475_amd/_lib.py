@@ -18,7 +18,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_AGAIN = 0, 1, 2, 3, 4
 RULE_CA, RULE_HEAT = 0, 1
 ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
 FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2, FLAG_FUSE4 = 1, 2, 4, 8, 16
-FLAG_MARCH, FLAG_FUSE8 = 32, 64
+FLAG_MARCH, FLAG_FUSE8, FLAG_FUSE16 = 32, 64, 128
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 

@@ -81,7 +81,7 @@ static int default_threads(int rule, int r)
 }
 
 // Launch flags for an explicit tile size: where tile rows span 16 bytes,
-// the register-march engine with four steps per launch (non-temporal stores
+// the register-march engine with eight steps per launch (non-temporal stores
 // once the state is far beyond the caches, level >= 15); the matrix-core map
 // and narrower tiles use the LDS engine with whole segments.
 static int default_flags(int map, int k, int rule, int r)
@@ -92,7 +92,7 @@ static int default_flags(int map, int k, int rule, int r)
             fl |= rule == FRACTAL_RULE_CA ? (FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_NT_STORE)
                                           : FRACTAL_FLAG_FUSE4;
         else
-            fl |= FRACTAL_FLAG_MARCH | FRACTAL_FLAG_FUSE4 | (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
+            fl |= FRACTAL_FLAG_MARCH | FRACTAL_FLAG_FUSE8 | (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
     }
     return fl;
 }
@@ -119,16 +119,18 @@ static int clamp_r(int k, int r)
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
 // launches measured on MI355X, all on the register-march engine with omega
 // in the curve order split over the dies.  Level >= 15: automaton 64 x 64
-// tiles, eight steps per launch; heat 16 x 16 tiles, four steps; both with
-// non-temporal stores.  Below: automaton 128 x 128 and heat 32 x 32 tiles,
-// four steps, plain stores (the state stays in the last-level cache).
+// tiles with sixteen steps per launch, heat 32 x 32 tiles with eight, both
+// with non-temporal stores.  Below: automaton 16 x 16 and heat 32 x 32
+// tiles, eight steps, plain stores (the state stays in the last-level cache).
 static fractal_tuning builtin_default(int k, int rule)
 {
     const bool big = k >= 15;
-    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? (big ? 6 : 7) : (big ? 4 : 5));
+    const int r = clamp_r(k, rule == FRACTAL_RULE_CA ? (big ? 6 : 4) : 5);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
-    if ((t.flags & FRACTAL_FLAG_MARCH) && big && rule == FRACTAL_RULE_CA)
-        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8;
+    if (t.flags & FRACTAL_FLAG_MARCH)
+        t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |
+                  ((big && rule == FRACTAL_RULE_CA) ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8) |
+                  (big ? FRACTAL_FLAG_NT_STORE : 0);
     return t;
 }
 
@@ -169,9 +171,11 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
     if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
     if (fuse & (fuse - 1))
-        return set_error(FRACTAL_E_INVAL, "FUSE2, FUSE4 and FUSE8 are exclusive");
-    if ((fuse & FRACTAL_FLAG_FUSE8) && !march)
-        return set_error(FRACTAL_E_INVAL, "FUSE8 needs FRACTAL_FLAG_MARCH");
+        return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
+    if ((fuse & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)) && !march)
+        return set_error(FRACTAL_E_INVAL, "FUSE8 and FUSE16 need FRACTAL_FLAG_MARCH");
+    if ((fuse & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
+        return set_error(FRACTAL_E_INVAL, "FUSE16 is for the automaton only");
     if ((fuse || march) && !(t->flags & FRACTAL_FLAG_SEGMENTS))
         return set_error(FRACTAL_E_INVAL, "fused and march launches need FRACTAL_FLAG_SEGMENTS");
     if ((fuse || march) && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
@@ -331,7 +335,7 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         return rc;
     }
     // Few-step timings; enough launches that per-launch gaps are included.
-    const int reps = k >= 15 ? 16 : (k >= 12 ? 32 : 64); // multiples of 16 (fused pairs)
+    const int reps = k >= 15 ? 32 : 64; // multiples of 32 (pairs of 16-step launches)
     fractal_tuning best{};
     float best_ms = 1e30f;
     std::vector<fractal_tuning> cands;
@@ -356,15 +360,16 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         // non-temporal stores
         if (row_bytes >= 16)
             for (int fuse : {0, (int)FRACTAL_FLAG_FUSE2, (int)FRACTAL_FLAG_FUSE4,
-                             (int)FRACTAL_FLAG_FUSE8})
+                             (int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16})
                 for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
-                    cands.push_back(fractal_tuning{
+                    if (fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA)
+                        cands.push_back(fractal_tuning{
                         r, 256, FRACTAL_ORDER_CURVE_XCD,
                         FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse});
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)
-        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 16, t, s);
+        rc = launch_steps(MAP_LAMBDA, k, rule, alpha, d_buf0, d_buf1, 32, t, s);
         if (!rc)
             rc = hip_error(hipEventRecord(e0, s), "event record");
         if (!rc)

@@ -54,8 +54,10 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         t.r = k - kMaxBlockLevel;
     if ((1 << t.r) * (int)cell_bytes(rule) < 16) // fused and march launches need 16-byte rows
         t.flags &= ~(kFuseFlags | FRACTAL_FLAG_MARCH);
-    if (!(t.flags & FRACTAL_FLAG_MARCH) && (t.flags & FRACTAL_FLAG_FUSE8))
-        t.flags = (t.flags & ~FRACTAL_FLAG_FUSE8) | FRACTAL_FLAG_FUSE4; // LDS engine: 4 at most
+    if (!(t.flags & FRACTAL_FLAG_MARCH) && (t.flags & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)))
+        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE4; // LDS engine: 4 at most
+    if ((t.flags & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
+        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8; // heat marches 8 at most
     if (t.flags & FRACTAL_FLAG_MARCH)
         t.threads = 256;
     else if (t.threads == 256 && t.r < 3)

@@ -50,7 +50,7 @@ template <int RULE, int R, int T, int FL>
 static BatchMarchFn bm_fn()
 {
     constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID)
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
         return batch_march_kernel<RULE, R, T, HL, FL, march_wpe(T), march_depth(RULE, T)>;
     else
         return nullptr;
@@ -67,6 +67,7 @@ static BatchMarchFn bm_pick(int r, int T)
         case 2: return bm_fn<RULE, RR, 2, FL>();                                                   \
         case 4: return bm_fn<RULE, RR, 4, FL>();                                                   \
         case 8: return bm_fn<RULE, RR, 8, FL>();                                                   \
+        case 16: return bm_fn<RULE, RR, 16, FL>();                                                   \
         default: return nullptr;                                                                   \
         }
         FRACTAL_BM_R(2)

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "device_map.hpp"
 #include "device_tile.hpp"
 #include "internal.hpp"
@@ -40,11 +42,19 @@ struct MGeom {
 // Launch shape of a T-step march: halo lanes per side (T <= HL * cells per
 // chunk), the wavefronts per SIMD its register allocation must allow, and
 // the rows it loads ahead of the walk -- measured fastest at level 16: eight
-// steps keep their 64 words of row state at three wavefronts per SIMD; the
-// automaton's 16-cell chunks afford eight rows of prefetch at four steps.
-constexpr int march_hl(int rule, int T) { return T <= (rule == RULE_CA ? 16 : 4) ? 1 : 2; }
-constexpr int march_wpe(int T) { return T >= 8 ? 3 : 1; }
+// steps keep their row state at three wavefronts per SIMD (sixteen at two);
+// the automaton's 16-cell chunks afford eight rows of prefetch at four steps.
+constexpr int march_hl(int rule, int T)
+{
+    return T <= (rule == RULE_CA ? 16 : 4) ? 1 : (T <= 8 ? 2 : 4);
+}
+// Step counts a march launch takes: 16 for the automaton (one chunk of
+// halo), 8 for heat.
+constexpr bool march_supported(int rule, int T) { return T <= (rule == RULE_CA ? 16 : 8); }
+constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
 constexpr int march_depth(int rule, int T) { return (rule == RULE_CA && T <= 4) ? 8 : 4; }
+// Band heights (and so band origins) are multiples of this row period.
+constexpr int march_row_period(int rule) { return rule == RULE_CA ? 16 : 4; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -62,56 +72,142 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v)
                                                  true);
 }
 
-// One level of the walk: the new value of this lane's chunk of row yy from
-// the chunks of rows yy-1 (up), yy (md) and yy+1 (dn) after the previous
-// level; `inside` is false for chunks outside the array or off the tile set.
-template <int RULE>
-__device__ __forceinline__ void march_level(const uint32_t (&up)[4], const uint32_t (&md)[4],
-                                            const uint32_t (&dn)[4], int xc, int yy, bool inside,
-                                            float alpha, float c1, uint32_t (&out)[4])
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
 {
-    if constexpr (RULE == RULE_CA) {
-        uint32_t vc[4];
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Row state of one lane chunk (16 cells of memory) and one level of the
+// walk for each rule.  A level computes this lane's chunk of row yy from the
+// chunks of rows yy-1 (up), yy (md) and yy+1 (dn) of the previous level;
+// `ok` is false for chunks outside the array, off the tile set, or whose
+// cells (xc & yy) rules off the gasket as a whole; YQ = yy mod Q is known at
+// compile time (tile and band origins are multiples of Q and the walk is
+// unrolled Q rows at a time), so the member pattern inside the chunk is a
+// constant.
+template <int RULE>
+struct MarchRule;
+
+// Automaton: registers hold cells as 4-bit counters, 8 per word (cell
+// xc + 8j + n in bits 4n..4n+3 of word j), so one add sums 8 cells.
+template <>
+struct MarchRule<RULE_CA> {
+    static constexpr int W = 2;  // words per chunk
+    static constexpr int Q = 16; // row period of the in-chunk member pattern
+    static constexpr int U = 16; // rows per unrolled pass of the walk
+    // 16 bytes of 0/1 cells -> nibbles: byte j of a word gets cells 2j
+    // (low nibble) and 2j+1 (high nibble)
+    static __device__ __forceinline__ void load(const u32x4 &v, uint32_t (&s)[W])
+    {
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
-            vc[w] = up[w] + md[w] + dn[w]; // column sums, <= 3 per byte
-        const uint32_t vl = from_left(vc[3]);
-        const uint32_t vr = from_right(vc[0]);
-        // cells x..x+15 with x a multiple of 16: word w is on the gasket iff
-        // ((x/4 + w) & (yy/4)) == 0, and then byte b is a member iff
-        // (b & (yy & 3)) == 0
-        const uint32_t uy = (uint32_t)yy;
-        const uint32_t pat = 0x01010101u & ~((uy & 1u) * 0xFF00FF00u) &
-                             ~(((uy >> 1) & 1u) * 0xFFFF0000u);
-        const uint32_t xw = (uint32_t)xc >> 2;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t left = (w == 0) ? vl : vc[w - 1];
-            const uint32_t right = (w == 3) ? vr : vc[w + 1];
-            // 3x3 sums, centre included (<= 9 per byte, no carries)
-            const uint32_t t = vc[w] + __builtin_amdgcn_alignbyte(vc[w], left, 3) +
-                               __builtin_amdgcn_alignbyte(right, vc[w], 1);
-            // live neighbours c = t - self; B3/S23 keeps or makes a cell
-            // alive iff (c | self) == 3
-            const uint32_t alive = bytes_eq<3>((t - md[w]) | md[w]);
-            const bool on = inside && (((xw + (uint32_t)w) & (uy >> 2)) == 0u);
-            out[w] = on ? (alive & pat) : 0u;
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t lo = v[2 * j], hi = v[2 * j + 1];
+            const uint32_t ev = __builtin_amdgcn_perm(hi, lo, 0x06040200u); // cells 0,2,4,6
+            const uint32_t od = __builtin_amdgcn_perm(hi, lo, 0x07050301u); // cells 1,3,5,7
+            s[j] = ev | (od << 4);
         }
-    } else {
-        const float ml = __uint_as_float(from_left(md[3]));
-        const float mr = __uint_as_float(from_right(md[0]));
-        const uint32_t uy = (uint32_t)yy;
-        const bool on = inside && (((uint32_t)xc & uy) == 0u);
+    }
+    static __device__ __forceinline__ u32x4 store(const uint32_t (&s)[W])
+    {
+        u32x4 v;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t ev = s[j] & 0x0F0F0F0Fu, od = (s[j] >> 4) & 0x0F0F0F0Fu;
+            v[2 * j] = __builtin_amdgcn_perm(od, ev, 0x05010400u);
+            v[2 * j + 1] = __builtin_amdgcn_perm(od, ev, 0x07030602u);
+        }
+        return v;
+    }
+    // member nibbles (value 1 << 3) of word j for rows with yy mod 16 == YQ:
+    // cell 8j + n is a member iff ((8j + n) & YQ) == 0
+    template <int YQ>
+    static constexpr uint32_t pattern(int j)
+    {
+        uint32_t p = 0u;
+        for (int c = 0; c < 8; ++c)
+            if (((8 * j + c) & YQ) == 0)
+                p |= 8u << (4 * c);
+        return p;
+    }
+    template <int YQ>
+    static __device__ __forceinline__ void level(const uint32_t (&up)[W], const uint32_t (&md)[W],
+                                                 const uint32_t (&dn)[W], bool ok, float, float,
+                                                 uint32_t (&out)[W])
+    {
+        uint32_t vc[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            vc[j] = up[j] + md[j] + dn[j]; // column sums, <= 3 per nibble
+        const uint32_t vl = from_left(vc[W - 1]);
+        const uint32_t vr = from_right(vc[0]);
+        const uint32_t m = ok ? ~0u : 0u;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const uint32_t left = (j == 0) ? vl : vc[j - 1];
+            const uint32_t right = (j == W - 1) ? vr : vc[j + 1];
+            // 3x3 sums, centre included (<= 9 per nibble, no carries): each
+            // nibble plus its west (funnel shift in from the left word) and
+            // east neighbours
+            const uint32_t t = vc[j] + __builtin_amdgcn_alignbit(vc[j], left, 28) +
+                               __builtin_amdgcn_alignbit(right, vc[j], 4);
+            // live neighbours c = t - self; B3/S23 keeps or makes a cell
+            // alive iff (c | self) == 3; y = that ^ 3 is 0 exactly then, and
+            // (y & 7) + 7 reaches bit 3 iff y & 7 != 0 (no carry out)
+            const uint32_t y = ((t - md[j]) | md[j]) ^ 0x33333333u;
+            const uint32_t h = ((y & 0x77777777u) + 0x77777777u) | y;
+            out[j] = ((~h & m) & pattern<YQ>(j)) >> 3;
+        }
+    }
+};
+
+// Heat: registers hold the 4 float32 cells of the chunk.
+template <>
+struct MarchRule<RULE_HEAT> {
+    static constexpr int W = 4;
+    static constexpr int Q = 4;
+    // a multiple of 3 as well: the three rows each level keeps then rotate
+    // through fixed registers, with no moves at the loop's back edge
+    static constexpr int U = 12;
+    static __device__ __forceinline__ void load(const u32x4 &v, uint32_t (&s)[W])
+    {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            s[w] = v[w];
+    }
+    static __device__ __forceinline__ u32x4 store(const uint32_t (&s)[W])
+    {
+        return u32x4{s[0], s[1], s[2], s[3]};
+    }
+    template <int YQ>
+    static __device__ __forceinline__ void level(const uint32_t (&up)[W], const uint32_t (&md)[W],
+                                                 const uint32_t (&dn)[W], bool ok, float alpha,
+                                                 float c1, uint32_t (&out)[W])
+    {
+        // cell w of the chunk is a member iff (w & YQ) == 0 (given ok);
+        // non-members are 0 without arithmetic
+        const float ml = __uint_as_float(from_left(md[0 + 3]));
+        float mr = 0.0f;
+        if constexpr ((3 & YQ) == 0)
+            mr = __uint_as_float(from_right(md[0]));
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if ((w & YQ) != 0) {
+                out[w] = 0u;
+                continue;
+            }
             const float wv = (w == 0) ? ml : __uint_as_float(md[w - 1]);
             const float ev = (w == 3) ? mr : __uint_as_float(md[w + 1]);
             const float v = heat_cell(__uint_as_float(md[w]), __uint_as_float(up[w]),
                                       __uint_as_float(dn[w]), wv, ev, alpha, c1);
-            out[w] = (on && (((uint32_t)w & uy) == 0u)) ? __float_as_uint(v) : 0u;
+            out[w] = ok ? __float_as_uint(v) : 0u;
         }
     }
-}
+};
 
 // Block coordinates of tile `id` under the lambda map: base-3 digit mu-1 of
 // the id (CURVE orders) or of omega_x / omega_y for odd / even mu (NATURAL,
@@ -167,8 +263,14 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
                                            TileXY t, int band, int band_log, bool active, int col)
 {
     using M = MGeom<RULE, R, T, HL>;
+    using RU = MarchRule<RULE>;
+    constexpr int W = RU::W;
+    constexpr int Q = RU::Q; // tile and band origins are multiples of Q
+    static_assert(Q == march_row_period(RULE), "row period");
+    constexpr int U = RU::U;
+    static_assert(U % Q == 0 && U % D == 0, "unrolled pass: whole row periods and ring turns");
     const int n = 1 << k;
-    const int H = M::RHO >> band_log; // band height
+    const int H = M::RHO >> band_log; // band height, a multiple of Q
     const int xc = (int)(t.x << R) + col * M::CC;
     const int ybase = (int)(t.y << R) + band * H; // first row of the band
     const bool col_ok = active && xc >= 0 && xc < n;
@@ -187,48 +289,51 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
         return v;
     };
 
-    uint32_t p2[T][4], p1[T][4]; // per level: rows yy-1 and yy of its newest yy+1
+    uint32_t p2[T][W], p1[T][W]; // per level: rows yy-1 and yy of its newest yy+1
 #pragma unroll
     for (int l = 0; l < T; ++l)
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < W; ++w)
             p2[l][w] = p1[l][w] = 0u;
     u32x4 ring[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
         ring[d] = load_row(d);
-    for (int i0 = 0; i0 < rows; i0 += D) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
+    for (int i0 = 0; i0 < rows; i0 += U) {
+        static_for<0, U>([&](auto dc) {
+            constexpr int d = decltype(dc)::value;
             const int i = i0 + d;
-            uint32_t cur[4] = {ring[d][0], ring[d][1], ring[d][2], ring[d][3]};
-            ring[d] = load_row(i + D);
+            uint32_t cur[W];
+            RU::load(ring[d % D], cur);
+            ring[d % D] = load_row(i + D);
+            static_for<1, T + 1>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                constexpr int yq = (((d - T - l) % Q) + Q) % Q; // (row of level l) mod Q
+                const int yy = ybase - T + i - l;
+                const bool ok = col_ok && yy >= 0 && yy < n && (((uint32_t)xc & (uint32_t)yy) &
+                                                                ~(uint32_t)(Q - 1)) == 0u;
+                uint32_t out[W];
+                RU::template level<yq>(p2[l - 1], p1[l - 1], cur, ok, alpha, c1, out);
 #pragma unroll
-            for (int l = 1; l <= T; ++l) {
-                const int yy = ybase - T + i - l; // row of level l
-                const bool inside = col_ok && yy >= 0 && yy < n;
-                uint32_t out[4];
-                march_level<RULE>(p2[l - 1], p1[l - 1], cur, xc, yy, inside, alpha, c1, out);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
+                for (int w = 0; w < W; ++w) {
                     p2[l - 1][w] = p1[l - 1][w];
                     p1[l - 1][w] = cur[w];
                     cur[w] = out[w];
                 }
-            }
+            });
             // cur: level T at band row j
             const int j = i - 2 * T;
             const int y = ybase + j;
             if (interior && col_ok && j >= 0 && j < H &&
                 ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u)) {
-                const u32x4 o = {cur[0], cur[1], cur[2], cur[3]};
+                const u32x4 o = RU::store(cur);
                 u32x4 *dp = reinterpret_cast<u32x4 *>(dst + off0 + (int64_t)(j + T) * pitch);
                 if constexpr (FL & TILE_NT_STORE)
                     __builtin_nontemporal_store(o, dp);
                 else
                     *dp = o;
             }
-        }
+        });
     }
 }
 

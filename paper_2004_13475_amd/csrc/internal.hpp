@@ -61,15 +61,17 @@ StepFn pick_step_lambda(int rule, int r, int threads, int flags);
 StepFn pick_step_bb(int rule, int r, int threads, int flags);
 StepFn pick_step_mfma(int rule, int r, int threads, int flags);
 
-// Steps one launch advances under these flags (1, 2, 4 or 8).
+// Steps one launch advances under these flags (1, 2, 4, 8 or 16).
 inline int launch_steps_of(int flags)
 {
-    return (flags & FRACTAL_FLAG_FUSE8)   ? 8
+    return (flags & FRACTAL_FLAG_FUSE16)  ? 16
+           : (flags & FRACTAL_FLAG_FUSE8) ? 8
            : (flags & FRACTAL_FLAG_FUSE4) ? 4
            : (flags & FRACTAL_FLAG_FUSE2) ? 2
                                           : 1;
 }
-constexpr int kFuseFlags = FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8;
+constexpr int kFuseFlags =
+    FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16;
 
 // Arguments of one register-march launch (FRACTAL_FLAG_MARCH).
 struct MarchArgs {
@@ -119,8 +121,8 @@ struct BatchEntry {
     int32_t flip0; // launches this instance makes before this list's first
 };
 static_assert(sizeof(BatchEntry) == 48, "BatchEntry layout");
-// An instance sits in at most one list per launch size (8, 4, 2, 1 steps).
-constexpr int kMaxListsPerItem = 4;
+// An instance sits in at most one list per launch size (16, 8, 4, 2, 1 steps).
+constexpr int kMaxListsPerItem = 5;
 
 // One gasket advanced by a batched launch sequence.
 struct BatchItem {

@@ -11,7 +11,7 @@ template <int MAP, int RULE, int R, int T, int FL>
 static MarchFn march_fn()
 {
     constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID)
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
         return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;
     else
         return nullptr;
@@ -28,6 +28,7 @@ static MarchFn march_pick_rt(int r, int T)
         case 2: return march_fn<MAP, RULE, RR, 2, FL>();                                           \
         case 4: return march_fn<MAP, RULE, RR, 4, FL>();                                           \
         case 8: return march_fn<MAP, RULE, RR, 8, FL>();                                           \
+        case 16: return march_fn<MAP, RULE, RR, 16, FL>();                                           \
         default: return nullptr;                                                                   \
         }
         FRACTAL_MARCH_R(2)
@@ -70,13 +71,16 @@ int march_tiles_per_wave(int rule, int r, int T)
 
 // Bands per tile (log2): the fewest that give the chip about 2.5
 // wavefronts per SIMD (fewer leave HBM latency exposed), keeping bands at
-// least 4T rows high (the 2T halo rows each band re-reads stay cheap).
+// least 4T rows high (the 2T halo rows each band re-reads stay cheap) and a
+// multiple of the kernel's row period.
 int march_band_log(int rule, int r, int T, uint64_t tiles)
 {
     const uint64_t P = (uint64_t)march_tiles_per_wave(rule, r, T);
     const uint64_t want = 10u * 256u; // 2.5 wavefronts x 4 SIMDs x 256 CUs
+    const int qr = march_row_period(rule == FRACTAL_RULE_CA ? RULE_CA : RULE_HEAT);
+    const int hmin = 4 * T > qr ? 4 * T : qr;
     int b = 0;
-    while (b < r && ((1 << r) >> (b + 1)) >= 4 * T && ((tiles << b) + P - 1) / P < want)
+    while (b < r && ((1 << r) >> (b + 1)) >= hmin && ((tiles << b) + P - 1) / P < want)
         ++b;
     return b;
 }

@@ -43,7 +43,8 @@ MARCH = F.FLAG_MARCH | F.FLAG_SEGMENTS
                                     (5, 0, 0, MARCH | F.FLAG_NT_STORE | F.FLAG_FUSE4),
                                     (4, 256, 0, MARCH | F.FLAG_FUSE2),
                                     (7, 64, 0, MARCH),
-                                    (6, 0, 0, MARCH | F.FLAG_FUSE8 | F.FLAG_PERSISTENT)])
+                                    (6, 0, 0, MARCH | F.FLAG_FUSE8 | F.FLAG_PERSISTENT),
+                                    (5, 0, 2, MARCH | F.FLAG_FUSE16)])
 def test_batch_alone_equals_in_mix(tuning):
     torch = torch_dev()
     specs = _mix(40, 3, 1, 11, 37)

@@ -193,7 +193,7 @@ def test_fused_launches(rule, map_):
                         assert_match(k, rule, fa.cpu().numpy(), ref, f"fused k={k} r={r} t={steps}")
 
 
-MARCH_FUSE = (0, F.FLAG_FUSE2, F.FLAG_FUSE4, F.FLAG_FUSE8)
+MARCH_FUSE = (0, F.FLAG_FUSE2, F.FLAG_FUSE4, F.FLAG_FUSE8, F.FLAG_FUSE16)
 
 
 @pytest.mark.parametrize("map_", [F.MAP_LAMBDA, F.MAP_BB])
@@ -212,15 +212,17 @@ def test_march_launches(rule, map_):
             if (1 << r) * cell < 16 or k - r > 15:
                 continue
             ref_by_steps = {}
-            for steps in (1, 2, 3, 7, 8, 13, 16, 19):
+            for steps in (1, 2, 3, 7, 8, 13, 16, 19, 32, 37):
                 b0, b1 = to_device(init), zeros_state(k, rule)
                 F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, 64, 2, F.FLAG_SEGMENTS)
                 _sync()
                 ref_by_steps[steps] = (b0 if steps % 2 == 0 else b1).view(torch.uint8).clone()
             for fuse in MARCH_FUSE:
+                if fuse == F.FLAG_FUSE16 and rule != fi.RULE_CA:
+                    continue
                 for (th, order, nt) in ((256, 2, 2), (64, 0, 0), (256, 1, 0)):
                     fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | nt | fuse
-                    for steps in (1, 2, 3, 7, 8, 13, 16, 19):
+                    for steps in (1, 2, 3, 7, 8, 13, 16, 19, 32, 37):
                         a0, a1 = to_device(init), zeros_state(k, rule)
                         F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, th, order, fl)
                         _sync()
@@ -255,12 +257,14 @@ def test_march_rejects_bad_tunings():
     del torch
 
 
-@pytest.mark.parametrize("flags", [11, 19, 35 | 16, 35 | 64])
+@pytest.mark.parametrize("flags", [11, 19, 35 | 16, 35 | 64, 35 | 128])
 @pytest.mark.parametrize("rule", RULES)
 def test_fused_full_size_k16_sampled(rule, flags):
     """Level 16 with two-, four- and eight-step launches (LDS and register
     march engines), 200 steps, sampled against the oracle's light-cone
     windows."""
+    if flags & 128 and rule != fi.RULE_CA:
+        pytest.skip("sixteen-step launches are for the automaton")
     k = 16
     n = 1 << k
     r = 7 if rule == fi.RULE_CA else 6
