@@ -12,6 +12,7 @@ special case, hand-derived values); none is "parity unpinned".
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -162,3 +163,37 @@ def valid_interior(k: int, x0: int, y0: int, w: int, h: int, steps: int):
     hi_x = w if x0 + w >= n else w - steps
     hi_y = h if y0 + h >= n else h - steps
     return slice(lo_y, max(lo_y, hi_y)), slice(lo_x, max(lo_x, hi_x))
+
+
+def gasket_mask(k: int) -> np.ndarray:
+    """Membership of every cell of the n x n embedding (Eq. 2 set): cell
+    (x, y) belongs to the level-k gasket iff x & y == 0.  Row y, column x."""
+    n = 1 << k
+    ax = np.arange(n, dtype=np.int64)
+    return np.bitwise_and.outer(ax, ax) == 0
+
+
+def single_write(k: int, rule: int, value: int) -> np.ndarray:
+    """Section 6.2, test SW: a constant written on every element of the
+    gasket, embedded in an n x n array that starts at 0.  `value` is the low
+    byte for the automaton's uint8 cells, the float32 bit pattern for heat
+    cells."""
+    mask = gasket_mask(k)
+    if rule == 0:
+        out = np.zeros(mask.shape, dtype=np.uint8)
+        out[mask] = value & 0xFF
+    else:
+        out = np.zeros(mask.shape, dtype=np.float32)
+        out[mask] = np.array([value & 0xFFFFFFFF], dtype=np.uint32).view(np.float32)[0]
+    return out
+
+
+def reduce_(k: int, state: np.ndarray):
+    """Section 6.2, test RD: the arithmetic sum of all elements of the
+    gasket (cells off the gasket do not take part).  uint8 states give the
+    exact integer; float states give the exactly rounded float64 sum
+    (math.fsum)."""
+    vals = np.asarray(state)[gasket_mask(k)]
+    if vals.dtype == np.uint8:
+        return int(vals.astype(np.int64).sum())
+    return math.fsum(vals.astype(np.float64).tolist())

@@ -244,3 +244,61 @@ def test_inputs_zero_off_gasket_and_ranges():
     assert ht.min() >= 0 and ht.max() < 1
     # window generation equals slicing the full state
     assert np.array_equal(fi.window_values(k, 1, 1, 30, 40, 50, 60), ht[40:100, 30:80])
+
+
+# ------------------------------------------------------ SW and RD (Sec. 6.2)
+@pytest.mark.parametrize("k", range(0, 11))
+def test_gasket_mask_matches_scan(k):
+    """The oracle's membership array agrees with the C oracle's cell test on
+    every cell (small k) and has 3^k members (Eq. 2)."""
+    mask = oracle.gasket_mask(k)
+    assert int(mask.sum()) == 3 ** k
+    if k <= 5:
+        n = 1 << k
+        for y in range(n):
+            for x in range(n):
+                assert mask[y, x] == oracle.member(x, y, k)
+
+
+@pytest.mark.parametrize("rule,value,cell", [(0, 1, 1), (0, 0x1FF, 0xFF), (1, 0x3F800000, 1.0),
+                                             (1, 0xC0490FDB, float(np.float32(-3.14159274)))])
+def test_single_write_closed_form(rule, value, cell):
+    """SW writes `value` on exactly the 3^k gasket cells and 0 elsewhere; its
+    reduction is 3^k times the value (exact: 3^k * value needs < 53 bits)."""
+    for k in range(0, 10):
+        out = oracle.single_write(k, rule, value)
+        nz = out != 0
+        assert int(nz.sum()) == 3 ** k
+        assert np.all(out[nz] == np.array(cell, dtype=out.dtype))
+        tot = oracle.reduce_(k, out)
+        assert tot == (3 ** k) * cell
+
+
+def test_reduce_brute_force_exact():
+    """RD against an exact rational sum of the members, cell by cell, on
+    random uint8 and float32 states (tiny levels), with garbage off the
+    gasket that must not count."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    for k in range(0, 6):
+        n = 1 << k
+        u8 = rng.integers(0, 256, size=(n, n), dtype=np.uint8)
+        f32 = (rng.standard_normal((n, n)) * 1e3).astype(np.float32)
+        want_u, want_f = 0, Fraction(0)
+        for y in range(n):
+            for x in range(n):
+                if (x & y) == 0:
+                    want_u += int(u8[y, x])
+                    want_f += Fraction(float(f32[y, x]))
+        assert oracle.reduce_(k, u8) == want_u
+        assert oracle.reduce_(k, f32) == float(want_f)  # exactly rounded
+
+
+def test_reduce_of_seeded_heat_state_is_exact():
+    """Seeded heat values are multiples of 2^-24 below 1, so the sum of a
+    level-10 state (59049 members) is exact in float64 and equals the
+    integer sum of the 24-bit numerators times 2^-24."""
+    k = 10
+    st = fi.full_state(k, 1, 5)
+    num = int((st.astype(np.float64) * (1 << 24)).astype(np.int64).sum())
+    assert oracle.reduce_(k, st) == num / float(1 << 24)
