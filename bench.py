@@ -16,6 +16,7 @@ Also on the same JSON line:
   batch         256 gaskets of levels 8..14, 500 steps, one graph launch vs
                 256 plain lambda_step calls
   serve         (with --serve SECONDS) Poisson request stream, p50/p99
+  sw_rd         tests SW (single write) and RD (reduction), lambda vs BB
   cpu_baseline  the CPU oracle on a bounded sample of the default workload
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
@@ -210,6 +211,60 @@ def bb_leg(g, per_launch, nsteps):
             "bb_us_by_r": {str(r): v * 1e6 for r, v in res.items()},
             "bb_lds_engine_us_by_r": {str(r): v * 1e6 for r, v in lds.items()},
         }
+    return out
+
+
+def sw_rd_leg(F, torch, k, reps=20):
+    """Tests SW and RD of Section 6.2 at level k: each map at tile sides
+    16..128, seconds per call (HIP events over `reps` calls); lambda vs BB at
+    lambda's best tile size and at each map's best.  Algorithmic bytes: the
+    member segments written (SW) or read (RD) once, half the step figure."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for rule, dt in ((0, torch.uint8), (1, torch.float32)):
+        n = 1 << k
+        buf = torch.zeros((n, n), dtype=dt, device="cuda")
+        res = {"sw": {}, "rd": {}}
+        for r in range(4, 8):
+            if k - r > 15:
+                continue
+            work = torch.empty(max(8, F.reduce_workspace(k, r)), dtype=torch.uint8, device="cuda")
+            val = torch.zeros(1, dtype=torch.float64, device="cuda")
+            for map_ in (F.MAP_LAMBDA, F.MAP_BB):
+                for op in ("sw", "rd"):
+                    def call():
+                        if op == "sw":
+                            F.single_write(map_, k, r, rule, 1, buf)
+                        else:
+                            F.reduce(map_, k, r, rule, buf, work, val)
+                    call()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        call()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    res[op][(r, map_)] = e0.elapsed_time(e1) * 1e-3 / reps
+            del work, val
+        alg = BYTES_PER_CELL[rule] / 2 * 3 ** k
+        row = {}
+        for op in ("sw", "rd"):
+            lam = {r: t for (r, m), t in res[op].items() if m == F.MAP_LAMBDA}
+            bb = {r: t for (r, m), t in res[op].items() if m == F.MAP_BB}
+            rl, rbb = min(lam, key=lam.get), min(bb, key=bb.get)
+            achieved = alg / lam[rl] / 1e9
+            row[op] = {"lambda_r": rl, "lambda_us": lam[rl] * 1e6, "bb_r": rbb,
+                       "bb_us": bb[rbb] * 1e6, "bb_us_same_r": bb[rl] * 1e6,
+                       "speedup_same_r": bb[rl] / lam[rl], "speedup_best": bb[rbb] / lam[rl],
+                       "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                    "alg_bytes": alg},
+                       "lambda_us_by_r": {str(r): t * 1e6 for r, t in lam.items()},
+                       "bb_us_by_r": {str(r): t * 1e6 for r, t in bb.items()}}
+        out[RULE_NAME[rule]] = row
+        del buf
+        torch.cuda.empty_cache()
     return out
 
 
@@ -500,6 +555,7 @@ def main() -> int:
     batch = None if args.no_batch else batch_leg(F, torch)
     serve = serve_leg(F, torch, args.serve) if args.serve > 0 else None
     sweep = sweep_k_leg(F, torch) if args.sweep_k else None
+    swrd = None if args.no_bb else {f"k{kk}": sw_rd_leg(F, torch, kk) for kk in sorted({k, 16})}
     ceiling = None if args.no_bb else copy_ceiling(torch)
 
     cpu = None
@@ -536,6 +592,7 @@ def main() -> int:
                                     "roofline": rfs[r]}
                      for r in (0, 1)},
         "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
+        "sw_rd": swrd,
         "lambda_vs_bb_by_k": sweep,
         "device_copy_GBs": ceiling,
         "cpu_baseline": cpu,

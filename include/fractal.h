@@ -136,11 +136,12 @@ int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
                       void *stream);
 
 /* Launches of the step entry points below without an explicit tuning use,
- * for an explicit r, 64 or 256 threads (one 16-byte chunk per lane), the
- * die-aware curve order for lambda and launch order for the bounding box,
- * whole segments, and where tile rows span >= 16 bytes two (automaton) or
- * four (heat) steps per launch; for FRACTAL_R_AUTO, the cached autotuned
- * launch or a built-in default. */
+ * for an explicit r, the die-aware curve order for lambda and launch order
+ * for the bounding box, whole segments, and where tile rows span >= 16 bytes
+ * the register-march engine with eight steps per launch (non-temporal
+ * stores from level 15), else the LDS engine one step per launch (64 or 256
+ * threads); for FRACTAL_R_AUTO, the cached autotuned launch or a built-in
+ * default.  The matrix-core map always uses the LDS engine. */
 
 /* Bounding-box step (Section 1; Section 6.2): a grid of all (n/rho)^2
  * workgroups with the identity map omega -> tile; a workgroup whose tile
@@ -186,6 +187,36 @@ int fractal_get_tuning(int k, int rule, fractal_tuning *out);
 
 /* Replace the cached entry for (current device, k, rule). */
 int fractal_set_tuning(int k, int rule, const fractal_tuning *tuning);
+
+/* Test SW of Section 6.2 (single write): every member cell of the level-k
+ * gasket in d_buf (n x n, row-major, uint8 for FRACTAL_RULE_CA, float32 for
+ * FRACTAL_RULE_HEAT) is set to `value` (its low byte for uint8 cells, its
+ * bit pattern for float32 cells), over tiles of side 2^r reached through
+ * lambda (map 0) or the bounding box (map 1).  Cells off the gasket are
+ * written 0 where they lie in a non-empty tile and in a 64-byte row segment
+ * that holds a member, and are not touched elsewhere, so on a buffer that
+ * starts at 0 (as in the paper) the result is value on the gasket and 0 off
+ * it.  0 <= k <= 16,
+ * 0 <= r <= min(k, 7), k - r <= 15.  d_buf must be 16-byte aligned. */
+int fractal_single_write(int map, int k, int r, int rule, uint32_t value,
+                         void *d_buf, void *stream);
+
+/* Bytes of device workspace fractal_reduce needs for (k, r): one 8-byte
+ * partial per tile plus the partials of the summation tree. */
+int fractal_reduce_workspace(int k, int r, size_t *bytes);
+
+/* Test RD of Section 6.2 (reduction): *d_out (8 bytes of device memory) =
+ * the sum of the member cells of d_buf: a uint64 for uint8 cells, a float64
+ * (the float32 values summed in float64) for float32 cells; cells off the
+ * gasket are ignored.  Each tile's cells are summed in a fixed order into
+ * slot lambda^-1(tile) of d_work, and the slots are summed by a fixed tree,
+ * so the result does not depend on the map, the dispatch or the timing
+ * (lambda and BB agree bit for bit).  d_work: caller-owned, at least
+ * fractal_reduce_workspace(k, r) bytes, 8-byte aligned; its contents are
+ * overwritten.  Same ranges as fractal_single_write; E_INVAL on a short
+ * workspace. */
+int fractal_reduce(int map, int k, int r, int rule, const void *d_buf,
+                   void *d_work, size_t work_bytes, void *d_out, void *stream);
 
 /* One gasket of a batch. */
 typedef struct fractal_instance {

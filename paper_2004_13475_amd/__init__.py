@@ -8,4 +8,5 @@ from ._lib import (  # noqa: F401
     MAP_MFMA, OK, ORDER_CURVE, ORDER_CURVE_XCD, ORDER_NATURAL, R_AUTO, RULE_CA,
     RULE_HEAT, FractalError, Server, autotune, batch_step, bb_step,
     exported_symbols, get_tuning, grid_dims, lambda_map, lambda_map_mfma,
-    lambda_step, lambda_step_mfma, load, now, seed_fill, set_tuning, step_tuned)
+    lambda_step, lambda_step_mfma, load, now, reduce, reduce_workspace, seed_fill, set_tuning,
+    single_write, step_tuned)

@@ -27,6 +27,7 @@ EXPORTED = [
     "fractal_seed_fill", "fractal_bb_step", "fractal_lambda_step",
     "fractal_lambda_step_mfma", "fractal_step_tuned", "fractal_autotune",
     "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_step",
+    "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
     "fractal_now", "fractal_serve_create", "fractal_serve_submit",
     "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
 ]
@@ -93,6 +94,9 @@ def load():
         "fractal_get_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
         "fractal_set_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
         "fractal_batch_step": ([ctypes.POINTER(Instance), i, ctypes.POINTER(Tuning), vp], i),
+        "fractal_single_write": ([i, i, i, i, u32, vp, vp], i),
+        "fractal_reduce_workspace": ([i, i, ctypes.POINTER(ctypes.c_size_t)], i),
+        "fractal_reduce": ([i, i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
         "fractal_now": ([], ctypes.c_double),
         "fractal_serve_create": ([vp, ctypes.c_size_t, i, i, vp, ctypes.POINTER(vp)], i),
         "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
@@ -207,6 +211,29 @@ def batch_step(instances, tuning=None, stream=None):
     if tuning is not None:
         tp = ctypes.byref(Tuning(*tuning) if len(tuning) == 4 else Tuning(*tuning, 0))
     return _check(load().fractal_batch_step(arr, len(instances), tp, _stream(stream)))
+
+
+def single_write(map_, k, r, rule, value, buf, stream=None):
+    """Test SW: `value` (uint8 low byte / float32 bit pattern) on every
+    gasket cell of `buf`."""
+    return _check(load().fractal_single_write(map_, k, r, rule, int(value) & 0xFFFFFFFF,
+                                              _ptr(buf), _stream(stream)))
+
+
+def reduce_workspace(k, r) -> int:
+    """Bytes of device workspace `reduce` needs."""
+    b = ctypes.c_size_t()
+    _check(load().fractal_reduce_workspace(k, r, ctypes.byref(b)))
+    return b.value
+
+
+def reduce(map_, k, r, rule, buf, work, out, stream=None):
+    """Test RD: the sum of the gasket cells of `buf` into the 8-byte device
+    buffer `out` (uint64 for uint8 cells, float64 for float32 cells); `work`
+    is a device buffer of at least reduce_workspace(k, r) bytes."""
+    nbytes = work.numel() * work.element_size() if hasattr(work, "numel") else 1 << 62
+    return _check(load().fractal_reduce(map_, k, r, rule, _ptr(buf), _ptr(work), nbytes,
+                                        _ptr(out), _stream(stream)))
 
 
 def now() -> float:

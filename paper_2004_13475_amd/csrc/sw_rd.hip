@@ -1,0 +1,407 @@
+// sw_rd.hip -- tests SW (single write) and RD (reduction) of the paper's
+// case study (Section 6.2) on the lambda and bounding-box maps.
+//
+// A wavefront takes P tiles side by side; a tile's lanes each own one
+// chunk column (16 bytes, or the whole row of a narrower tile) and walk the
+// tile's rows.  SW writes every 64-byte segment that holds a member (value on
+// members, 0 elsewhere in the segment); RD loads every chunk that holds a
+// member and sums its members, lanes of a tile combine their sums by a fixed
+// butterfly, and the tile's sum goes to slot lambda^-1(tile) of the
+// workspace; a fixed summation tree then reduces the slots.  Nothing depends
+// on which map dispatched a tile or when, so lambda and BB agree bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "device_map.hpp"
+#include "device_march.hpp"
+#include "internal.hpp"
+
+namespace fractal {
+
+template <int RULE, int R>
+struct SGeom {
+    static constexpr int S = (RULE == RULE_CA) ? 1 : 4;
+    static constexpr int RHO = 1 << R;
+    static constexpr int RB = RHO * S;               // tile row bytes
+    static constexpr int CB = RB < 16 ? RB : 16;     // bytes per lane chunk
+    static constexpr int CC = CB / S;                // cells per chunk
+    static constexpr int IL = RB / CB;               // lanes per tile (power of two)
+    static constexpr int P = 64 / IL;                // tiles per wavefront
+    static constexpr int SLOG = (RULE == RULE_CA) ? 6 : 4; // cells per 64-byte segment (log2)
+};
+
+struct SwRdArgs {
+    uint8_t *buf;
+    int k;
+    int rb;
+    uint64_t total;   // tiles in the map's id space
+    uint32_t value;   // SW
+    uint64_t *slots;  // RD: one 8-byte partial per non-empty tile
+};
+
+// lambda^-1: the curve index of non-empty tile (x, y): base-3 digit mu-1 is
+// 2 where bit mu-1 of x is set, 0 where that of y is set, 1 where neither.
+__device__ __forceinline__ uint32_t lambda_inverse(uint32_t x, uint32_t y, int rb)
+{
+    uint32_t L = 0u;
+    for (int mu = rb - 1; mu >= 0; --mu) {
+        const uint32_t bx = (x >> mu) & 1u, by = (y >> mu) & 1u;
+        L = 3u * L + (bx ? 2u : (by ? 0u : 1u));
+    }
+    return L;
+}
+
+template <int CB>
+__device__ __forceinline__ void chunk_load(const uint8_t *p, uint8_t (&b)[CB])
+{
+    if constexpr (CB == 16) {
+        const u32x4 v = *reinterpret_cast<const u32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            b[i] = (uint8_t)(v[i >> 2] >> (8 * (i & 3)));
+    } else if constexpr (CB == 8) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            b[i] = (uint8_t)(((i < 4) ? v.x : v.y) >> (8 * (i & 3)));
+    } else if constexpr (CB == 4) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            b[i] = (uint8_t)(v >> (8 * i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+            b[i] = p[i];
+    }
+}
+
+template <int CB>
+__device__ __forceinline__ void chunk_store(uint8_t *p, const uint8_t (&b)[CB])
+{
+    if constexpr (CB >= 4) {
+        uint32_t w[CB / 4];
+#pragma unroll
+        for (int q = 0; q < CB / 4; ++q)
+            w[q] = (uint32_t)b[4 * q] | ((uint32_t)b[4 * q + 1] << 8) |
+                   ((uint32_t)b[4 * q + 2] << 16) | ((uint32_t)b[4 * q + 3] << 24);
+        if constexpr (CB == 16)
+            *reinterpret_cast<u32x4 *>(p) = u32x4{w[0], w[1], w[2], w[3]};
+        else if constexpr (CB == 8)
+            *reinterpret_cast<uint2 *>(p) = uint2{w[0], w[1]};
+        else
+            *reinterpret_cast<uint32_t *>(p) = w[0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+            p[i] = b[i];
+    }
+}
+
+// Sum of v over the IL lanes of this lane's group (aligned runs of IL lanes),
+// by a fixed butterfly; every lane of the group ends with the same bits.
+template <int IL>
+__device__ __forceinline__ uint64_t group_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 1; off < IL; off <<= 1) {
+        const int src = (int)((lane_id() ^ (uint32_t)off) << 2);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(v >> 32));
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+template <int IL>
+__device__ __forceinline__ double group_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 1; off < IL; off <<= 1) {
+        const int src = (int)((lane_id() ^ (uint32_t)off) << 2);
+        const uint64_t bits = (uint64_t)__double_as_longlong(v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)bits);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(bits >> 32));
+        const double o = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+        // a + b and b + a are the same float64, so both partners agree
+        v = (lane_id() & (uint32_t)off) ? o + v : v + o;
+    }
+    return v;
+}
+
+enum : int { OP_SW = 0, OP_RD = 1 };
+
+template <int RULE, int R, int MAP, int OP>
+__global__ __launch_bounds__(256) void swrd_kernel(SwRdArgs a)
+{
+    using G = SGeom<RULE, R>;
+    const uint32_t lane = lane_id();
+    const uint32_t grp = lane / (uint32_t)G::IL;
+    const int col = (int)(lane - grp * (uint32_t)G::IL);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t tile = wave * G::P + grp;
+    bool active = tile < a.total;
+    uint32_t tx = 0u, ty = 0u, slot = 0u;
+    if (active) {
+        if constexpr (MAP == MAP_BB) {
+            tx = (uint32_t)tile & ((1u << a.rb) - 1u);
+            ty = (uint32_t)(tile >> a.rb);
+            active = (tx & ty) == 0u;
+            if (active)
+                slot = lambda_inverse(tx, ty, a.rb);
+        } else {
+            const TileXY t = lambda_lane((uint32_t)tile, a.rb, FRACTAL_ORDER_CURVE);
+            tx = t.x;
+            ty = t.y;
+            slot = (uint32_t)tile;
+        }
+    }
+    if constexpr (OP == OP_SW) {
+        if (!active)
+            return;
+    } else {
+        if (__builtin_amdgcn_ballot_w64(active) == 0u)
+            return; // the group sums below need every lane of the wavefront
+    }
+    const uint32_t n = 1u << a.k;
+    const uint32_t x = (tx << R) + (uint32_t)col * G::CC;
+    const uint32_t y0 = ty << R;
+    uint8_t *base = a.buf + ((uint64_t)y0 * n + x) * G::S;
+    const uint64_t pitch = (uint64_t)n * G::S;
+    uint32_t acc_u = 0u;
+    double acc_d = 0.0;
+    for (int j = 0; j < G::RHO; ++j) {
+        const uint32_t y = y0 + (uint32_t)j;
+        uint8_t *p = base + (uint64_t)j * pitch;
+        if constexpr (OP == OP_SW) {
+            if (((x >> G::SLOG) & (y >> G::SLOG)) != 0u)
+                continue; // no member in this 64-byte segment
+            uint8_t b[G::CB];
+#pragma unroll
+            for (int c = 0; c < G::CC; ++c) {
+                const bool m = ((x + (uint32_t)c) & y) == 0u;
+#pragma unroll
+                for (int q = 0; q < G::S; ++q)
+                    b[c * G::S + q] = m ? (uint8_t)(a.value >> (8 * q)) : (uint8_t)0;
+            }
+            chunk_store<G::CB>(p, b);
+        } else {
+            if (!active || (x & y) != 0u)
+                continue; // no member in this chunk
+            uint8_t b[G::CB];
+            chunk_load<G::CB>(p, b);
+#pragma unroll
+            for (int c = 0; c < G::CC; ++c) {
+                const bool m = (((uint32_t)c) & y) == 0u;
+                if constexpr (RULE == RULE_CA) {
+                    acc_u += m ? b[c] : 0u;
+                } else {
+                    const uint32_t bits = (uint32_t)b[4 * c] | ((uint32_t)b[4 * c + 1] << 8) |
+                                          ((uint32_t)b[4 * c + 2] << 16) |
+                                          ((uint32_t)b[4 * c + 3] << 24);
+                    acc_d += m ? (double)__uint_as_float(bits) : 0.0;
+                }
+            }
+        }
+    }
+    if constexpr (OP == OP_RD) {
+        uint64_t out;
+        if constexpr (RULE == RULE_CA)
+            out = group_sum_u64<G::IL>((uint64_t)acc_u);
+        else
+            out = (uint64_t)__double_as_longlong(group_sum_f64<G::IL>(acc_d));
+        if (active && col == 0)
+            a.slots[slot] = out;
+    }
+}
+
+// One pass of the summation tree: workgroup b sums in[b*4096 .. +4096) --
+// thread t adds elements t, t + 256, ... in order, then a fixed LDS tree.
+template <bool F64>
+__global__ __launch_bounds__(256) void tree_kernel(const uint64_t *__restrict__ in, uint64_t n,
+                                                   uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t sh[256];
+    const uint32_t t = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * 4096u + t;
+    uint64_t acc_u = 0u;
+    double acc_d = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint64_t e = base + 256u * (uint64_t)i;
+        if (e < n) {
+            if constexpr (F64)
+                acc_d += __longlong_as_double((long long)in[e]);
+            else
+                acc_u += in[e];
+        }
+    }
+    sh[t] = F64 ? (uint64_t)__double_as_longlong(acc_d) : acc_u;
+    __syncthreads();
+    for (uint32_t s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            if constexpr (F64)
+                sh[t] = (uint64_t)__double_as_longlong(__longlong_as_double((long long)sh[t]) +
+                                                       __longlong_as_double((long long)sh[t + s]));
+            else
+                sh[t] += sh[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        out[blockIdx.x] = sh[0];
+}
+
+typedef void (*SwRdFn)(SwRdArgs);
+
+template <int RULE, int MAP, int OP>
+static SwRdFn swrd_pick_r(int r)
+{
+    switch (r) {
+    case 0: return swrd_kernel<RULE, 0, MAP, OP>;
+    case 1: return swrd_kernel<RULE, 1, MAP, OP>;
+    case 2: return swrd_kernel<RULE, 2, MAP, OP>;
+    case 3: return swrd_kernel<RULE, 3, MAP, OP>;
+    case 4: return swrd_kernel<RULE, 4, MAP, OP>;
+    case 5: return swrd_kernel<RULE, 5, MAP, OP>;
+    case 6: return swrd_kernel<RULE, 6, MAP, OP>;
+    case 7: return swrd_kernel<RULE, 7, MAP, OP>;
+    default: return nullptr;
+    }
+}
+
+template <int OP>
+static SwRdFn swrd_pick(int map, int rule, int r)
+{
+    if (map == MAP_BB)
+        return rule == FRACTAL_RULE_CA ? swrd_pick_r<RULE_CA, MAP_BB, OP>(r)
+                                       : swrd_pick_r<RULE_HEAT, MAP_BB, OP>(r);
+    return rule == FRACTAL_RULE_CA ? swrd_pick_r<RULE_CA, MAP_LAMBDA, OP>(r)
+                                   : swrd_pick_r<RULE_HEAT, MAP_LAMBDA, OP>(r);
+}
+
+static int tiles_per_wave(int rule, int r)
+{
+    const int rbytes = (1 << r) * (int)cell_bytes(rule);
+    const int cb = rbytes < 16 ? rbytes : 16;
+    return 64 / (rbytes / cb);
+}
+
+static int check_swrd(int map, int k, int r, int rule, const void *buf)
+{
+    if (map != MAP_LAMBDA && map != MAP_BB)
+        return set_error(FRACTAL_E_INVAL, "map %d: SW and RD run on lambda (0) or BB (1)", map);
+    if (k < 0 || k > kMaxStepLevel || r < 0 || r > k || r > kMaxR || k - r > kMaxBlockLevel)
+        return set_error(FRACTAL_E_INVAL, "need 0 <= r <= min(k, %d), k <= %d, k - r <= %d "
+                         "(k=%d r=%d)", kMaxR, kMaxStepLevel, kMaxBlockLevel, k, r);
+    if (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT)
+        return set_error(FRACTAL_E_INVAL, "unknown rule %d", rule);
+    if (!buf)
+        return set_error(FRACTAL_E_INVAL, "null buffer");
+    if (reinterpret_cast<uintptr_t>(buf) % 16)
+        return set_error(FRACTAL_E_INVAL, "buffer must be 16-byte aligned");
+    return FRACTAL_OK;
+}
+
+static int launch_swrd(SwRdFn fn, int rule, int r, const SwRdArgs &a, hipStream_t s)
+{
+    const uint64_t P = (uint64_t)tiles_per_wave(rule, r);
+    const uint64_t waves = (a.total + P - 1) / P;
+    const uint64_t grid = (waves + 3) / 4;
+    SwRdArgs arg = a;
+    void *args[] = {&arg};
+    return hip_error(hipLaunchKernel((const void *)fn, dim3((unsigned)grid), dim3(256), args, 0, s),
+                     "SW/RD kernel launch");
+}
+
+// Sizes of the summation tree's levels: n_0 = 3^(k-r) slots, then
+// ceil(n_i / 4096) until one value remains (that one is the result).
+static std::vector<uint64_t> tree_levels(int k, int r)
+{
+    std::vector<uint64_t> lv{pow3_u64(k - r)};
+    while (lv.back() > 1)
+        lv.push_back((lv.back() + 4095) / 4096);
+    if (lv.size() == 1)
+        lv.push_back(1); // one slot still takes one pass
+    return lv;
+}
+
+} // namespace fractal
+
+using namespace fractal;
+
+extern "C" {
+
+int fractal_single_write(int map, int k, int r, int rule, uint32_t value, void *d_buf,
+                         void *stream)
+{
+    int rc = check_swrd(map, k, r, rule, d_buf);
+    if (rc)
+        return rc;
+    SwRdArgs a;
+    a.buf = static_cast<uint8_t *>(d_buf);
+    a.k = k;
+    a.rb = k - r;
+    a.total = map == MAP_BB ? (uint64_t)1 << (2 * (k - r)) : pow3_u64(k - r);
+    a.value = value;
+    a.slots = nullptr;
+    return launch_swrd(swrd_pick<OP_SW>(map, rule, r), rule, r, a, static_cast<hipStream_t>(stream));
+}
+
+int fractal_reduce_workspace(int k, int r, size_t *bytes)
+{
+    if (!bytes)
+        return set_error(FRACTAL_E_INVAL, "null output");
+    if (k < 0 || k > kMaxStepLevel || r < 0 || r > k || r > kMaxR || k - r > kMaxBlockLevel)
+        return set_error(FRACTAL_E_INVAL, "bad level k=%d r=%d", k, r);
+    const std::vector<uint64_t> lv = tree_levels(k, r);
+    uint64_t words = 0;
+    for (size_t i = 0; i + 1 < lv.size(); ++i)
+        words += lv[i];
+    *bytes = (size_t)(8 * words);
+    return FRACTAL_OK;
+}
+
+int fractal_reduce(int map, int k, int r, int rule, const void *d_buf, void *d_work,
+                   size_t work_bytes, void *d_out, void *stream)
+{
+    int rc = check_swrd(map, k, r, rule, d_buf);
+    if (rc)
+        return rc;
+    size_t need = 0;
+    if ((rc = fractal_reduce_workspace(k, r, &need)))
+        return rc;
+    if (!d_work || !d_out)
+        return set_error(FRACTAL_E_INVAL, "null workspace or output");
+    if (reinterpret_cast<uintptr_t>(d_work) % 8 || reinterpret_cast<uintptr_t>(d_out) % 8)
+        return set_error(FRACTAL_E_INVAL, "workspace and output must be 8-byte aligned");
+    if (work_bytes < need)
+        return set_error(FRACTAL_E_INVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t *w = static_cast<uint64_t *>(d_work);
+    SwRdArgs a;
+    a.buf = static_cast<uint8_t *>(const_cast<void *>(d_buf));
+    a.k = k;
+    a.rb = k - r;
+    a.total = map == MAP_BB ? (uint64_t)1 << (2 * (k - r)) : pow3_u64(k - r);
+    a.value = 0;
+    a.slots = w;
+    if ((rc = launch_swrd(swrd_pick<OP_RD>(map, rule, r), rule, r, a, s)))
+        return rc;
+    const std::vector<uint64_t> lv = tree_levels(k, r);
+    uint64_t *in = w;
+    for (size_t i = 0; i + 1 < lv.size(); ++i) {
+        uint64_t *out = (i + 2 == lv.size()) ? static_cast<uint64_t *>(d_out) : in + lv[i];
+        if (rule == FRACTAL_RULE_HEAT)
+            hipLaunchKernelGGL(tree_kernel<true>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
+                               lv[i], out);
+        else
+            hipLaunchKernelGGL(tree_kernel<false>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
+                               lv[i], out);
+        if ((rc = hip_error(hipGetLastError(), "reduction tree launch")))
+            return rc;
+        in = out;
+    }
+    return FRACTAL_OK;
+}
+
+} // extern "C"
