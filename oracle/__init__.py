@@ -197,3 +197,48 @@ def reduce_(k: int, state: np.ndarray):
     if vals.dtype == np.uint8:
         return int(vals.astype(np.int64).sum())
     return math.fsum(vals.astype(np.float64).tolist())
+
+
+def compact_index(k: int, r: int, x, y):
+    """Offset of cell (x, y) in compact storage (Section 7: the data packed
+    into the orthotope by lambda^-1): tiles of side 2^r kept in the order
+    whose base-3 digits beta_mu (mu = 1..k-r) give the tile's block through
+    Theorem 1's table (mirrored: x bit = [beta == 2], y bit = [beta == 0]),
+    each tile's box row-major.  Inverting digit by digit: beta_mu = 2 where
+    bit mu-1 of the block x is set, 0 where that of y is, 1 where neither.
+    Works on integers or integer arrays."""
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    rho = 1 << r
+    bx, by = x >> r, y >> r
+    L = np.zeros_like(x)
+    for mu in range(k - r - 1, -1, -1):
+        xb = (bx >> mu) & 1
+        yb = (by >> mu) & 1
+        L = 3 * L + np.where(xb == 1, 2, np.where(yb == 1, 0, 1))
+    return (L * rho + (y & (rho - 1))) * rho + (x & (rho - 1))
+
+
+def pack(k: int, r: int, state: np.ndarray) -> np.ndarray:
+    """The compact state (1-D, 3^(k-r) * 4^r cells) holding the boxes of the
+    non-empty tiles of the n x n `state`."""
+    n = 1 << k
+    rho = 1 << r
+    out = np.zeros(3 ** (k - r) * rho * rho, dtype=state.dtype)
+    ys, xs = np.meshgrid(np.arange(n, dtype=np.int64), np.arange(n, dtype=np.int64),
+                         indexing="ij")
+    live = ((xs >> r) & (ys >> r)) == 0
+    out[compact_index(k, r, xs[live], ys[live])] = state[live]
+    return out
+
+
+def unpack(k: int, r: int, compact: np.ndarray) -> np.ndarray:
+    """The n x n state whose non-empty tile boxes come from `compact` (cells
+    of empty tiles 0)."""
+    n = 1 << k
+    out = np.zeros((n, n), dtype=compact.dtype)
+    ys, xs = np.meshgrid(np.arange(n, dtype=np.int64), np.arange(n, dtype=np.int64),
+                         indexing="ij")
+    live = ((xs >> r) & (ys >> r)) == 0
+    out[live] = compact[compact_index(k, r, xs[live], ys[live])]
+    return out

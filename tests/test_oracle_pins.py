@@ -302,3 +302,53 @@ def test_reduce_of_seeded_heat_state_is_exact():
     st = fi.full_state(k, 1, 5)
     num = int((st.astype(np.float64) * (1 << 24)).astype(np.int64).sum())
     assert oracle.reduce_(k, st) == num / float(1 << 24)
+
+
+# ------------------------------------------- compact storage (Section 7)
+def _omega_of_curve(L, rb):
+    """omega of the compact grid whose digits are those of L: odd mu (digit
+    mu-1 of L, mu-1 even) to omega_x, even mu to omega_y (Theorem 1)."""
+    wx = wy = 0
+    px = py = 1
+    for mu in range(1, rb + 1):
+        d = L % 3
+        L //= 3
+        if mu % 2 == 1:
+            wx += d * px
+            px *= 3
+        else:
+            wy += d * py
+            py *= 3
+    return wx, wy
+
+
+@pytest.mark.parametrize("k,r", [(2, 0), (4, 1), (5, 2), (6, 3), (7, 2), (8, 4), (9, 5)])
+def test_compact_tile_order_is_lambda(k, r):
+    """Tile L of compact storage is the block lambda(omega) of the paper's
+    map (the oracle's step-by-step Theorem 1 construction, mirrored) for the
+    omega whose digits are L's: its first cell sits at offset L * rho^2."""
+    rb = k - r
+    rho = 1 << r
+    for L in range(3 ** rb):
+        wx, wy = _omega_of_curve(L, rb)
+        lx, ly = oracle.lambda_(rb, wx, wy)
+        assert int(oracle.compact_index(k, r, lx * rho, ly * rho)) == L * rho * rho
+
+
+@pytest.mark.parametrize("k,r", [(3, 0), (5, 2), (7, 3), (8, 5), (9, 7)])
+def test_compact_index_bijection_and_round_trip(k, r):
+    """Cells of non-empty tiles map one to one onto [0, 3^(k-r) 4^r); pack
+    then unpack restores every cell of a gasket-supported state, and the
+    member count is 3^k after packing (Eq. 2)."""
+    n = 1 << k
+    ys, xs = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    live = ((xs >> r) & (ys >> r)) == 0
+    idx = oracle.compact_index(k, r, xs[live], ys[live])
+    size = 3 ** (k - r) * 4 ** r
+    assert np.array_equal(np.sort(idx), np.arange(size))
+    st = fi.full_state(k, 0, 9)
+    c = oracle.pack(k, r, st)
+    assert c.size == size and int(c.sum()) == int(st.sum())
+    assert np.array_equal(oracle.unpack(k, r, c), st)
+    ones = oracle.pack(k, r, oracle.single_write(k, 0, 1))
+    assert int(ones.sum()) == 3 ** k
