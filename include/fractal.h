@@ -218,6 +218,47 @@ int fractal_reduce_workspace(int k, int r, size_t *bytes);
 int fractal_reduce(int map, int k, int r, int rule, const void *d_buf,
                    void *d_work, size_t work_bytes, void *d_out, void *stream);
 
+/* Compact storage through lambda^-1 (the compact manipulation that Section 7
+ * names as future work): a state of level k with tiles of side rho = 2^r
+ * keeps only its 3^(k-r) non-empty tiles.  Tile L (0 <= L < 3^(k-r)) is the
+ * one whose block is lambda(L) in the curve order -- base-3 digit mu-1 of L
+ * is beta_mu, block bit mu-1 of x is [beta == 2] and of y is [beta == 0] --
+ * and its rho x rho box is stored row-major at cell offset L * rho^2; so
+ * cell (x, y) of the gasket lives at
+ *   (lambda^-1(x >> r, y >> r) * rho + (y & (rho-1))) * rho + (x & (rho-1)).
+ * Box cells off the gasket hold 0.  Size 3^(k-r) * 4^r cells instead of 4^k,
+ * which lets one GPU hold levels up to 20.  Tile rows must span >= 16 bytes
+ * (r >= 4 for uint8 cells, r >= 2 for float32); 0 <= r <= 7, k - r <= 18. */
+
+/* Bytes of one compact state; k <= 20. */
+int fractal_compact_bytes(int k, int r, int rule, size_t *bytes);
+
+/* Copy the tile boxes of an n x n state (k <= 16) into compact storage
+ * (pack) or back (unpack; cells of empty tiles are not written).  Buffers
+ * device, 16-byte aligned, non-overlapping. */
+int fractal_pack(int k, int r, int rule, const void *d_embedded, void *d_compact,
+                 void *stream);
+int fractal_unpack(int k, int r, int rule, const void *d_compact, void *d_embedded,
+                   void *stream);
+
+/* Seeded initial state written directly in compact storage: every box cell
+ * gets the value fractal_seed_fill gives the same (x, y) (the SplitMix64
+ * counter y * n + x taken modulo 2^64 beyond level 16); k <= 20. */
+int fractal_compact_seed_fill(int k, int r, int rule, uint32_t stream_id,
+                              void *d_compact, void *stream);
+
+/* `steps` steps of `rule` on a compact state, ping-ponging between d_c0 and
+ * d_c1 (result in buf[steps & 1]) with the register-march engine; each lane
+ * finds the tiles around its own through lambda^-1.  Results equal
+ * pack(fractal_lambda_step(unpack(state))) bit for bit.  flags: 0 for the
+ * default (the longest launch the tile allows up to 16 steps for the
+ * automaton from level 15, else 8; non-temporal stores from level 15), or
+ * FRACTAL_FLAG_FUSE2/4/8/16 and FRACTAL_FLAG_NT_STORE (MARCH and SEGMENTS
+ * are implied and accepted); steps per launch and halo must fit in one
+ * tile (T <= rho).  k <= 20; buffers of fractal_compact_bytes each. */
+int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0,
+                         void *d_c1, int steps, int flags, void *stream);
+
 /* One gasket of a batch. */
 typedef struct fractal_instance {
     int k;       /* level, 0..16                                  */

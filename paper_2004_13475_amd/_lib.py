@@ -28,6 +28,8 @@ EXPORTED = [
     "fractal_lambda_step_mfma", "fractal_step_tuned", "fractal_autotune",
     "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_step",
     "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
+    "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
+    "fractal_compact_step",
     "fractal_now", "fractal_serve_create", "fractal_serve_submit",
     "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
 ]
@@ -97,6 +99,11 @@ def load():
         "fractal_single_write": ([i, i, i, i, u32, vp, vp], i),
         "fractal_reduce_workspace": ([i, i, ctypes.POINTER(ctypes.c_size_t)], i),
         "fractal_reduce": ([i, i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
+        "fractal_compact_bytes": ([i, i, i, ctypes.POINTER(ctypes.c_size_t)], i),
+        "fractal_pack": ([i, i, i, vp, vp, vp], i),
+        "fractal_unpack": ([i, i, i, vp, vp, vp], i),
+        "fractal_compact_seed_fill": ([i, i, i, u32, vp, vp], i),
+        "fractal_compact_step": ([i, i, i, f, vp, vp, i, i, vp], i),
         "fractal_now": ([], ctypes.c_double),
         "fractal_serve_create": ([vp, ctypes.c_size_t, i, i, vp, ctypes.POINTER(vp)], i),
         "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
@@ -234,6 +241,33 @@ def reduce(map_, k, r, rule, buf, work, out, stream=None):
     nbytes = work.numel() * work.element_size() if hasattr(work, "numel") else 1 << 62
     return _check(load().fractal_reduce(map_, k, r, rule, _ptr(buf), _ptr(work), nbytes,
                                         _ptr(out), _stream(stream)))
+
+
+def compact_bytes(k, r, rule) -> int:
+    """Bytes of one compact state (tiles of side 2^r kept in lambda order)."""
+    b = ctypes.c_size_t()
+    _check(load().fractal_compact_bytes(k, r, rule, ctypes.byref(b)))
+    return b.value
+
+
+def pack(k, r, rule, embedded, compact, stream=None):
+    return _check(load().fractal_pack(k, r, rule, _ptr(embedded), _ptr(compact),
+                                      _stream(stream)))
+
+
+def unpack(k, r, rule, compact, embedded, stream=None):
+    return _check(load().fractal_unpack(k, r, rule, _ptr(compact), _ptr(embedded),
+                                        _stream(stream)))
+
+
+def compact_seed_fill(k, r, rule, stream_id, compact, stream=None):
+    return _check(load().fractal_compact_seed_fill(k, r, rule, stream_id, _ptr(compact),
+                                                   _stream(stream)))
+
+
+def compact_step(k, r, rule, alpha, buf0, buf1, steps, flags=0, stream=None):
+    return _check(load().fractal_compact_step(k, r, rule, alpha, _ptr(buf0), _ptr(buf1), steps,
+                                              flags, _stream(stream)))
 
 
 def now() -> float:

@@ -115,6 +115,19 @@ __device__ __forceinline__ TileXY lambda_mfma(BetaFn beta_for, int rb)
     return TileXY{px, nb1 - py};
 }
 
+// lambda^-1: the curve index of non-empty tile (x, y) of a level-rb tile
+// space, the inverse of lambda on the curve order: base-3 digit mu-1 is 2
+// where bit mu-1 of x is set, 0 where that of y is set, 1 where neither.
+__device__ __forceinline__ uint32_t lambda_inverse(uint32_t x, uint32_t y, int rb)
+{
+    uint32_t L = 0u;
+    for (int mu = rb - 1; mu >= 0; --mu) {
+        const uint32_t bx = (x >> mu) & 1u, by = (y >> mu) & 1u;
+        L = 3u * L + (bx ? 2u : (by ? 0u : 1u));
+    }
+    return L;
+}
+
 // Split [0, N) into 8 contiguous ranges, one per accelerator die: hardware
 // workgroup b runs on die b % 8 (round-robin dispatch), and becomes the
 // (b / 8)-th id of that die's range.  A bijection of [0, N).

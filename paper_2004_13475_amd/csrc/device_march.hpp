@@ -258,9 +258,33 @@ struct MarchLane {
 // level-k state: src -> dst, T steps.  Every argument may differ between
 // groups; all 64 lanes must call it (the level updates read neighbouring
 // lanes), inactive groups with active = false.
-template <int RULE, int R, int T, int HL, int FL, int D>
-__device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int k, float alpha,
-                                           TileXY t, int band, int band_log, bool active, int col)
+// Where a lane's chunk column of walk row i (array row y) lives, for a
+// state stored as the n x n array: `has` tells whether row y has storage,
+// `ld` / `st` give the chunk's address in the input / output state.
+struct EmbeddedAddr {
+    const uint8_t *src;
+    uint8_t *dst;
+    int64_t off0;  // byte offset of the chunk in walk row 0
+    int64_t pitch; // bytes per array row
+    int n;
+    __device__ __forceinline__ bool has(int y) const { return y >= 0 && y < n; }
+    __device__ __forceinline__ const uint8_t *ld(int i, int) const
+    {
+        return src + off0 + (int64_t)i * pitch;
+    }
+    __device__ __forceinline__ uint8_t *st(int i, int) const
+    {
+        return dst + off0 + (int64_t)i * pitch;
+    }
+};
+
+// The walk of one group over the band of H rows starting at array row ybase,
+// chunk column starting at array column xc: src -> dst through `A`, T steps.
+// Every argument may differ between groups; all 64 lanes must call it (the
+// level updates read neighbouring lanes), inactive groups with col_ok false.
+template <int RULE, int R, int T, int HL, int FL, int D, class Addr>
+__device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha, int xc,
+                                              int ybase, int H, bool col_ok, bool interior)
 {
     using M = MGeom<RULE, R, T, HL>;
     using RU = MarchRule<RULE>;
@@ -270,22 +294,15 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
     constexpr int U = RU::U;
     static_assert(U % Q == 0 && U % D == 0, "unrolled pass: whole row periods and ring turns");
     const int n = 1 << k;
-    const int H = M::RHO >> band_log; // band height, a multiple of Q
-    const int xc = (int)(t.x << R) + col * M::CC;
-    const int ybase = (int)(t.y << R) + band * H; // first row of the band
-    const bool col_ok = active && xc >= 0 && xc < n;
-    const bool interior = col >= 0 && col < M::IL;
-    const int64_t pitch = (int64_t)n * M::S;
-    const int64_t off0 = ((int64_t)ybase - T) * pitch + (int64_t)xc * M::S;
     const int rows = H + 2 * T;
     const float c1 = 1.0f - 4.0f * alpha;
 
     auto load_row = [&](int i) -> u32x4 {
         const int y = ybase - T + i;
         u32x4 v = {0u, 0u, 0u, 0u};
-        if (i < rows && col_ok && y >= 0 && y < n &&
+        if (i < rows && col_ok && A.has(y) &&
             ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u))
-            v = *reinterpret_cast<const u32x4 *>(src + off0 + (int64_t)i * pitch);
+            v = *reinterpret_cast<const u32x4 *>(A.ld(i, y));
         return v;
     };
 
@@ -327,7 +344,7 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
             if (interior && col_ok && j >= 0 && j < H &&
                 ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u)) {
                 const u32x4 o = RU::store(cur);
-                u32x4 *dp = reinterpret_cast<u32x4 *>(dst + off0 + (int64_t)(j + T) * pitch);
+                u32x4 *dp = reinterpret_cast<u32x4 *>(A.st(j + T, y));
                 if constexpr (FL & TILE_NT_STORE)
                     __builtin_nontemporal_store(o, dp);
                 else
@@ -335,6 +352,26 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
             }
         });
     }
+}
+
+// march_walk_at over the n x n array: band `band` (of 2^band_log) of tile t.
+template <int RULE, int R, int T, int HL, int FL, int D>
+__device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int k, float alpha,
+                                           TileXY t, int band, int band_log, bool active, int col)
+{
+    using M = MGeom<RULE, R, T, HL>;
+    const int n = 1 << k;
+    const int H = M::RHO >> band_log; // band height, a multiple of the row period
+    const int xc = (int)(t.x << R) + col * M::CC;
+    const int ybase = (int)(t.y << R) + band * H; // first row of the band
+    EmbeddedAddr A;
+    A.src = src;
+    A.dst = dst;
+    A.pitch = (int64_t)n * M::S;
+    A.off0 = ((int64_t)ybase - T) * A.pitch + (int64_t)xc * M::S;
+    A.n = n;
+    march_walk_at<RULE, R, T, HL, FL, D>(A, k, alpha, xc, ybase, H,
+                                         active && xc >= 0 && xc < n, col >= 0 && col < M::IL);
 }
 
 // One gasket: wavefront w of the grid takes (tile, band) items w*P .. w*P+P-1

@@ -7,30 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "seed.hpp"
 
 namespace fractal {
-
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t i)
-{
-    uint64_t z = (i + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Cell value as a 32-bit pattern: automaton top bit, heat (z >> 40) * 2^-24.
-template <int RULE>
-__device__ __forceinline__ uint32_t seeded_cell(uint64_t base, uint32_t x, uint32_t y,
-                                                int k)
-{
-    if ((x & y) != 0u)
-        return 0u;
-    const uint64_t z = splitmix64_at(base + ((uint64_t)y << k) + x);
-    if constexpr (RULE == FRACTAL_RULE_CA)
-        return (uint32_t)(z >> 63);
-    else
-        return __float_as_uint((float)(uint32_t)(z >> 40) * 0x1.0p-24f);
-}
 
 // Each thread fills one 16-byte chunk (16 automaton cells or 4 heat cells)
 // of a row; rows narrower than a chunk are filled cell by cell.

@@ -38,18 +38,6 @@ struct SwRdArgs {
     uint64_t *slots;  // RD: one 8-byte partial per non-empty tile
 };
 
-// lambda^-1: the curve index of non-empty tile (x, y): base-3 digit mu-1 is
-// 2 where bit mu-1 of x is set, 0 where that of y is set, 1 where neither.
-__device__ __forceinline__ uint32_t lambda_inverse(uint32_t x, uint32_t y, int rb)
-{
-    uint32_t L = 0u;
-    for (int mu = rb - 1; mu >= 0; --mu) {
-        const uint32_t bx = (x >> mu) & 1u, by = (y >> mu) & 1u;
-        L = 3u * L + (bx ? 2u : (by ? 0u : 1u));
-    }
-    return L;
-}
-
 template <int CB>
 __device__ __forceinline__ void chunk_load(const uint8_t *p, uint8_t (&b)[CB])
 {

@@ -139,3 +139,21 @@ def test_oracle_and_product_share_nothing():
         if f.endswith((".py", ".c", ".h")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2004_13475_amd" not in txt and "csrc" not in txt
+
+
+def test_compact_sizes_and_validation():
+    """Compact storage holds 3^(k-r) tiles of 4^r cells; tile rows must span
+    16 bytes, k <= 20, k - r <= 18."""
+    for rule, S in ((0, 1), (1, 4)):
+        for k in range(0, 21):
+            for r in range(0, 8):
+                ok = r <= k and k - r <= 18 and (1 << r) * S >= 16
+                if ok:
+                    assert F.compact_bytes(k, r, rule) == 3 ** (k - r) * 4 ** r * S
+                else:
+                    with pytest.raises(F.FractalError):
+                        F.compact_bytes(k, r, rule)
+    with pytest.raises(F.FractalError):
+        F.compact_bytes(21, 7, 0)
+    # zero steps is a no-op that touches no device memory
+    F.compact_step(10, 4, 0, 0.2, FAKE0, FAKE1, 0, 0, stream=0)
