@@ -17,6 +17,7 @@ Also on the same JSON line:
                 256 plain lambda_step calls
   serve         (with --serve SECONDS) Poisson request stream, p50/p99
   sw_rd         tests SW (single write) and RD (reduction), lambda vs BB
+  compact       compact storage through lambda^-1 at levels 16, 18, 20
   cpu_baseline  the CPU oracle on a bounded sample of the default workload
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
@@ -265,6 +266,41 @@ def sw_rd_leg(F, torch, k, reps=20):
         out[RULE_NAME[rule]] = row
         del buf
         torch.cuda.empty_cache()
+    return out
+
+
+def compact_leg(F, torch, steps=64):
+    """Compact storage (tiles kept in lambda order): per-step time and cell
+    rate at levels 16, 18 and 20 with the default compact launch, and the
+    state bytes against the n x n array's."""
+    stream = torch.cuda.current_stream()
+    alpha = float(__import__("numpy").float32(ALPHA))
+    out = {}
+    for rule, r in ((0, 6), (1, 5)):
+        row = {}
+        for k in (16, 18, 20):
+            nbytes = F.compact_bytes(k, r, rule)
+            free, _ = torch.cuda.mem_get_info()
+            if 2 * nbytes + (1 << 30) > free:
+                row[f"k{k}"] = {"skipped": "device memory"}
+                continue
+            c0 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            c1 = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+            F.compact_seed_fill(k, r, rule, 1, c0)
+            F.compact_step(k, r, rule, alpha, c0, c1, 32)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            F.compact_step(k, r, rule, alpha, c0, c1, steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / steps
+            row[f"k{k}"] = {"r": r, "us_per_step": sec * 1e6, "cells_per_s": 3 ** k / sec,
+                            "state_GB": nbytes / 1e9,
+                            "array_state_GB": (1 << (2 * k)) * (1 if rule == 0 else 4) / 1e9}
+            del c0, c1
+            torch.cuda.empty_cache()
+        out[RULE_NAME[rule]] = row
     return out
 
 
@@ -556,6 +592,7 @@ def main() -> int:
     serve = serve_leg(F, torch, args.serve) if args.serve > 0 else None
     sweep = sweep_k_leg(F, torch) if args.sweep_k else None
     swrd = None if args.no_bb else {f"k{kk}": sw_rd_leg(F, torch, kk) for kk in sorted({k, 16})}
+    compact = None if args.no_k16 else compact_leg(F, torch)
     ceiling = None if args.no_bb else copy_ceiling(torch)
 
     cpu = None
@@ -592,7 +629,7 @@ def main() -> int:
                                     "roofline": rfs[r]}
                      for r in (0, 1)},
         "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
-        "sw_rd": swrd,
+        "sw_rd": swrd, "compact": compact,
         "lambda_vs_bb_by_k": sweep,
         "device_copy_GBs": ceiling,
         "cpu_baseline": cpu,
