@@ -242,3 +242,71 @@ def unpack(k: int, r: int, compact: np.ndarray) -> np.ndarray:
     live = ((xs >> r) & (ys >> r)) == 0
     out[live] = compact[compact_index(k, r, xs[live], ys[live])]
     return out
+
+
+# ------------------------------------------------------------ NBB family
+def nbb_member_mask(replicas, s: int, level: int, x0: int = 0, y0: int = 0,
+                    w: int | None = None, h: int | None = None) -> np.ndarray:
+    """Membership of the level-`level` NBB fractal (Section 3): cell (x, y)
+    of the s^level x s^level embedding belongs to it iff, at every scale, the
+    base-s digit pair (x_d, y_d) is the offset of one of the replicas.  For
+    the window [x0, x0+w) x [y0, y0+h); cells outside the embedding are not
+    members."""
+    n = s ** level
+    w = n if w is None else w
+    h = n if h is None else h
+    xs = np.arange(x0, x0 + w, dtype=np.int64)[None, :]
+    ys = np.arange(y0, y0 + h, dtype=np.int64)[:, None]
+    allowed = np.zeros((s, s), dtype=bool)
+    for (tx, ty) in replicas:
+        allowed[ty, tx] = True
+    m = (xs >= 0) & (xs < n) & (ys >= 0) & (ys < n)
+    xv, yv = np.clip(xs, 0, n - 1), np.clip(ys, 0, n - 1)
+    for _ in range(level):
+        m = m & allowed[yv % s, xv % s]
+        xv, yv = xv // s, yv // s
+    return m
+
+
+def nbb_lambda(replicas, s: int, rb: int, wx: int, wy: int):
+    """Theorem 1 for any NBB table, step by step: for mu = 1..rb, beta_mu is
+    the base-k digit ceil(mu/2) - 1 of omega_x (odd mu) or omega_y (even
+    mu), tau = H[beta_mu], Delta^mu = tau * s^(mu-1), and lambda is the sum
+    of the Delta^mu."""
+    k = len(replicas)
+    lx = ly = 0
+    for mu in range(1, rb + 1):
+        v = wx if mu % 2 == 1 else wy
+        beta = (v // k ** ((mu + 1) // 2 - 1)) % k
+        tx, ty = replicas[beta]
+        lx += tx * s ** (mu - 1)
+        ly += ty * s ** (mu - 1)
+    return lx, ly
+
+
+def nbb_single_write(replicas, s: int, level: int, value: int) -> np.ndarray:
+    """Test SW on an NBB fractal: `value` (uint8) on every member, 0 elsewhere."""
+    return nbb_member_mask(replicas, s, level).astype(np.uint8) * np.uint8(value & 0xFF)
+
+
+def nbb_reduce(replicas, s: int, level: int, state: np.ndarray) -> int:
+    """Test RD on an NBB fractal: the exact integer sum of the members."""
+    return int(np.asarray(state)[nbb_member_mask(replicas, s, level)].astype(np.int64).sum())
+
+
+def nbb_ca_run(replicas, s: int, level: int, state: np.ndarray, steps: int,
+               x0: int = 0, y0: int = 0) -> np.ndarray:
+    """`steps` synchronous steps of the test-CA rule (Section 6.2: Moore
+    neighbourhood, fractal cells only, B3/S23) on a window of the NBB
+    fractal whose top-left cell is (x0, y0); cells outside the window count
+    as dead."""
+    a = (np.asarray(state) != 0).astype(np.int64)
+    h, w = a.shape
+    mask = nbb_member_mask(replicas, s, level, x0, y0, w, h)
+    a = a * mask
+    for _ in range(steps):
+        p = np.pad(a, 1)
+        cnt = sum(p[1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
+                  for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dx, dy) != (0, 0))
+        a = (((cnt == 3) | ((a == 1) & (cnt == 2))) & mask).astype(np.int64)
+    return a.astype(np.uint8)

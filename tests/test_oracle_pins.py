@@ -352,3 +352,114 @@ def test_compact_index_bijection_and_round_trip(k, r):
     assert np.array_equal(oracle.unpack(k, r, c), st)
     ones = oracle.pack(k, r, oracle.single_write(k, 0, 1))
     assert int(ones.sum()) == 3 ** k
+
+
+# --------------------------------------------------- NBB family (Sec. 3)
+NBB_TABLES = {
+    "gasket": ([(0, 0), (0, 1), (1, 1)], 2),
+    "carpet": ([(0, 0), (1, 0), (2, 0), (0, 1), (2, 1), (0, 2), (1, 2), (2, 2)], 3),
+    "vicsek": ([(1, 0), (0, 1), (1, 1), (2, 1), (1, 2)], 3),
+    "xfractal": ([(0, 0), (2, 0), (1, 1), (0, 2), (2, 2)], 3),
+    "cantor": ([(0, 0), (2, 0)], 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NBB_TABLES))
+def test_nbb_member_count_and_dimension(name):
+    """Eq. 2 and Lemma 1: k^level members, Hausdorff exponent log k / log s."""
+    reps, s = NBB_TABLES[name]
+    k = len(reps)
+    for level in range(0, 6 if s == 3 else 9):
+        m = oracle.nbb_member_mask(reps, s, level)
+        assert int(m.sum()) == k ** level
+        if level >= 2:
+            n = s ** level
+            assert abs(math.log(m.sum()) / math.log(n) - math.log(k) / math.log(s)) < 1e-12
+
+
+def test_nbb_carpet_golden_and_gasket_orientation():
+    """The carpet at level 2 equals the hand-drawn fixture; the gasket table
+    gives the paper's orientation x & (n - 1 - y) == 0 (Section 6.1)."""
+    rows = [l.strip() for l in open(os.path.join(GOLDEN, "nbb_carpet_level2.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 9 and all(len(r) == 9 for r in rows)
+    want = np.array([[c == "X" for c in r] for r in rows])
+    reps, s = NBB_TABLES["carpet"]
+    assert np.array_equal(oracle.nbb_member_mask(reps, s, 2), want)
+    reps, s = NBB_TABLES["gasket"]
+    for level in range(0, 8):
+        n = 1 << level
+        ys, xs = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        assert np.array_equal(oracle.nbb_member_mask(reps, s, level), (xs & (n - 1 - ys)) == 0)
+
+
+@pytest.mark.parametrize("name", sorted(NBB_TABLES))
+def test_nbb_lambda_bijection_on_lemma2_grid(name):
+    """Theorem 1 / Lemma 2: the map from the k^ceil(rb/2) x k^floor(rb/2)
+    grid hits every non-empty block exactly once (brute force)."""
+    reps, s = NBB_TABLES[name]
+    k = len(reps)
+    for rb in range(0, 6 if k <= 5 else 5):
+        gx, gy = k ** ((rb + 1) // 2), k ** (rb // 2)
+        seen = set()
+        for wy in range(gy):
+            for wx in range(gx):
+                seen.add(oracle.nbb_lambda(reps, s, rb, wx, wy))
+        blocks = oracle.nbb_member_mask(reps, s, rb)
+        want = {(int(x), int(y)) for y, x in zip(*np.nonzero(blocks))}
+        assert seen == want and len(want) == gx * gy
+
+
+def test_nbb_lambda_gasket_matches_specialised_oracle():
+    """With the gasket's table the general map is the gasket map of the C
+    oracle in the paper's orientation."""
+    reps, s = NBB_TABLES["gasket"]
+    for rb in range(0, 9):
+        gx, gy = 3 ** ((rb + 1) // 2), 3 ** (rb // 2)
+        for wy in range(gy):
+            for wx in range(gx):
+                assert oracle.nbb_lambda(reps, s, rb, wx, wy) == oracle.lambda_paper(rb, wx, wy)
+
+
+def test_nbb_ca_gasket_matches_c_oracle_mirrored():
+    """On the gasket table the NBB automaton is the C oracle's automaton
+    mirrored vertically (the two orientations of Section 6.1)."""
+    reps, s = NBB_TABLES["gasket"]
+    for k in (3, 6, 8):
+        st = fi.full_state(k, 0, 21)        # (x & y) == 0 orientation
+        mirrored = st[::-1, :].copy()       # x & (n-1-y) == 0 orientation
+        for steps in (1, 3, 7):
+            a = oracle.nbb_ca_run(reps, s, k, mirrored, steps)
+            b = oracle.ca_run(k, st, steps)[::-1, :]
+            assert np.array_equal(a, b), (k, steps)
+
+
+@pytest.mark.parametrize("name", ["carpet", "vicsek", "xfractal"])
+def test_nbb_ca_equals_textbook_life_then_mask(name):
+    """On any NBB fractal the automaton equals textbook Game of Life on the
+    zero-padded array (library convolution) followed by clearing the cells
+    off the fractal, since cells off the fractal stay 0."""
+    reps, s = NBB_TABLES[name]
+    level = 4
+    n = s ** level
+    rng = np.random.default_rng(5)
+    mask = oracle.nbb_member_mask(reps, s, level)
+    st = (rng.random((n, n)) < 0.5).astype(np.uint8) * mask
+    kern = np.ones((3, 3), dtype=np.int64)
+    kern[1, 1] = 0
+    ref = st.astype(np.int64)
+    for _ in range(6):
+        cnt = signal.convolve2d(ref, kern, mode="same", boundary="fill")
+        ref = (((cnt == 3) | ((ref == 1) & (cnt == 2))) & mask).astype(np.int64)
+    assert np.array_equal(oracle.nbb_ca_run(reps, s, level, st, 6), ref.astype(np.uint8))
+
+
+def test_nbb_single_write_and_reduce():
+    reps, s = NBB_TABLES["carpet"]
+    for level in range(0, 5):
+        sw = oracle.nbb_single_write(reps, s, level, 0x133)
+        assert int((sw != 0).sum()) == 8 ** level and set(np.unique(sw)) <= {0, 0x33}
+        assert oracle.nbb_reduce(reps, s, level, sw) == 0x33 * 8 ** level
+        junk = sw.copy()
+        junk[sw == 0] = 200
+        assert oracle.nbb_reduce(reps, s, level, junk) == 0x33 * 8 ** level
