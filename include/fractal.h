@@ -259,6 +259,60 @@ int fractal_compact_seed_fill(int k, int r, int rule, uint32_t stream_id,
 int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0,
                          void *d_c1, int steps, int flags, void *stream);
 
+/* General NBB fractals (Section 3, Table 1): a fractal of the family is
+ * given by k replicas per level on an s x s grid, replica beta (0 <= beta <
+ * k) at offset H[beta] = (tau_x[beta], tau_y[beta]), distinct cells of
+ * [0, s)^2.  The level-R fractal lives in an n x n uint8 array, n = s^R,
+ * row-major; cell (x, y) is a member iff every base-s digit pair (x_d, y_d)
+ * is a replica offset; it has k^R members (Eq. 2).  Tiles have side s^r;
+ * map 0 launches Theorem 1's compact grid of k^ceil(r_b/2) x k^floor(r_b/2)
+ * workgroups (r_b = R - r), map 1 the bounding box of (n/s^r)^2.  Limits:
+ * 2 <= s <= 8, k <= min(s^2, 32), n <= 65536 with n^2 <= 2^32, s^r <= 128.
+ * The paper's Table 1 shows the replica grids only as figures; the built-in
+ * tables are the usual definitions of those fractals. */
+#define FRACTAL_NBB_MAX_K 32
+typedef struct fractal_nbb {
+    int k; /* replicas per level */
+    int s; /* scale factor per level */
+    uint8_t tau_x[FRACTAL_NBB_MAX_K];
+    uint8_t tau_y[FRACTAL_NBB_MAX_K];
+} fractal_nbb;
+#define FRACTAL_NBB_GASKET 0  /* (3, 2), H = {(0,0), (0,1), (1,1)}: x & (n-1-y) == 0 */
+#define FRACTAL_NBB_CARPET 1  /* (8, 3): all but the centre                        */
+#define FRACTAL_NBB_VICSEK 2  /* (5, 3): centre and the four edge midpoints         */
+#define FRACTAL_NBB_XFRACTAL 3 /* (5, 3): centre and the four corners               */
+#define FRACTAL_NBB_HFRACTAL 4 /* (7, 3): left and right columns and the centre     */
+#define FRACTAL_NBB_CANTOR 5  /* (2, 3): (0,0) and (2,0), a Cantor set on one row   */
+
+/* A built-in table (host only); replicas numbered in row-major order of their
+ * grid cells, except the gasket, which keeps the paper's numbering. */
+int fractal_nbb_builtin(int which, fractal_nbb *out);
+
+/* Theorem 1 for any NBB table: lambda(omega) for every omega of the
+ * k^ceil(rb/2) x k^floor(rb/2) grid into d_xy[2*(wy*gx+wx) + {0,1}]; every
+ * wavefront sums the levels' offsets tau * s^(mu-1) by a butterfly over its
+ * lanes.  s^rb and k^rb <= 2^31. */
+int fractal_nbb_lambda_map(const fractal_nbb *f, int rb, uint32_t *d_xy, void *stream);
+
+/* Test SW on an NBB fractal: value (low byte) on every member of d_buf
+ * (n x n uint8); other cells untouched. */
+int fractal_nbb_single_write(const fractal_nbb *f, int map, int level, int r,
+                             uint32_t value, void *d_buf, void *stream);
+
+/* Test RD on an NBB fractal: *d_out (uint64, device) = sum of the member
+ * cells; per-tile sums go to the tile's compact-grid slot (the inverse map
+ * for BB) and a fixed tree adds them, so both maps agree bit for bit. */
+int fractal_nbb_reduce_workspace(const fractal_nbb *f, int level, int r, size_t *bytes);
+int fractal_nbb_reduce(const fractal_nbb *f, int map, int level, int r,
+                       const void *d_buf, void *d_work, size_t work_bytes,
+                       void *d_out, void *stream);
+
+/* Test CA on an NBB fractal: `steps` synchronous B3/S23 steps counting
+ * fractal Moore neighbours (cells off the fractal must hold 0 in both
+ * buffers), ping-ponging d_buf0 -> d_buf1; result in buf[steps & 1]. */
+int fractal_nbb_ca_step(const fractal_nbb *f, int map, int level, int r,
+                        void *d_buf0, void *d_buf1, int steps, void *stream);
+
 /* One gasket of a batch. */
 typedef struct fractal_instance {
     int k;       /* level, 0..16                                  */

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libfractal.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_AGAIN = 0, 1, 2, 3, 4
 RULE_CA, RULE_HEAT = 0, 1
+NBB_GASKET, NBB_CARPET, NBB_VICSEK, NBB_XFRACTAL, NBB_HFRACTAL, NBB_CANTOR = range(6)
 ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
 FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2, FLAG_FUSE4 = 1, 2, 4, 8, 16
 FLAG_MARCH, FLAG_FUSE8, FLAG_FUSE16 = 32, 64, 128
@@ -29,7 +30,9 @@ EXPORTED = [
     "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_step",
     "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
     "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
-    "fractal_compact_step",
+    "fractal_compact_step", "fractal_nbb_builtin", "fractal_nbb_lambda_map",
+    "fractal_nbb_single_write", "fractal_nbb_reduce_workspace", "fractal_nbb_reduce",
+    "fractal_nbb_ca_step",
     "fractal_now", "fractal_serve_create", "fractal_serve_submit",
     "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
 ]
@@ -47,6 +50,14 @@ class Tuning(ctypes.Structure):
 
     def as_tuple(self):
         return (self.r, self.threads, self.order, self.flags)
+
+
+class Nbb(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("s", ctypes.c_int),
+                ("tau_x", ctypes.c_uint8 * 32), ("tau_y", ctypes.c_uint8 * 32)]
+
+    def replicas(self):
+        return [(self.tau_x[i], self.tau_y[i]) for i in range(self.k)]
 
 
 class Instance(ctypes.Structure):
@@ -104,6 +115,12 @@ def load():
         "fractal_unpack": ([i, i, i, vp, vp, vp], i),
         "fractal_compact_seed_fill": ([i, i, i, u32, vp, vp], i),
         "fractal_compact_step": ([i, i, i, f, vp, vp, i, i, vp], i),
+        "fractal_nbb_builtin": ([i, ctypes.POINTER(Nbb)], i),
+        "fractal_nbb_lambda_map": ([ctypes.POINTER(Nbb), i, vp, vp], i),
+        "fractal_nbb_single_write": ([ctypes.POINTER(Nbb), i, i, i, u32, vp, vp], i),
+        "fractal_nbb_reduce_workspace": ([ctypes.POINTER(Nbb), i, i, ctypes.POINTER(ctypes.c_size_t)], i),
+        "fractal_nbb_reduce": ([ctypes.POINTER(Nbb), i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
+        "fractal_nbb_ca_step": ([ctypes.POINTER(Nbb), i, i, i, vp, vp, i, vp], i),
         "fractal_now": ([], ctypes.c_double),
         "fractal_serve_create": ([vp, ctypes.c_size_t, i, i, vp, ctypes.POINTER(vp)], i),
         "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
@@ -268,6 +285,48 @@ def compact_seed_fill(k, r, rule, stream_id, compact, stream=None):
 def compact_step(k, r, rule, alpha, buf0, buf1, steps, flags=0, stream=None):
     return _check(load().fractal_compact_step(k, r, rule, alpha, _ptr(buf0), _ptr(buf1), steps,
                                               flags, _stream(stream)))
+
+
+def nbb_builtin(which) -> Nbb:
+    """A built-in NBB table (FRACTAL_NBB_*)."""
+    f = Nbb()
+    _check(load().fractal_nbb_builtin(which, ctypes.byref(f)))
+    return f
+
+
+def nbb_make(k, s, replicas) -> Nbb:
+    """An NBB table from a list of (tau_x, tau_y) replica offsets."""
+    f = Nbb()
+    f.k, f.s = k, s
+    for i, (x, y) in enumerate(replicas):
+        f.tau_x[i], f.tau_y[i] = x, y
+    return f
+
+
+def nbb_lambda_map(f, rb, out, stream=None):
+    return _check(load().fractal_nbb_lambda_map(ctypes.byref(f), rb, _ptr(out), _stream(stream)))
+
+
+def nbb_single_write(f, map_, level, r, value, buf, stream=None):
+    return _check(load().fractal_nbb_single_write(ctypes.byref(f), map_, level, r,
+                                                  int(value) & 0xFF, _ptr(buf), _stream(stream)))
+
+
+def nbb_reduce_workspace(f, level, r) -> int:
+    b = ctypes.c_size_t()
+    _check(load().fractal_nbb_reduce_workspace(ctypes.byref(f), level, r, ctypes.byref(b)))
+    return b.value
+
+
+def nbb_reduce(f, map_, level, r, buf, work, out, stream=None):
+    nbytes = work.numel() * work.element_size() if hasattr(work, "numel") else 1 << 62
+    return _check(load().fractal_nbb_reduce(ctypes.byref(f), map_, level, r, _ptr(buf),
+                                            _ptr(work), nbytes, _ptr(out), _stream(stream)))
+
+
+def nbb_ca_step(f, map_, level, r, buf0, buf1, steps, stream=None):
+    return _check(load().fractal_nbb_ca_step(ctypes.byref(f), map_, level, r, _ptr(buf0),
+                                             _ptr(buf1), steps, _stream(stream)))
 
 
 def now() -> float:

@@ -29,7 +29,8 @@ HIP_FLAGS = [
 SOURCES = ["api.cpp", "step_kernels.hip", "step_lambda.hip", "step_bb.hip", "step_mfma.hip",
            "step_march.hip",
            "seed.hip", "batch.hip", "batch_ca.hip", "batch_heat.hip", "batch_march.hip",
-           "sw_rd.hip", "compact.hip", "compact_ca.hip", "compact_heat.hip", "serve.cpp"]
+           "sw_rd.hip", "compact.hip", "compact_ca.hip", "compact_heat.hip", "nbb.hip",
+           "serve.cpp"]
 
 
 def _compile(src: str) -> str:

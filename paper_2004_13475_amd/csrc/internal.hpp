@@ -176,6 +176,12 @@ class BatchPlan {
 // per launch: counts[j] launches of Tmax >> j steps.
 void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem]);
 
+// Deterministic sum of n0 8-byte slots (uint64, or float64 if f64) at the
+// start of `work` into *d_out by a fixed 4096-ary tree; `work` must hold
+// reduce_tree_words(n0) words.
+uint64_t reduce_tree_words(uint64_t n0);
+int launch_reduce_tree(uint64_t *work, uint64_t n0, void *d_out, bool f64, hipStream_t s);
+
 // Batched march kernel for (rule, r, T steps, non-temporal stores).
 typedef void (*BatchMarchFn)(const BatchEntry *, int, uint64_t, int, int);
 BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt);

@@ -301,16 +301,45 @@ static int launch_swrd(SwRdFn fn, int rule, int r, const SwRdArgs &a, hipStream_
                      "SW/RD kernel launch");
 }
 
-// Sizes of the summation tree's levels: n_0 = 3^(k-r) slots, then
-// ceil(n_i / 4096) until one value remains (that one is the result).
-static std::vector<uint64_t> tree_levels(int k, int r)
+// Sizes of the summation tree's levels: n_0 slots, then ceil(n_i / 4096)
+// until one value remains (that one is the result).
+static std::vector<uint64_t> tree_levels(uint64_t n0)
 {
-    std::vector<uint64_t> lv{pow3_u64(k - r)};
+    std::vector<uint64_t> lv{n0};
     while (lv.back() > 1)
         lv.push_back((lv.back() + 4095) / 4096);
     if (lv.size() == 1)
         lv.push_back(1); // one slot still takes one pass
     return lv;
+}
+
+uint64_t reduce_tree_words(uint64_t n0)
+{
+    const std::vector<uint64_t> lv = tree_levels(n0);
+    uint64_t words = 0;
+    for (size_t i = 0; i + 1 < lv.size(); ++i)
+        words += lv[i];
+    return words;
+}
+
+int launch_reduce_tree(uint64_t *work, uint64_t n0, void *d_out, bool f64, hipStream_t s)
+{
+    const std::vector<uint64_t> lv = tree_levels(n0);
+    uint64_t *in = work;
+    for (size_t i = 0; i + 1 < lv.size(); ++i) {
+        uint64_t *out = (i + 2 == lv.size()) ? static_cast<uint64_t *>(d_out) : in + lv[i];
+        if (f64)
+            hipLaunchKernelGGL(tree_kernel<true>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
+                               lv[i], out);
+        else
+            hipLaunchKernelGGL(tree_kernel<false>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
+                               lv[i], out);
+        int rc = hip_error(hipGetLastError(), "reduction tree launch");
+        if (rc)
+            return rc;
+        in = out;
+    }
+    return FRACTAL_OK;
 }
 
 } // namespace fractal
@@ -341,10 +370,7 @@ int fractal_reduce_workspace(int k, int r, size_t *bytes)
         return set_error(FRACTAL_E_INVAL, "null output");
     if (k < 0 || k > kMaxStepLevel || r < 0 || r > k || r > kMaxR || k - r > kMaxBlockLevel)
         return set_error(FRACTAL_E_INVAL, "bad level k=%d r=%d", k, r);
-    const std::vector<uint64_t> lv = tree_levels(k, r);
-    uint64_t words = 0;
-    for (size_t i = 0; i + 1 < lv.size(); ++i)
-        words += lv[i];
+    const uint64_t words = reduce_tree_words(pow3_u64(k - r));
     *bytes = (size_t)(8 * words);
     return FRACTAL_OK;
 }
@@ -375,20 +401,8 @@ int fractal_reduce(int map, int k, int r, int rule, const void *d_buf, void *d_w
     a.slots = w;
     if ((rc = launch_swrd(swrd_pick<OP_RD>(map, rule, r), rule, r, a, s)))
         return rc;
-    const std::vector<uint64_t> lv = tree_levels(k, r);
-    uint64_t *in = w;
-    for (size_t i = 0; i + 1 < lv.size(); ++i) {
-        uint64_t *out = (i + 2 == lv.size()) ? static_cast<uint64_t *>(d_out) : in + lv[i];
-        if (rule == FRACTAL_RULE_HEAT)
-            hipLaunchKernelGGL(tree_kernel<true>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
-                               lv[i], out);
-        else
-            hipLaunchKernelGGL(tree_kernel<false>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
-                               lv[i], out);
-        if ((rc = hip_error(hipGetLastError(), "reduction tree launch")))
-            return rc;
-        in = out;
-    }
+    if ((rc = launch_reduce_tree(w, pow3_u64(k - r), d_out, rule == FRACTAL_RULE_HEAT, s)))
+        return rc;
     return FRACTAL_OK;
 }
 
