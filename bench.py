@@ -18,6 +18,7 @@ Also on the same JSON line:
   serve         (with --serve SECONDS) Poisson request stream, p50/p99
   sw_rd         tests SW (single write) and RD (reduction), lambda vs BB
   compact       compact storage through lambda^-1 at levels 16, 18, 20
+  nbb           carpet and Vicsek fractals: SW, RD, CA, lambda vs BB
   cpu_baseline  the CPU oracle on a bounded sample of the default workload
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
@@ -301,6 +302,60 @@ def compact_leg(F, torch, steps=64):
             del c0, c1
             torch.cuda.empty_cache()
         out[RULE_NAME[rule]] = row
+    return out
+
+
+def nbb_leg(F, torch, reps=5):
+    """The general NBB family: Sierpinski carpet (8, 3) at level 9 and Vicsek
+    (5, 3) at level 9 (19683 x 19683), tests SW, RD and CA (one step) through
+    lambda and the bounding box at tile sides 3..81; seconds per call and
+    lambda's speedup at each map's best tile side."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, which in (("carpet", F.NBB_CARPET), ("vicsek", F.NBB_VICSEK)):
+        f = F.nbb_builtin(which)
+        level = 9
+        n = f.s ** level
+        buf = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+        b1 = torch.zeros_like(buf)
+        F.nbb_single_write(f, F.MAP_LAMBDA, level, 2, 1, buf)
+        res = {"sw": {}, "rd": {}, "ca": {}}
+        for r in range(1, 5):
+            work = torch.empty(max(8, F.nbb_reduce_workspace(f, level, r)), dtype=torch.uint8,
+                               device="cuda")
+            val = torch.zeros(1, dtype=torch.int64, device="cuda")
+            for map_ in (F.MAP_LAMBDA, F.MAP_BB):
+                for op in ("sw", "rd", "ca"):
+                    def call():
+                        if op == "sw":
+                            F.nbb_single_write(f, map_, level, r, 1, buf)
+                        elif op == "rd":
+                            F.nbb_reduce(f, map_, level, r, buf, work, val)
+                        else:
+                            F.nbb_ca_step(f, map_, level, r, buf, b1, 1)
+                    call()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        call()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    res[op][(r, map_)] = e0.elapsed_time(e1) * 1e-3 / reps
+            del work, val
+        row = {"k": f.k, "s": f.s, "level": level, "members": f.k ** level}
+        for op, d in res.items():
+            lam = {r: t for (r, m), t in d.items() if m == F.MAP_LAMBDA}
+            bb = {r: t for (r, m), t in d.items() if m == F.MAP_BB}
+            rl, rbb = min(lam, key=lam.get), min(bb, key=bb.get)
+            row[op] = {"lambda_tile": f.s ** rl, "lambda_us": lam[rl] * 1e6,
+                       "bb_tile": f.s ** rbb, "bb_us": bb[rbb] * 1e6,
+                       "speedup_best": bb[rbb] / lam[rl],
+                       "speedup_by_tile": {str(f.s ** r): bb[r] / lam[r] for r in lam}}
+        out[name] = row
+        del buf, b1
+        torch.cuda.empty_cache()
     return out
 
 
@@ -593,6 +648,7 @@ def main() -> int:
     sweep = sweep_k_leg(F, torch) if args.sweep_k else None
     swrd = None if args.no_bb else {f"k{kk}": sw_rd_leg(F, torch, kk) for kk in sorted({k, 16})}
     compact = None if args.no_k16 else compact_leg(F, torch)
+    nbb = None if args.no_bb else nbb_leg(F, torch)
     ceiling = None if args.no_bb else copy_ceiling(torch)
 
     cpu = None
@@ -629,7 +685,7 @@ def main() -> int:
                                     "roofline": rfs[r]}
                      for r in (0, 1)},
         "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
-        "sw_rd": swrd, "compact": compact,
+        "sw_rd": swrd, "compact": compact, "nbb": nbb,
         "lambda_vs_bb_by_k": sweep,
         "device_copy_GBs": ceiling,
         "cpu_baseline": cpu,
