@@ -156,8 +156,11 @@ def roofline(rule, cells, sec_per_launch, tuning, traffic=None, kernel=""):
     spl = steps_per_launch(tuning)
     alg = BYTES_PER_CELL[rule] * cells
     achieved = alg / sec_per_launch / 1e9
+    rate = None if traffic is None else traffic / sec_per_launch / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBs": rate, "traffic_frac": None if rate is None else rate / HBM_PEAK_GBS,
+            "kernel": kernel,
             "steps_per_launch": spl, "alg_bytes_per_launch": alg,
             "avg_launch_us": sec_per_launch * 1e6,
             "per_step_equivalent_GBs": alg * spl / sec_per_launch / 1e9}
@@ -511,6 +514,11 @@ def batch_leg(F, torch, count=256, steps=500, seed=2004):
 
 
 def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
+    """Continuous batching: `seconds` of open-loop Poisson arrivals at `rate`
+    req/s (levels 9..15, steps 10..1000, rule 50/50) through the server --
+    latency = done minus scheduled arrival, p50/p99 --; the same requests
+    submitted at once (saturated server: cells/s over the drain time); and
+    the same requests solved one at a time with plain lambda_step calls."""
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(seed))
     nreq = int(rate * seconds)
@@ -523,30 +531,38 @@ def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
     arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     cells = int(sum(3 ** int(k) * int(s) for k, s in zip(ks, steps)))
     alpha = float(np.float32(ALPHA))
-    tickets = []
-    with F.Server(arena, nbytes, max_slots=256, steps_per_iter=8) as srv:
-        t0 = F.now()
-        for i in range(nreq):
-            target = t0 + float(arrivals[i])
-            while F.now() < target:
-                time.sleep(min(0.0005, max(0.0, target - F.now())))
-            tickets.append(srv.submit(int(ks[i]), int(rules[i]), int(steps[i]), alpha,
-                                      seed=10000 + i, t_arrival=target))
-        res = {}
-        while len(res) < nreq:
-            for t in tickets:
-                if t not in res:
-                    r = srv.poll(t)
-                    if r is not None:
-                        res[t] = r
-            time.sleep(0.002)
-        t_end = F.now()
-    lat = np.array([res[t][3] - res[t][1] for t in tickets])
-    ok = all(res[t][0] == 0 for t in tickets)
+
+    def run(paced):
+        tickets = []
+        with F.Server(arena, nbytes, max_slots=256, steps_per_iter=8) as srv:
+            t0 = F.now()
+            for i in range(nreq):
+                target = t0 + (float(arrivals[i]) if paced else 0.0)
+                while paced and F.now() < target:
+                    time.sleep(min(0.0005, max(0.0, target - F.now())))
+                tickets.append(srv.submit(int(ks[i]), int(rules[i]), int(steps[i]), alpha,
+                                          seed=10000 + i, t_arrival=target))
+            res = {}
+            while len(res) < nreq:
+                for t in tickets:
+                    if t not in res:
+                        r = srv.poll(t)
+                        if r is not None:
+                            res[t] = r
+                time.sleep(0.002)
+            t_end = F.now()
+        lat = np.array([res[t][3] - res[t][1] for t in tickets])
+        sums = [res[t][4] for t in tickets]
+        return t_end - t0, lat, all(res[t][0] == 0 for t in tickets), sums
+
+    drain, lat, ok, sums_paced = run(True)
     out = {"requests": nreq, "rate": rate, "arrival_s": float(arrivals[-1]),
-           "drain_s": t_end - t0, "cell_updates": cells,
-           "cells_per_s": cells / (t_end - t0), "p50_s": float(np.percentile(lat, 50)),
+           "drain_s": drain, "cell_updates": cells,
+           "cells_per_s": cells / drain, "p50_s": float(np.percentile(lat, 50)),
            "p99_s": float(np.percentile(lat, 99)), "all_ok": ok}
+    burst, _, ok_b, sums_burst = run(False)
+    out.update({"saturated_drain_s": burst, "saturated_cells_per_s": cells / burst,
+                "saturated_all_ok": ok_b, "same_results_paced_and_saturated": sums_paced == sums_burst})
     # the same trace solved one request at a time with plain launches
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -566,7 +582,8 @@ def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
     torch.cuda.synchronize()
     seq = e0.elapsed_time(e1) * 1e-3
     out.update({"sequential_s": seq, "sequential_wall_s": time.perf_counter() - t1,
-                "sequential_cells_per_s": cells / seq})
+                "sequential_cells_per_s": cells / seq,
+                "saturated_vs_sequential": seq / burst})
     del arena
     torch.cuda.empty_cache()
     return out
@@ -582,7 +599,7 @@ def main() -> int:
     ap.add_argument("--no-bb", action="store_true", help="skip the bounding-box leg")
     ap.add_argument("--no-k16", action="store_true", help="skip the level-16 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-gasket batch leg")
-    ap.add_argument("--serve", type=float, default=0.0,
+    ap.add_argument("--serve", type=float, default=20.0,
                     help="seconds of Poisson arrivals for the serving leg (0 = skip)")
     ap.add_argument("--sweep-k", action="store_true",
                     help="add lambda vs bounding box for levels 8..16 (about a minute)")
