@@ -35,7 +35,7 @@ struct CompactAddr {
     }
     __device__ __forceinline__ bool has(int y) const
     {
-        return y >= 0 && y < n && col(y) != nullptr;
+        return (uint32_t)y < (uint32_t)n && col(y) != nullptr;
     }
     __device__ __forceinline__ const uint8_t *ld(int, int y) const
     {

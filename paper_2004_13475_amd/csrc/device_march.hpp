@@ -267,7 +267,7 @@ struct EmbeddedAddr {
     int64_t off0;  // byte offset of the chunk in walk row 0
     int64_t pitch; // bytes per array row
     int n;
-    __device__ __forceinline__ bool has(int y) const { return y >= 0 && y < n; }
+    __device__ __forceinline__ bool has(int y) const { return (uint32_t)y < (uint32_t)n; }
     __device__ __forceinline__ const uint8_t *ld(int i, int) const
     {
         return src + off0 + (int64_t)i * pitch;
@@ -306,12 +306,18 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
         return v;
     };
 
-    uint32_t p2[T][W], p1[T][W]; // per level: rows yy-1 and yy of its newest yy+1
+    // Per input level, the rows before its newest: with a pass of a whole
+    // number of 3 rows, three slots indexed by row mod 3 (no moves at the
+    // loop's back edge); otherwise two rows shifted each row.
+    constexpr bool RING3 = (U % 3) == 0;
+    uint32_t win[T][RING3 ? 3 : 2][W];
 #pragma unroll
     for (int l = 0; l < T; ++l)
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-            p2[l][w] = p1[l][w] = 0u;
+        for (int q = 0; q < (RING3 ? 3 : 2); ++q)
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                win[l][q][w] = 0u;
     u32x4 ring[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
@@ -327,15 +333,26 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
                 constexpr int l = decltype(lc)::value;
                 constexpr int yq = (((d - T - l) % Q) + Q) % Q; // (row of level l) mod Q
                 const int yy = ybase - T + i - l;
-                const bool ok = col_ok && yy >= 0 && yy < n && (((uint32_t)xc & (uint32_t)yy) &
-                                                                ~(uint32_t)(Q - 1)) == 0u;
+                const bool ok = col_ok && (uint32_t)yy < (uint32_t)n &&
+                                (((uint32_t)xc & (uint32_t)yy) & ~(uint32_t)(Q - 1)) == 0u;
                 uint32_t out[W];
-                RU::template level<yq>(p2[l - 1], p1[l - 1], cur, ok, alpha, c1, out);
+                if constexpr (RING3) {
+                    // rows i-2, i-1 of level l-1 in slots (i-2) mod 3, (i-1) mod 3
+                    RU::template level<yq>(win[l - 1][(d + 1) % 3], win[l - 1][(d + 2) % 3], cur,
+                                           ok, alpha, c1, out);
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    p2[l - 1][w] = p1[l - 1][w];
-                    p1[l - 1][w] = cur[w];
-                    cur[w] = out[w];
+                    for (int w = 0; w < W; ++w) {
+                        win[l - 1][d % 3][w] = cur[w];
+                        cur[w] = out[w];
+                    }
+                } else {
+                    RU::template level<yq>(win[l - 1][0], win[l - 1][1], cur, ok, alpha, c1, out);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        win[l - 1][0][w] = win[l - 1][1][w];
+                        win[l - 1][1][w] = cur[w];
+                        cur[w] = out[w];
+                    }
                 }
             });
             // cur: level T at band row j
