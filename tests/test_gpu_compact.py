@@ -111,13 +111,14 @@ def test_compact_step_equals_array_step(rule):
                 assert_match(k, rule, emb, ref, f"compact k={k} r={r}")
 
 
-@pytest.mark.parametrize("rule", RULES)
-def test_compact_level18_sampled(rule):
+@pytest.mark.parametrize("rule,k", [(fi.RULE_CA, 18), (fi.RULE_HEAT, 18), (fi.RULE_CA, 20)])
+def test_compact_level18_sampled(rule, k):
     """Level 18 (387,420,489 cells; the n x n array would take 69 GB per
-    float32 buffer): 64 compact steps from the compact seeded fill, sampled
-    in light-cone windows against the oracle."""
+    float32 buffer) and, for the automaton, level 20 (3.5e9 cells, 19.6 GB
+    per compact state, byte offsets past 2^34): 64 compact steps from the
+    compact seeded fill, sampled in light-cone windows against the oracle."""
     torch = torch_dev()
-    k, steps = 18, 64
+    steps = 64
     r = 6 if rule == fi.RULE_CA else 5
     n = 1 << k
     c0, c1 = _cbuf(k, r, rule), _cbuf(k, r, rule)
@@ -125,7 +126,8 @@ def test_compact_level18_sampled(rule):
     F.compact_step(k, r, rule, ALPHA, c0, c1, steps)
     _sync()
     flat = c0  # steps even: result in buffer 0
-    for (cx, cy) in [(0, 0), (n - 48, 0), (0, n - 48), (150000, 40000), (65536, 131072)]:
+    for (cx, cy) in [(0, 0), (n - 48, 0), (0, n - 48), (150000, 40000), (65536, 131072),
+                     (n // 2 + 4096, n // 4 + 12)]:
         x0, y0, w, h = window_plan(k, steps, 48, 48, cx, cy)
         win = fi.window_values(k, rule, 7, x0, y0, w, h)
         ref = oracle_steps(k, rule, win if rule == 0 else win.astype(np.float64), steps, x0, y0)
@@ -138,7 +140,7 @@ def test_compact_level18_sampled(rule):
         got = np.zeros(ref.shape, dtype=ref.dtype if rule == 0 else np.float32)
         idx = torch.from_numpy(oracle.compact_index(k, r, xs[live], ys[live])).to("cuda")
         got[live] = flat[idx].cpu().numpy()
-        assert_match(k, rule, got, ref, f"compact k18 window ({cx},{cy})")
+        assert_match(k, rule, got, ref, f"compact k{k} window ({cx},{cy})")
     del c0, c1
     torch.cuda.empty_cache()
 
