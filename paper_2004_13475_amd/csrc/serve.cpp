@@ -2,7 +2,10 @@
 // resident in a caller-provided device arena.
 //
 // A scheduler thread admits queued requests first come first served when a
-// slot and arena space are free, initialises their state on the device,
+// slot and arena space are free, initialises their state on the device (on
+// a stream of its own, so that the memory-bound clear and seed of new
+// requests overlap the compute-bound steps of the running ones; the step
+// stream waits for it only before the iteration that first uses them),
 // and then repeatedly enqueues one iteration: steps_per_iter launches of the
 // batched step kernel over every active slot (slots with fewer remaining
 // steps drop out of the later launches of the iteration).  Requests that
@@ -108,6 +111,11 @@ class Server {
         if ((rc = hip_error(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking),
                             "copy stream")))
             return rc;
+        if ((rc = hip_error(hipStreamCreateWithFlags(&init_stream_, hipStreamNonBlocking),
+                            "init stream")))
+            return rc;
+        if ((rc = hip_error(hipEventCreateWithFlags(&init_ev_, hipEventDisableTiming), "event")))
+            return rc;
         worker_ = std::thread([this] { run(); });
         retirer_ = std::thread([this] { retire_loop(); });
         return FRACTAL_OK;
@@ -125,6 +133,10 @@ class Server {
             (void)hipHostFree(host_sums_);
         if (copy_stream_)
             (void)hipStreamDestroy(copy_stream_);
+        if (init_stream_)
+            (void)hipStreamDestroy(init_stream_);
+        if (init_ev_)
+            (void)hipEventDestroy(init_ev_);
     }
 
     int submit(const fractal_request *rq, uint64_t *ticket)
@@ -256,17 +268,26 @@ class Server {
                 Slot sl = slot_copy(adm[q].slot);
                 const fractal_request &rq = adm_rq[q];
                 const size_t sb = state_bytes(sl.k, sl.rule);
-                int rc = hip_error(hipMemsetAsync(sl.buf1, 0, sb, stream_), "state clear");
+                int rc = hip_error(hipMemsetAsync(sl.buf1, 0, sb, init_stream_), "state clear");
                 if (!rc) {
                     if (rq.h_init)
                         rc = hip_error(hipMemcpyAsync(sl.buf0, rq.h_init, sb, hipMemcpyHostToDevice,
-                                                      stream_),
+                                                      init_stream_),
                                        "state upload");
                     else
-                        rc = launch_seed_fill(sl.k, sl.rule, rq.seed, sl.buf0, stream_);
+                        rc = launch_seed_fill(sl.k, sl.rule, rq.seed, sl.buf0, init_stream_);
                 }
                 if (rc)
                     abort_slot(adm[q].slot, rc);
+            }
+            if (!adm.empty()) {
+                // the next launches on the step stream use the new states
+                int rc = hip_error(hipEventRecord(init_ev_, init_stream_), "event record");
+                if (!rc)
+                    rc = hip_error(hipStreamWaitEvent(stream_, init_ev_, 0), "stream wait");
+                if (rc)
+                    for (const Admitted &a : adm)
+                        abort_slot(a.slot, rc);
             }
             {
                 std::lock_guard<std::mutex> lk(mu_);
@@ -371,9 +392,12 @@ class Server {
     // Give up on a slot after a device error (its ticket reports the error).
     void abort_slot(int i, int code)
     {
+        (void)hipStreamSynchronize(init_stream_);
         (void)hipStreamSynchronize(stream_);
         std::lock_guard<std::mutex> lk(mu_);
         Slot &s = slots_[i];
+        if (!s.busy)
+            return; // already given up
         fail_ticket(s.ticket, code);
         alloc_.release(s.offset);
         s = Slot();
@@ -431,7 +455,8 @@ class Server {
     uint8_t *arena_;
     size_t arena_bytes_;
     int max_slots_, per_iter_;
-    hipStream_t stream_, copy_stream_ = nullptr;
+    hipStream_t stream_, copy_stream_ = nullptr, init_stream_ = nullptr;
+    hipEvent_t init_ev_ = nullptr; // the newest admissions' initialisation
     int device_ = 0;
     size_t table_off_[2] = {0, 0}, sums_off_ = 0, state_base_ = 0;
     BatchEntry *host_table_[2] = {nullptr, nullptr};
