@@ -51,7 +51,8 @@ WORKLOADS = {"k14": 14, "k16": 16}
 AUTOTUNE = False  # set by --autotune
 RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
-              "device_march.hpp", "step_march.hip"]
+              "device_march.hpp", "march_pick.hpp", "step_march.hip", "step_march_ca.hip",
+              "step_march_heat.hip"]
 
 
 def kernel_hash() -> str:

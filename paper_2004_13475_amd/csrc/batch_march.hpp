@@ -1,6 +1,9 @@
-// batch_march.hip -- the register-march engine over a batch work list: each
-// lane group finds its instance by the tile prefix, then walks that
-// instance's tile as the single-gasket march kernel does.
+// batch_march.hpp -- the register-march engine over a batch work list:
+// each lane group finds its instance by the tile prefix, then walks that
+// instance's tile as the single-gasket march kernel does.  Instantiated per
+// rule in batch_march_ca.hip and batch_march_heat.hip.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include "batch_kernels.hpp"
@@ -29,7 +32,9 @@ void batch_march_kernel(const BatchEntry *__restrict__ table, int count, uint64_
     const bool active = ln.grp < (uint32_t)M::P && w < total;
     if (__builtin_amdgcn_ballot_w64(active) == 0u)
         return;
-    const uint8_t *src = nullptr;
+    // Idle lanes still issue the walk's loads, from a readable chunk: the
+    // first instance's state (the list is not empty, since a lane is active).
+    const uint8_t *src = table[0].buf0;
     uint8_t *dst = nullptr;
     int k = R;
     float alpha = 0.0f;
@@ -81,11 +86,10 @@ static BatchMarchFn bm_pick(int r, int T)
     }
 }
 
-BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt)
+template <int RULE>
+static BatchMarchFn bm_pick_rule(int r, int T, bool nt)
 {
-    if (rule == FRACTAL_RULE_CA)
-        return nt ? bm_pick<RULE_CA, TILE_NT_STORE>(r, T) : bm_pick<RULE_CA, 0>(r, T);
-    return nt ? bm_pick<RULE_HEAT, TILE_NT_STORE>(r, T) : bm_pick<RULE_HEAT, 0>(r, T);
+    return nt ? bm_pick<RULE, TILE_NT_STORE>(r, T) : bm_pick<RULE, 0>(r, T);
 }
 
 } // namespace fractal

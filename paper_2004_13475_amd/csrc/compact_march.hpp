@@ -25,6 +25,7 @@ struct CompactAddr {
     static constexpr int RHO = 1 << R;
     static constexpr int64_t ROWB = (int64_t)RHO * S; // bytes per tile row
     const uint8_t *up, *mid, *dn;
+    const uint8_t *base; // the state's first tile: always readable
     uint8_t *dst;
     int y0; // first array row of the lane's tile row
     int n;
@@ -41,6 +42,7 @@ struct CompactAddr {
     {
         return col(y) + (int64_t)(y & (RHO - 1)) * ROWB;
     }
+    __device__ __forceinline__ const uint8_t *any() const { return base; }
     __device__ __forceinline__ uint8_t *st(int, int y) const
     {
         return dst + (int64_t)(y & (RHO - 1)) * ROWB;
@@ -102,6 +104,7 @@ void compact_march_kernel(CompactArgs a)
     A.up = tile_col(-1);
     A.mid = tile_col(0);
     A.dn = tile_col(1);
+    A.base = a.src;
     A.dst = a.dst + (int64_t)tile * TB + coff; // used by the interior lanes only
     A.y0 = (int)(t.y << R);
     A.n = n;

@@ -55,6 +55,10 @@ constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
 constexpr int march_depth(int rule, int T) { return (rule == RULE_CA && T <= 4) ? 8 : 4; }
 // Band heights (and so band origins) are multiples of this row period.
 constexpr int march_row_period(int rule) { return rule == RULE_CA ? 16 : 4; }
+// Whether the walk's first passes leave out the levels not yet needed (about
+// T(T+1) of the T(H+2T) level rows of a band of H rows) at the price of
+// compiling those passes separately.
+constexpr bool march_peel(int rule, int T) { return true; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -183,29 +187,63 @@ struct MarchRule<RULE_HEAT> {
     {
         return u32x4{s[0], s[1], s[2], s[3]};
     }
+    // a + b over the terms that are present (at least one is)
+    template <bool A, bool B>
+    static __device__ __forceinline__ float sum2(float a, float b)
+    {
+#pragma clang fp contract(off)
+        if constexpr (A && B)
+            return a + b;
+        else if constexpr (A)
+            return a;
+        else
+            return b;
+    }
     template <int YQ>
     static __device__ __forceinline__ void level(const uint32_t (&up)[W], const uint32_t (&md)[W],
                                                  const uint32_t (&dn)[W], bool ok, float alpha,
                                                  float c1, uint32_t (&out)[W])
     {
-        // cell w of the chunk is a member iff (w & YQ) == 0 (given ok);
-        // non-members are 0 without arithmetic
-        const float ml = __uint_as_float(from_left(md[0 + 3]));
-        float mr = 0.0f;
-        if constexpr ((3 & YQ) == 0)
+        // Cell w of a chunk in a row of phase p is a member iff (w & p) == 0
+        // (given that row's ok).  Neighbours that are off the gasket by phase
+        // alone hold 0 and are left out of the sum ((N + S) + (W + E) as in
+        // heat_cell; leaving out a +0 term changes at most the sign of a
+        // zero).  Where ok is false every cell of the chunk, and of the
+        // previous level at the same place, is 0, so a coefficient of 0
+        // gives 0 without a select per cell.
+        constexpr int PU = (YQ + Q - 1) % Q; // phase of the row above
+        constexpr int PD = (YQ + 1) % Q;     // phase of the row below
+        const float a = ok ? alpha : 0.0f;
+        float ml = 0.0f, mr = 0.0f;
+        if constexpr ((3 & YQ) == 0) // cell 3 of the left chunk is a member
+            ml = __uint_as_float(from_left(md[3]));
+        if constexpr ((3 & YQ) == 0) // cell 3 is a member and needs cell 0 on the right
             mr = __uint_as_float(from_right(md[0]));
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            if ((w & YQ) != 0) {
+        static_for<0, W>([&](auto wc) {
+            constexpr int w = decltype(wc)::value;
+            if constexpr ((w & YQ) != 0) {
                 out[w] = 0u;
-                continue;
+            } else {
+                constexpr bool HU = (w & PU) == 0, HD = (w & PD) == 0;
+                constexpr int WL = (w + 3) & 3, WR = (w + 1) & 3;
+                constexpr bool HW = (WL & YQ) == 0, HE = (WR & YQ) == 0;
+                static_assert(HU || HD || HW || HE, "a member has a member neighbour");
+                const float wv = (w == 0) ? ml : __uint_as_float(md[w == 0 ? 0 : w - 1]);
+                const float ev = (w == 3) ? mr : __uint_as_float(md[w == 3 ? 0 : w + 1]);
+                float sum;
+                {
+#pragma clang fp contract(off)
+                    if constexpr ((HU || HD) && (HW || HE))
+                        sum = sum2<HU, HD>(__uint_as_float(up[w]), __uint_as_float(dn[w])) +
+                              sum2<HW, HE>(wv, ev);
+                    else if constexpr (HU || HD)
+                        sum = sum2<HU, HD>(__uint_as_float(up[w]), __uint_as_float(dn[w]));
+                    else
+                        sum = sum2<HW, HE>(wv, ev);
+                    out[w] = __float_as_uint(__builtin_fmaf(a, sum, c1 * __uint_as_float(md[w])));
+                }
             }
-            const float wv = (w == 0) ? ml : __uint_as_float(md[w - 1]);
-            const float ev = (w == 3) ? mr : __uint_as_float(md[w + 1]);
-            const float v = heat_cell(__uint_as_float(md[w]), __uint_as_float(up[w]),
-                                      __uint_as_float(dn[w]), wv, ev, alpha, c1);
-            out[w] = ok ? __float_as_uint(v) : 0u;
-        }
+        });
     }
 };
 
@@ -254,10 +292,6 @@ struct MarchLane {
     }
 };
 
-// The walk of one group over band `band` (of 2^band_log) of tile t of a
-// level-k state: src -> dst, T steps.  Every argument may differ between
-// groups; all 64 lanes must call it (the level updates read neighbouring
-// lanes), inactive groups with active = false.
 // Where a lane's chunk column of walk row i (array row y) lives, for a
 // state stored as the n x n array: `has` tells whether row y has storage,
 // `ld` / `st` give the chunk's address in the input / output state.
@@ -268,6 +302,7 @@ struct EmbeddedAddr {
     int64_t pitch; // bytes per array row
     int n;
     __device__ __forceinline__ bool has(int y) const { return (uint32_t)y < (uint32_t)n; }
+    __device__ __forceinline__ const uint8_t *any() const { return src; }
     __device__ __forceinline__ const uint8_t *ld(int i, int) const
     {
         return src + off0 + (int64_t)i * pitch;
@@ -282,7 +317,8 @@ struct EmbeddedAddr {
 // chunk column starting at array column xc: src -> dst through `A`, T steps.
 // Every argument may differ between groups; all 64 lanes must call it (the
 // level updates read neighbouring lanes), inactive groups with col_ok false.
-template <int RULE, int R, int T, int HL, int FL, int D, class Addr>
+template <int RULE, int R, int T, int HL, int FL, int D, bool PEEL = march_peel(RULE, T),
+          class Addr>
 __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha, int xc,
                                               int ybase, int H, bool col_ok, bool interior)
 {
@@ -297,13 +333,23 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
     const int rows = H + 2 * T;
     const float c1 = 1.0f - 4.0f * alpha;
 
-    auto load_row = [&](int i) -> u32x4 {
+    // Rows are loaded D rows ahead into a ring.  Every lane loads (a chunk
+    // without storage or members reads the always-valid chunk A.any() and
+    // is taken as 0 when used): with no branch around the loads the wait
+    // for a row can count the loads still in flight.  `take` marks the four
+    // words as used at that point, so none of their registers is reused
+    // while the load may still write it.
+    bool keep[D];
+    auto load_row = [&](int i, bool &want) -> u32x4 {
         const int y = ybase - T + i;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (i < rows && col_ok && A.has(y) &&
-            ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u))
-            v = *reinterpret_cast<const u32x4 *>(A.ld(i, y));
-        return v;
+        want = i < rows && col_ok && A.has(y) &&
+               ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u);
+        return *reinterpret_cast<const u32x4 *>(want ? A.ld(i, y) : A.any());
+    };
+    auto take = [](u32x4 v, bool want) -> u32x4 {
+        uint32_t a = v[0], b = v[1], c = v[2], e = v[3];
+        asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(e));
+        return want ? u32x4{a, b, c, e} : u32x4{0u, 0u, 0u, 0u};
     };
 
     // Per input level, the rows before its newest: with a pass of a whole
@@ -321,58 +367,90 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
     u32x4 ring[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        ring[d] = load_row(d);
-    for (int i0 = 0; i0 < rows; i0 += U) {
+        ring[d] = load_row(d, keep[d]);
+    // One pass of U walk rows from walk row i0.  Level l is needed from the
+    // row T - l above the band down, which it reaches at walk row 2l; the
+    // first passes (F = i0, known at compile time) leave out the levels not
+    // yet needed and keep only their window filling from walk row 2l - 2
+    // on; later passes (F < 0) run every level.
+    auto pass = [&](int i0, auto fc) {
+        constexpr int F = decltype(fc)::value;
         static_for<0, U>([&](auto dc) {
             constexpr int d = decltype(dc)::value;
             const int i = i0 + d;
             uint32_t cur[W];
-            RU::load(ring[d % D], cur);
-            ring[d % D] = load_row(i + D);
+            RU::load(take(ring[d % D], keep[d % D]), cur);
+            ring[d % D] = load_row(i + D, keep[d % D]);
+            // keep the prefetch here: the scheduler would otherwise sink it
+            // next to its use D rows later under register pressure
+            __builtin_amdgcn_sched_barrier(0);
             static_for<1, T + 1>([&](auto lc) {
                 constexpr int l = decltype(lc)::value;
                 constexpr int yq = (((d - T - l) % Q) + Q) % Q; // (row of level l) mod Q
-                const int yy = ybase - T + i - l;
-                const bool ok = col_ok && (uint32_t)yy < (uint32_t)n &&
-                                (((uint32_t)xc & (uint32_t)yy) & ~(uint32_t)(Q - 1)) == 0u;
-                uint32_t out[W];
-                if constexpr (RING3) {
-                    // rows i-2, i-1 of level l-1 in slots (i-2) mod 3, (i-1) mod 3
-                    RU::template level<yq>(win[l - 1][(d + 1) % 3], win[l - 1][(d + 2) % 3], cur,
-                                           ok, alpha, c1, out);
+                if constexpr (F < 0 || F + d >= 2 * l) {
+                    const int yy = ybase - T + i - l;
+                    const bool ok = col_ok && (uint32_t)yy < (uint32_t)n &&
+                                    (((uint32_t)xc & (uint32_t)yy) & ~(uint32_t)(Q - 1)) == 0u;
+                    uint32_t out[W];
+                    if constexpr (RING3) {
+                        // rows i-2, i-1 of level l-1 in slots (i-2) mod 3, (i-1) mod 3
+                        RU::template level<yq>(win[l - 1][(d + 1) % 3], win[l - 1][(d + 2) % 3],
+                                               cur, ok, alpha, c1, out);
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        win[l - 1][d % 3][w] = cur[w];
-                        cur[w] = out[w];
+                        for (int w = 0; w < W; ++w) {
+                            win[l - 1][d % 3][w] = cur[w];
+                            cur[w] = out[w];
+                        }
+                    } else {
+                        RU::template level<yq>(win[l - 1][0], win[l - 1][1], cur, ok, alpha, c1,
+                                               out);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            win[l - 1][0][w] = win[l - 1][1][w];
+                            win[l - 1][1][w] = cur[w];
+                            cur[w] = out[w];
+                        }
                     }
-                } else {
-                    RU::template level<yq>(win[l - 1][0], win[l - 1][1], cur, ok, alpha, c1, out);
+                } else if constexpr (F + d >= 2 * l - 2) {
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        win[l - 1][0][w] = win[l - 1][1][w];
-                        win[l - 1][1][w] = cur[w];
-                        cur[w] = out[w];
+                        if constexpr (RING3) {
+                            win[l - 1][d % 3][w] = cur[w];
+                        } else {
+                            win[l - 1][0][w] = win[l - 1][1][w];
+                            win[l - 1][1][w] = cur[w];
+                        }
                     }
                 }
             });
             // cur: level T at band row j
-            const int j = i - 2 * T;
-            const int y = ybase + j;
-            if (interior && col_ok && j >= 0 && j < H &&
-                ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u)) {
-                const u32x4 o = RU::store(cur);
-                u32x4 *dp = reinterpret_cast<u32x4 *>(A.st(j + T, y));
-                if constexpr (FL & TILE_NT_STORE)
-                    __builtin_nontemporal_store(o, dp);
-                else
-                    *dp = o;
+            if constexpr (F < 0 || F + d >= 2 * T) {
+                const int j = i - 2 * T;
+                const int y = ybase + j;
+                if (interior && col_ok && j >= 0 && j < H &&
+                    ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u)) {
+                    const u32x4 o = RU::store(cur);
+                    u32x4 *dp = reinterpret_cast<u32x4 *>(A.st(j + T, y));
+                    if constexpr (FL & TILE_NT_STORE)
+                        __builtin_nontemporal_store(o, dp);
+                    else
+                        *dp = o;
+                }
             }
         });
-    }
+    };
+    // the first passes start below rows (rows >= 2T + Q > (NP - 1) U);
+    // without PEEL every pass runs every level (smaller code)
+    constexpr int NP = PEEL ? (2 * T + U - 1) / U : 0;
+    static_for<0, NP>([&](auto pc) {
+        pass(decltype(pc)::value * U, std::integral_constant<int, decltype(pc)::value * U>{});
+    });
+    for (int i0 = NP * U; i0 < rows; i0 += U)
+        pass(i0, std::integral_constant<int, -1>{});
 }
 
 // march_walk_at over the n x n array: band `band` (of 2^band_log) of tile t.
-template <int RULE, int R, int T, int HL, int FL, int D>
+template <int RULE, int R, int T, int HL, int FL, int D, bool PEEL = march_peel(RULE, T)>
 __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int k, float alpha,
                                            TileXY t, int band, int band_log, bool active, int col)
 {
@@ -387,8 +465,9 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
     A.pitch = (int64_t)n * M::S;
     A.off0 = ((int64_t)ybase - T) * A.pitch + (int64_t)xc * M::S;
     A.n = n;
-    march_walk_at<RULE, R, T, HL, FL, D>(A, k, alpha, xc, ybase, H,
-                                         active && xc >= 0 && xc < n, col >= 0 && col < M::IL);
+    march_walk_at<RULE, R, T, HL, FL, D, PEEL>(A, k, alpha, xc, ybase, H,
+                                               active && xc >= 0 && xc < n,
+                                               col >= 0 && col < M::IL);
 }
 
 // One gasket: wavefront w of the grid takes (tile, band) items w*P .. w*P+P-1

@@ -184,7 +184,13 @@ int launch_reduce_tree(uint64_t *work, uint64_t n0, void *d_out, bool f64, hipSt
 
 // Batched march kernel for (rule, r, T steps, non-temporal stores).
 typedef void (*BatchMarchFn)(const BatchEntry *, int, uint64_t, int, int);
-BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt);
+BatchMarchFn pick_batch_march_ca(int r, int T, bool nt);
+BatchMarchFn pick_batch_march_heat(int r, int T, bool nt);
+inline BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt)
+{
+    return rule == FRACTAL_RULE_CA ? pick_batch_march_ca(r, T, nt)
+                                   : pick_batch_march_heat(r, T, nt);
+}
 
 // Batched step kernels of one rule for (r, threads, flags): one workgroup
 // per tile (tf) and persistent (pf); nullptr if not instantiated.

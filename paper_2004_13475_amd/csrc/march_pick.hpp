@@ -1,0 +1,59 @@
+// march_pick.hpp -- instantiation of the register-march step kernels for
+// one rule (each rule's kernels are compiled in a source of their own).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_march.hpp"
+#include "internal.hpp"
+
+namespace fractal {
+
+template <int MAP, int RULE, int R, int T, int FL>
+static MarchFn march_fn()
+{
+    constexpr int HL = march_hl(RULE, T);
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
+        return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;
+    else
+        return nullptr;
+}
+
+template <int MAP, int RULE, int FL>
+static MarchFn march_pick_rt(int r, int T)
+{
+    switch (r) {
+#define FRACTAL_MARCH_R(RR)                                                                        \
+    case RR:                                                                                       \
+        switch (T) {                                                                               \
+        case 1: return march_fn<MAP, RULE, RR, 1, FL>();                                           \
+        case 2: return march_fn<MAP, RULE, RR, 2, FL>();                                           \
+        case 4: return march_fn<MAP, RULE, RR, 4, FL>();                                           \
+        case 8: return march_fn<MAP, RULE, RR, 8, FL>();                                           \
+        case 16: return march_fn<MAP, RULE, RR, 16, FL>();                                         \
+        default: return nullptr;                                                                   \
+        }
+        FRACTAL_MARCH_R(2)
+        FRACTAL_MARCH_R(3)
+        FRACTAL_MARCH_R(4)
+        FRACTAL_MARCH_R(5)
+        FRACTAL_MARCH_R(6)
+        FRACTAL_MARCH_R(7)
+#undef FRACTAL_MARCH_R
+    default: return nullptr;
+    }
+}
+
+template <int RULE>
+static MarchFn march_pick_rule(int map, int r, int T, bool nt)
+{
+    if (map == MAP_LAMBDA)
+        return nt ? march_pick_rt<MAP_LAMBDA, RULE, TILE_NT_STORE>(r, T)
+                  : march_pick_rt<MAP_LAMBDA, RULE, 0>(r, T);
+    if (map == MAP_BB)
+        return nt ? march_pick_rt<MAP_BB, RULE, TILE_NT_STORE>(r, T)
+                  : march_pick_rt<MAP_BB, RULE, 0>(r, T);
+    return nullptr;
+}
+
+} // namespace fractal

@@ -1,5 +1,6 @@
-// step_march.hip -- instantiations and host launcher of the register-march
-// step kernels (lambda and bounding-box maps).
+// step_march.hip -- host launcher of the register-march step kernels
+// (lambda and bounding-box maps); the kernels are instantiated per rule in
+// step_march_ca.hip and step_march_heat.hip.
 #include <hip/hip_runtime.h>
 
 #include "device_march.hpp"
@@ -7,58 +8,13 @@
 
 namespace fractal {
 
-template <int MAP, int RULE, int R, int T, int FL>
-static MarchFn march_fn()
-{
-    constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
-        return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;
-    else
-        return nullptr;
-}
-
-template <int MAP, int RULE, int FL>
-static MarchFn march_pick_rt(int r, int T)
-{
-    switch (r) {
-#define FRACTAL_MARCH_R(RR)                                                                        \
-    case RR:                                                                                       \
-        switch (T) {                                                                               \
-        case 1: return march_fn<MAP, RULE, RR, 1, FL>();                                           \
-        case 2: return march_fn<MAP, RULE, RR, 2, FL>();                                           \
-        case 4: return march_fn<MAP, RULE, RR, 4, FL>();                                           \
-        case 8: return march_fn<MAP, RULE, RR, 8, FL>();                                           \
-        case 16: return march_fn<MAP, RULE, RR, 16, FL>();                                           \
-        default: return nullptr;                                                                   \
-        }
-        FRACTAL_MARCH_R(2)
-        FRACTAL_MARCH_R(3)
-        FRACTAL_MARCH_R(4)
-        FRACTAL_MARCH_R(5)
-        FRACTAL_MARCH_R(6)
-        FRACTAL_MARCH_R(7)
-#undef FRACTAL_MARCH_R
-    default: return nullptr;
-    }
-}
-
-template <int MAP>
-static MarchFn march_pick_map(int rule, int r, int T, bool nt)
-{
-    if (rule == FRACTAL_RULE_CA)
-        return nt ? march_pick_rt<MAP, RULE_CA, TILE_NT_STORE>(r, T)
-                  : march_pick_rt<MAP, RULE_CA, 0>(r, T);
-    return nt ? march_pick_rt<MAP, RULE_HEAT, TILE_NT_STORE>(r, T)
-              : march_pick_rt<MAP, RULE_HEAT, 0>(r, T);
-}
+MarchFn pick_march_ca(int map, int r, int T, bool nt);
+MarchFn pick_march_heat(int map, int r, int T, bool nt);
 
 MarchFn pick_march(int map, int rule, int r, int T, bool nt)
 {
-    if (map == MAP_LAMBDA)
-        return march_pick_map<MAP_LAMBDA>(rule, r, T, nt);
-    if (map == MAP_BB)
-        return march_pick_map<MAP_BB>(rule, r, T, nt);
-    return nullptr;
+    return rule == FRACTAL_RULE_CA ? pick_march_ca(map, r, T, nt)
+                                   : pick_march_heat(map, r, T, nt);
 }
 
 int march_tiles_per_wave(int rule, int r, int T)

@@ -1,0 +1,11 @@
+// step_march_ca.hip -- the register-march step kernels of the automaton.
+#include "march_pick.hpp"
+
+namespace fractal {
+
+MarchFn pick_march_ca(int map, int r, int T, bool nt)
+{
+    return march_pick_rule<RULE_CA>(map, r, T, nt);
+}
+
+} // namespace fractal

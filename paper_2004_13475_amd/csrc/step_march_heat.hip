@@ -1,0 +1,11 @@
+// step_march_heat.hip -- the register-march step kernels of the heat rule.
+#include "march_pick.hpp"
+
+namespace fractal {
+
+MarchFn pick_march_heat(int map, int r, int T, bool nt)
+{
+    return march_pick_rule<RULE_HEAT>(map, r, T, nt);
+}
+
+} // namespace fractal
