@@ -31,8 +31,13 @@ struct CompactAddr {
     int n;
     __device__ __forceinline__ const uint8_t *col(int y) const
     {
+        // one of three pointers by masks: a select between neighbouring
+        // fields may otherwise become an indexed load from a stack copy
         const int s = (y - y0) >> R; // -1, 0 or 1
-        return s < 0 ? up : (s == 0 ? mid : dn);
+        const uint64_t mu = 0u - (uint64_t)(s < 0), md = 0u - (uint64_t)(s > 0);
+        const uint64_t v = ((uint64_t)up & mu) | ((uint64_t)dn & md) |
+                           ((uint64_t)mid & ~(mu | md));
+        return reinterpret_cast<const uint8_t *>(v);
     }
     __device__ __forceinline__ bool has(int y) const
     {

@@ -344,7 +344,10 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
         const int y = ybase - T + i;
         want = i < rows && col_ok && A.has(y) &&
                ((((uint32_t)xc >> M::SLOG) & ((uint32_t)y >> M::SLOG)) == 0u);
-        return *reinterpret_cast<const u32x4 *>(want ? A.ld(i, y) : A.any());
+        // global memory: a load through a generic pointer would count on
+        // the LDS counter as well, whose waits cannot leave loads in flight
+        using gu32x4 = const __attribute__((address_space(1))) u32x4;
+        return *(gu32x4 *)(want ? A.ld(i, y) : A.any());
     };
     auto take = [](u32x4 v, bool want) -> u32x4 {
         uint32_t a = v[0], b = v[1], c = v[2], e = v[3];
