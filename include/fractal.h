@@ -100,6 +100,18 @@ extern "C" {
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
                                      contiguous ranges of the tile list, instead
                                      of one workgroup per tile */
+#define FRACTAL_FLAG_STACK2 256  /* lambda-map march launches of one gasket:
+                                    walk vertical stacks of up to 2 tiles
+                                    (the tiles of a column split into runs;
+                                    each class of equal runs is a smaller
+                                    gasket of stacks mapped by lambda, so the
+                                    2T halo rows are paid once per stack).
+                                    Tiles are then taken in curve order.  The
+                                    BB map, batches and compact states ignore
+                                    it.  Needs FRACTAL_FLAG_MARCH; STACK2 / 4
+                                    / 8 are exclusive */
+#define FRACTAL_FLAG_STACK4 512  /* as STACK2, stacks of up to 4 tiles */
+#define FRACTAL_FLAG_STACK8 1024 /* as STACK2, stacks of up to 8 tiles */
 
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */

@@ -20,6 +20,7 @@ NBB_GASKET, NBB_CARPET, NBB_VICSEK, NBB_XFRACTAL, NBB_HFRACTAL, NBB_CANTOR = ran
 ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
 FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2, FLAG_FUSE4 = 1, 2, 4, 8, 16
 FLAG_MARCH, FLAG_FUSE8, FLAG_FUSE16 = 32, 64, 128
+FLAG_STACK2, FLAG_STACK4, FLAG_STACK8 = 256, 512, 1024
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 

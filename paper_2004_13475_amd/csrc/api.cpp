@@ -131,6 +131,11 @@ static fractal_tuning builtin_default(int k, int rule)
         t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |
                   ((big && rule == FRACTAL_RULE_CA) ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8) |
                   (big ? FRACTAL_FLAG_NT_STORE : 0);
+    // level 14 automaton: 16 steps a launch on stacks of two 16 x 16 tiles
+    // (the halo rows of 16 steps are then paid once per two tiles)
+    if (k == 14 && rule == FRACTAL_RULE_CA && r == 4 && (t.flags & FRACTAL_FLAG_MARCH))
+        t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE16 |
+                  FRACTAL_FLAG_STACK2;
     return t;
 }
 
@@ -168,10 +173,16 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "unknown order %d", t->order);
     const int fuse = t->flags & kFuseFlags;
     const bool march = (t->flags & FRACTAL_FLAG_MARCH) != 0;
-    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags))
+    const int stack = t->flags & kStackFlags;
+    if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH |
+                     kFuseFlags | kStackFlags))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
     if (fuse & (fuse - 1))
         return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
+    if (stack & (stack - 1))
+        return set_error(FRACTAL_E_INVAL, "the STACK flags are exclusive");
+    if (stack && !march)
+        return set_error(FRACTAL_E_INVAL, "STACK flags need FRACTAL_FLAG_MARCH");
     if ((fuse & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)) && !march)
         return set_error(FRACTAL_E_INVAL, "FUSE8 and FUSE16 need FRACTAL_FLAG_MARCH");
     if ((fuse & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
@@ -356,16 +367,19 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                     cands.push_back(t);
                 }
         }
-        // register march: 1, 2, 4 or 8 steps per launch, with and without
-        // non-temporal stores
+        // register march: 1, 2, 4, 8 or 16 steps per launch, with and
+        // without non-temporal stores; the longer launches also on stacks
         if (row_bytes >= 16)
             for (int fuse : {0, (int)FRACTAL_FLAG_FUSE2, (int)FRACTAL_FLAG_FUSE4,
                              (int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16})
                 for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
-                    if (fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA)
-                        cands.push_back(fractal_tuning{
-                        r, 256, FRACTAL_ORDER_CURVE_XCD,
-                        FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse});
+                    for (int stack : {0, (int)FRACTAL_FLAG_STACK2, (int)FRACTAL_FLAG_STACK4})
+                        if ((fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA) &&
+                            (stack == 0 || fuse == FRACTAL_FLAG_FUSE8 ||
+                             fuse == FRACTAL_FLAG_FUSE16))
+                            cands.push_back(fractal_tuning{
+                                r, 256, FRACTAL_ORDER_CURVE_XCD,
+                                FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse | stack});
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)

@@ -452,16 +452,16 @@ __device__ __forceinline__ void march_walk_at(const Addr &A, int k, float alpha,
         pass(i0, std::integral_constant<int, -1>{});
 }
 
-// march_walk_at over the n x n array: band `band` (of 2^band_log) of tile t.
+// march_walk_at over the n x n array: rows ybase .. ybase+H-1 of the tile
+// column starting at array column x0.
 template <int RULE, int R, int T, int HL, int FL, int D, bool PEEL = march_peel(RULE, T)>
-__device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int k, float alpha,
-                                           TileXY t, int band, int band_log, bool active, int col)
+__device__ __forceinline__ void march_walk_rows(const uint8_t *src, uint8_t *dst, int k,
+                                                float alpha, int x0, int ybase, int H,
+                                                bool active, int col)
 {
     using M = MGeom<RULE, R, T, HL>;
     const int n = 1 << k;
-    const int H = M::RHO >> band_log; // band height, a multiple of the row period
-    const int xc = (int)(t.x << R) + col * M::CC;
-    const int ybase = (int)(t.y << R) + band * H; // first row of the band
+    const int xc = x0 + col * M::CC;
     EmbeddedAddr A;
     A.src = src;
     A.dst = dst;
@@ -473,10 +473,39 @@ __device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int
                                                col >= 0 && col < M::IL);
 }
 
+// march_walk_at over the n x n array: band `band` (of 2^band_log) of tile t.
+template <int RULE, int R, int T, int HL, int FL, int D, bool PEEL = march_peel(RULE, T)>
+__device__ __forceinline__ void march_walk(const uint8_t *src, uint8_t *dst, int k, float alpha,
+                                           TileXY t, int band, int band_log, bool active, int col)
+{
+    using M = MGeom<RULE, R, T, HL>;
+    const int H = M::RHO >> band_log; // band height, a multiple of the row period
+    march_walk_rows<RULE, R, T, HL, FL, D, PEEL>(src, dst, k, alpha, (int)(t.x << R),
+                                                 (int)(t.y << R) + band * H, H, active, col);
+}
+
+// Vertical stacks of tiles.  In a level-rb gasket of tiles, column tx holds
+// the rows ty with (tx & ty) == 0: for tx = 2^j (2v + 1) these are runs of
+// 2^j tiles starting at rows 2^(j+1) s with (v & s) == 0, and the columns
+// tx = 2^c u hold runs of at least 2^c tiles, starting at rows 2^c s with
+// (u & s) == 0.  So the tiles split into classes j = 0 .. c: class j < c is
+// a level rb-j-1 gasket of stacks 2^j tiles high and class c a level rb-c
+// gasket of stacks 2^c high, each mapped by lambda (Theorem 1 applied to
+// the stacks).  A walk down a stack pays the 2T halo rows once for all its
+// tiles.  stack_level(j, c, rb) is the gasket level of class j.
+__host__ __device__ constexpr int stack_level(int j, int c, int rb)
+{
+    return j < c ? rb - j - 1 : rb - c;
+}
+
 // One gasket: wavefront w of the grid takes (tile, band) items w*P .. w*P+P-1
-// (tiles in the map's id order, bands of a tile adjacent).  D: rows loaded
-// ahead of the walk; WPE: wavefronts per SIMD the register allocation must
-// allow.
+// (tiles in the map's id order, bands of a tile adjacent), or with stacks
+// (lambda map, a.stack_log = c > 0) the stacks of its class, the classes
+// j = c .. 0 in turn, class j ending at wavefront class_wave[j] (tallest first,
+// so the longest walks start first, and workgroups in launch order, which
+// the hardware deals round-robin to the dies, so every die gets a share of
+// every class).  D: rows loaded ahead of the walk; WPE: wavefronts per SIMD
+// the register allocation must allow.
 template <int RULE, int R, int T, int HL, int MAP, int FL, int WPE = 1, int D = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void march_kernel(MarchArgs a)
@@ -485,9 +514,34 @@ void march_kernel(MarchArgs a)
     static_assert(M::VALID, "march shape");
     const MarchLane<RULE, R, T, HL> ln;
     uint32_t wg = blockIdx.x;
-    if (a.order == FRACTAL_ORDER_CURVE_XCD)
+    if (a.order == FRACTAL_ORDER_CURVE_XCD && !(MAP == MAP_LAMBDA && a.stack_log > 0))
         wg = xcd_chunk(wg, gridDim.x);
     const uint32_t wave = wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (MAP == MAP_LAMBDA && a.stack_log > 0) {
+        const int c = a.stack_log;
+        int j = c; // classes in the grid from j = c down to 0
+        while (j > 0 && wave >= a.class_wave[j])
+            --j;
+        if (wave >= a.class_wave[0])
+            return; // past the last class
+        const int level = stack_level(j, c, a.rb);
+        const uint64_t item = (uint64_t)(wave - (j < c ? a.class_wave[j + 1] : 0u)) * M::P + ln.grp;
+        uint64_t count = 1u; // stacks in class j: 3^level
+        for (int e = 0; e < level; ++e)
+            count *= 3u;
+        const bool active = ln.grp < (uint32_t)M::P && item < count;
+        uint32_t tx = 0u, ty0 = 0u;
+        if (active) {
+            const TileXY t = lambda_lane((uint32_t)item, level, FRACTAL_ORDER_CURVE);
+            tx = j < c ? (2u * t.x + 1u) << j : t.x << c;
+            ty0 = j < c ? t.y << (j + 1) : t.y << c;
+        }
+        if (__builtin_amdgcn_ballot_w64(active) == 0u)
+            return;
+        march_walk_rows<RULE, R, T, HL, FL, D>(a.src, a.dst, a.k, a.alpha, (int)(tx << R),
+                                               (int)(ty0 << R), M::RHO << j, active, ln.col);
+        return;
+    }
     const uint64_t item = (uint64_t)wave * M::P + ln.grp; // (tile, band)
     const uint64_t tile = item >> a.band_log;
     const int band = (int)(item & ((1u << a.band_log) - 1u));

@@ -72,6 +72,15 @@ inline int launch_steps_of(int flags)
 }
 constexpr int kFuseFlags =
     FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16;
+constexpr int kStackFlags = FRACTAL_FLAG_STACK2 | FRACTAL_FLAG_STACK4 | FRACTAL_FLAG_STACK8;
+// log2 of the highest stack under these flags (0: one tile per walk).
+inline int stack_log_of(int flags)
+{
+    return (flags & FRACTAL_FLAG_STACK8)   ? 3
+           : (flags & FRACTAL_FLAG_STACK4) ? 2
+           : (flags & FRACTAL_FLAG_STACK2) ? 1
+                                           : 0;
+}
 
 // Arguments of one register-march launch (FRACTAL_FLAG_MARCH).
 struct MarchArgs {
@@ -83,6 +92,8 @@ struct MarchArgs {
     int order;      // FRACTAL_ORDER_*
     uint32_t total; // tiles in the map's id space (3^rb, or 4^rb for BB)
     int band_log;   // log2 of the bands each tile is cut into
+    int stack_log;  // lambda map: 0, or c > 0 for stacks of up to 2^c tiles (no bands)
+    uint32_t class_wave[5]; // stacks: end of class j's wavefronts (classes c .. 0 in order)
 };
 typedef void (*MarchFn)(MarchArgs);
 // Kernel for (map, rule, r, T steps, non-temporal stores); nullptr if none.

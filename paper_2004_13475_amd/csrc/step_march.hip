@@ -85,6 +85,11 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     a.rb = rb;
     a.order = t.order;
     a.total = (uint32_t)tiles;
+    a.stack_log = map == MAP_LAMBDA ? stack_log_of(t.flags) : 0;
+    if (a.stack_log > rb)
+        a.stack_log = rb;
+    for (int j = 0; j < 5; ++j)
+        a.class_wave[j] = 0u;
     uint8_t *bufs[2] = {static_cast<uint8_t *>(b0), static_cast<uint8_t *>(b1)};
     const int wpg = t.threads / 64;
     for (size_t i = 0; i < plan.size(); ++i) {
@@ -93,9 +98,19 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
         const int P = march_tiles_per_wave(rule, t.r, T);
         if (!fn || P < 1)
             return set_error(FRACTAL_E_INVAL, "no march kernel for rule %d r %d T %d", rule, t.r, T);
-        a.band_log = march_band_log(rule, t.r, T, tiles);
-        const uint64_t items = tiles << a.band_log;
-        const uint64_t waves = (items + (uint64_t)P - 1) / (uint64_t)P;
+        uint64_t waves = 0;
+        if (a.stack_log > 0) {
+            a.band_log = 0;
+            for (int j = a.stack_log; j >= 0; --j) { // tallest stacks first
+                waves += (pow3_u64(stack_level(j, a.stack_log, rb)) + (uint64_t)P - 1) /
+                         (uint64_t)P;
+                a.class_wave[j] = (uint32_t)waves;
+            }
+        } else {
+            a.band_log = march_band_log(rule, t.r, T, tiles);
+            const uint64_t items = tiles << a.band_log;
+            waves = (items + (uint64_t)P - 1) / (uint64_t)P;
+        }
         const uint64_t grid = (waves + (uint64_t)wpg - 1) / (uint64_t)wpg;
         a.src = bufs[i & 1];
         a.dst = bufs[(i + 1) & 1];

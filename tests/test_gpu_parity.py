@@ -238,6 +238,41 @@ def test_march_launches(rule, map_):
                 assert_match(k, rule, a1.cpu().numpy(), ref, f"march k={k} r={r}")
 
 
+@pytest.mark.parametrize("rule", RULES)
+def test_march_stacks(rule):
+    """Stacks of up to 2, 4 or 8 tiles (each class of equal column runs a
+    smaller gasket of stacks under lambda) give the same bits as one step
+    per launch, at levels where the stack level is clamped to the tile
+    level (k - r < 3) and above; small levels also against the oracle."""
+    torch = torch_dev()
+    cell = 1 if rule == fi.RULE_CA else 4
+    fuses = (F.FLAG_FUSE2, F.FLAG_FUSE8) + ((F.FLAG_FUSE16,) if rule == fi.RULE_CA else ())
+    for k in (4, 6, 9, 12):
+        init = fi.window_values(k, rule, 90 + k)
+        for r in range(2, min(k, 7) + 1):
+            if (1 << r) * cell < 16:
+                continue
+            for steps in (3, 16, 37):
+                b0, b1 = to_device(init), zeros_state(k, rule)
+                F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, steps, r, 64, 2,
+                             F.FLAG_SEGMENTS)
+                _sync()
+                ref = (b0 if steps % 2 == 0 else b1).view(torch.uint8).clone()
+                for stack in (F.FLAG_STACK2, F.FLAG_STACK4, F.FLAG_STACK8):
+                    for fuse in fuses:
+                        fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | fuse | stack
+                        a0, a1 = to_device(init), zeros_state(k, rule)
+                        F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, a0, a1, steps, r, 256, 2, fl)
+                        _sync()
+                        fa = a0 if steps % 2 == 0 else a1
+                        assert torch.equal(fa.view(torch.uint8), ref), (k, r, steps, fl)
+                if k <= 6 and steps == 37:
+                    want = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64),
+                                        steps)
+                    assert_match(k, rule, (b0 if steps % 2 == 0 else b1).cpu().numpy(), want,
+                                 f"stacks k={k} r={r}")
+
+
 def test_march_rejects_bad_tunings():
     """March launches need whole segments, rows of >= 16 bytes and a lambda
     or BB map; FUSE8 needs the march engine."""

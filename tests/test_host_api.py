@@ -80,7 +80,8 @@ def test_tuning_defaults_and_validation():
             assert 0 <= r <= min(k, 7) and k - r <= 15
             assert th in (64, 256) and order in (0, 1, 2)
             lds = (0, 1, 2, 3, 9, 11, 17, 19)
-            march = tuple(32 | 1 | nt | fuse for nt in (0, 2) for fuse in (0, 8, 16, 64, 128))
+            march = tuple(32 | 1 | nt | fuse | st for nt in (0, 2) for fuse in (0, 8, 16, 64, 128)
+                          for st in (0, 256, 512, 1024))
             assert flags in lds + march, (k, rule, flags)
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
@@ -95,12 +96,13 @@ def test_tuning_defaults_and_validation():
     # march: needs whole segments, 16-byte rows, a lambda or BB map; FUSE8
     # only with march; one fuse flag at a time
     for map_, rule, r, fl in ((0, 0, 4, 32), (0, 0, 3, 33), (2, 0, 4, 33), (0, 0, 4, 1 | 64),
-                              (0, 0, 4, 33 | 8 | 64), (0, 0, 4, 33 | 256), (0, 1, 4, 33 | 128),
-                              (0, 0, 4, 1 | 128)):
+                              (0, 0, 4, 33 | 8 | 64), (0, 0, 4, 33 | 2048), (0, 1, 4, 33 | 128),
+                              (0, 0, 4, 1 | 128), (0, 0, 4, 1 | 256), (0, 0, 4, 33 | 256 | 512)):
         with pytest.raises(F.FractalError):
             F.step_tuned(map_, 10, rule, 0.2, FAKE0, FAKE1, 1, r, 256, 2, fl, stream=0)
     F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 0, 4, 256, 2, 33 | 64, stream=0)  # valid, 0 steps
     F.step_tuned(1, 10, 1, 0.2, FAKE0, FAKE1, 0, 2, 256, 0, 33 | 16, stream=0)
+    F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 0, 4, 256, 2, 33 | 64 | 1024, stream=0)
 
 
 def test_batch_validation():
