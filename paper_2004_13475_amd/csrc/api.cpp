@@ -125,7 +125,7 @@ static int clamp_r(int k, int r)
 static fractal_tuning builtin_default(int k, int rule)
 {
     const bool big = k >= 15;
-    const int r = clamp_r(k, big ? (rule == FRACTAL_RULE_CA ? 6 : 5) : 4);
+    const int r = clamp_r(k, (big && rule == FRACTAL_RULE_CA) ? 6 : 4);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
     if (t.flags & FRACTAL_FLAG_MARCH)
         t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |

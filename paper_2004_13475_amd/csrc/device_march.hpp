@@ -52,7 +52,13 @@ constexpr int march_hl(int rule, int T)
 // halo), 8 for heat.
 constexpr bool march_supported(int rule, int T) { return T <= (rule == RULE_CA ? 16 : 8); }
 constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
-constexpr int march_depth(int rule, int T) { return (rule == RULE_CA && T <= 4) ? 8 : 4; }
+// Rows loaded ahead of the walk: a whole number of them per unrolled pass
+// (16 rows for the automaton, 12 for heat).  Heat launches of 8 steps keep a
+// whole pass in flight (it costs registers but no occupancy at that size).
+constexpr int march_depth(int rule, int T)
+{
+    return rule == RULE_CA ? (T <= 4 ? 8 : 4) : (T >= 8 ? 12 : 4);
+}
 // Band heights (and so band origins) are multiples of this row period.
 constexpr int march_row_period(int rule) { return rule == RULE_CA ? 16 : 4; }
 // Whether the walk's first passes leave out the levels not yet needed (about
