@@ -387,8 +387,10 @@ double fractal_now(void);
 
 /* Create a server over d_arena (arena_bytes of device memory owned by the
  * caller, 256-byte aligned) with at most max_slots concurrently admitted
- * requests, working on `stream`.  steps_per_iter is the number of batched
- * step launches per scheduling iteration (>= 1).  A host thread is started. */
+ * requests, working on `stream`.  steps_per_iter (>= 1) is the number of
+ * steps each admitted request advances per scheduling iteration; they are
+ * fused into launches of up to 16 (automaton) or 8 (heat) steps, so 16 lets
+ * every launch take its longest form.  A host thread is started. */
 int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots,
                          int steps_per_iter, void *stream, void **server);
 

@@ -337,7 +337,7 @@ def now() -> float:
 class Server:
     """Handle on a libfractal request server (continuous batching)."""
 
-    def __init__(self, arena, arena_bytes, max_slots, steps_per_iter=8, stream=None):
+    def __init__(self, arena, arena_bytes, max_slots, steps_per_iter=16, stream=None):
         h = ctypes.c_void_p()
         _check(load().fractal_serve_create(_ptr(arena), arena_bytes, max_slots,
                                            steps_per_iter, _stream(stream), ctypes.byref(h)))

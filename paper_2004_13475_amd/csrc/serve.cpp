@@ -6,9 +6,9 @@
 // a stream of its own, so that the memory-bound clear and seed of new
 // requests overlap the compute-bound steps of the running ones; the step
 // stream waits for it only before the iteration that first uses them),
-// and then repeatedly enqueues one iteration: steps_per_iter launches of the
-// batched step kernel over every active slot (slots with fewer remaining
-// steps drop out of the later launches of the iteration).  Requests that
+// and then repeatedly enqueues one iteration: steps_per_iter steps of every
+// active slot, as the batched plan's fused launches (slots with fewer
+// remaining steps drop out of the later launches of the iteration).  Requests that
 // arrive meanwhile join the next iteration.  A finished slot leaves the table
 // at once; a retire thread waits for its last step, computes nothing on the
 // host, copies the final state (if asked) and the checksum back, stamps the
