@@ -105,8 +105,10 @@ extern "C" {
                                     (the tiles of a column split into runs;
                                     each class of equal runs is a smaller
                                     gasket of stacks mapped by lambda, so the
-                                    2T halo rows are paid once per stack).
-                                    Tiles are then taken in curve order.  The
+                                    2T halo rows are paid once per stack;
+                                    the classes are interleaved block by
+                                    block).  Tiles are then taken in curve
+                                    order.  The
                                     BB map, batches and compact states ignore
                                     it.  Needs FRACTAL_FLAG_MARCH; STACK2 / 4
                                     / 8 are exclusive */

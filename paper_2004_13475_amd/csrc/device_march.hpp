@@ -506,12 +506,15 @@ __host__ __device__ constexpr int stack_level(int j, int c, int rb)
 
 // One gasket: wavefront w of the grid takes (tile, band) items w*P .. w*P+P-1
 // (tiles in the map's id order, bands of a tile adjacent), or with stacks
-// (lambda map, a.stack_log = c > 0) the stacks of its class, the classes
-// j = c .. 0 in turn, class j ending at wavefront class_wave[j] (tallest first,
-// so the longest walks start first, and workgroups in launch order, which
-// the hardware deals round-robin to the dies, so every die gets a share of
-// every class).  D: rows loaded ahead of the walk; WPE: wavefronts per SIMD
-// the register allocation must allow.
+// (lambda map, a.stack_log = c > 0) one class's stacks.  Stack item L of
+// class c and the 3^(c-j-1) items from L 3^(c-j-1) of class j < c fill the
+// same 2^c x 2^c block of tiles (the low base-3 digits of a curve id pick
+// the sub-block), so the grid runs in groups of G = 1 + (3^c - 1) / 2
+// wavefronts over P blocks: one wavefront of class c, then 3^(c-j-1) of
+// each class j = c-1 .. 0.  Neighbouring tiles of all classes are walked
+// close together in time and place (the dies get contiguous runs of groups),
+// so halo columns are shared in L2.  D: rows loaded ahead of the walk; WPE:
+// wavefronts per SIMD the register allocation must allow.
 template <int RULE, int R, int T, int HL, int MAP, int FL, int WPE = 1, int D = 4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void march_kernel(MarchArgs a)
@@ -520,18 +523,31 @@ void march_kernel(MarchArgs a)
     static_assert(M::VALID, "march shape");
     const MarchLane<RULE, R, T, HL> ln;
     uint32_t wg = blockIdx.x;
-    if (a.order == FRACTAL_ORDER_CURVE_XCD && !(MAP == MAP_LAMBDA && a.stack_log > 0))
+    if (a.order == FRACTAL_ORDER_CURVE_XCD)
         wg = xcd_chunk(wg, gridDim.x);
     const uint32_t wave = wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (MAP == MAP_LAMBDA && a.stack_log > 0) {
+        if (wave >= a.stack_waves)
+            return; // past the last group
         const int c = a.stack_log;
-        int j = c; // classes in the grid from j = c down to 0
-        while (j > 0 && wave >= a.class_wave[j])
-            --j;
-        if (wave >= a.class_wave[0])
-            return; // past the last class
+        uint32_t pc = 1u; // 3^c
+        for (int e = 0; e < c; ++e)
+            pc *= 3u;
+        const uint32_t G = 1u + (pc - 1u) / 2u;
+        const uint32_t g = wave / G, slot = wave - g * G;
+        int j = c;
+        uint32_t base = 0u, size = 1u; // class j's wavefronts in a group: base .. base+size-1
+        if (slot >= 1u) {
+            j = c - 1;
+            base = 1u;
+            while (slot >= base + size) {
+                base += size;
+                size *= 3u;
+                --j;
+            }
+        }
         const int level = stack_level(j, c, a.rb);
-        const uint64_t item = (uint64_t)(wave - (j < c ? a.class_wave[j + 1] : 0u)) * M::P + ln.grp;
+        const uint64_t item = ((uint64_t)g * size + (slot - base)) * M::P + ln.grp;
         uint64_t count = 1u; // stacks in class j: 3^level
         for (int e = 0; e < level; ++e)
             count *= 3u;

@@ -93,7 +93,7 @@ struct MarchArgs {
     uint32_t total; // tiles in the map's id space (3^rb, or 4^rb for BB)
     int band_log;   // log2 of the bands each tile is cut into
     int stack_log;  // lambda map: 0, or c > 0 for stacks of up to 2^c tiles (no bands)
-    uint32_t class_wave[5]; // stacks: end of class j's wavefronts (classes c .. 0 in order)
+    uint32_t stack_waves; // stacks: wavefronts of the grid (groups x (1 + (3^c - 1) / 2))
 };
 typedef void (*MarchFn)(MarchArgs);
 // Kernel for (map, rule, r, T steps, non-temporal stores); nullptr if none.

@@ -88,8 +88,7 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     a.stack_log = map == MAP_LAMBDA ? stack_log_of(t.flags) : 0;
     if (a.stack_log > rb)
         a.stack_log = rb;
-    for (int j = 0; j < 5; ++j)
-        a.class_wave[j] = 0u;
+    a.stack_waves = 0u;
     uint8_t *bufs[2] = {static_cast<uint8_t *>(b0), static_cast<uint8_t *>(b1)};
     const int wpg = t.threads / 64;
     for (size_t i = 0; i < plan.size(); ++i) {
@@ -101,11 +100,10 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
         uint64_t waves = 0;
         if (a.stack_log > 0) {
             a.band_log = 0;
-            for (int j = a.stack_log; j >= 0; --j) { // tallest stacks first
-                waves += (pow3_u64(stack_level(j, a.stack_log, rb)) + (uint64_t)P - 1) /
-                         (uint64_t)P;
-                a.class_wave[j] = (uint32_t)waves;
-            }
+            // groups of P blocks of 2^c x 2^c tiles, 1 + (3^c - 1) / 2 wavefronts each
+            const uint64_t groups = (pow3_u64(rb - a.stack_log) + (uint64_t)P - 1) / (uint64_t)P;
+            waves = groups * (1u + (pow3_u64(a.stack_log) - 1u) / 2u);
+            a.stack_waves = (uint32_t)waves;
         } else {
             a.band_log = march_band_log(rule, t.r, T, tiles);
             const uint64_t items = tiles << a.band_log;
