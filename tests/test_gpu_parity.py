@@ -273,6 +273,36 @@ def test_march_stacks(rule):
                                  f"stacks k={k} r={r}")
 
 
+@pytest.mark.parametrize("rule", RULES)
+def test_autotune_picks_a_valid_launch(rule):
+    """The autotuner times its candidates (both engines, fusion depths,
+    stacks) on the caller's buffers, caches the fastest for the level, and
+    lambda steps under that cached launch give the same bits as one step per
+    launch; the built-in default comes back after set_tuning restores it."""
+    torch = torch_dev()
+    k = 10
+    before = F.get_tuning(k, rule)
+    init = fi.window_values(k, rule, 123)
+    w0, w1 = to_device(init), zeros_state(k, rule)
+    t = F.autotune(k, rule, ALPHA, w0, w1)
+    _sync()
+    assert tuple(F.get_tuning(k, rule)) == tuple(t)
+    r, th, order, fl = t
+    assert 0 <= r <= 7 and th in (64, 256) and order in (0, 1, 2)
+    assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024) == 0
+    for steps in (5, 40):
+        a0, a1 = to_device(init), zeros_state(k, rule)
+        F.lambda_step(k, F.R_AUTO, rule, ALPHA, a0, a1, steps)
+        b0, b1 = to_device(init), zeros_state(k, rule)
+        F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, steps, r, 64, 2, F.FLAG_SEGMENTS)
+        _sync()
+        got = a0 if steps % 2 == 0 else a1
+        ref = b0 if steps % 2 == 0 else b1
+        assert torch.equal(got.view(torch.uint8), ref.view(torch.uint8)), (t, steps)
+    F.set_tuning(k, rule, *before)
+    assert tuple(F.get_tuning(k, rule)) == tuple(before)
+
+
 def test_march_rejects_bad_tunings():
     """March launches need whole segments, rows of >= 16 bytes and a lambda
     or BB map; FUSE8 needs the march engine."""
