@@ -56,10 +56,15 @@ KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kern
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code: comments and whitespace are left
+    out, so editing a comment does not orphan the counter summaries."""
     h = hashlib.sha256()
     for f in KERNEL_SRC:
-        with open(os.path.join(ROOT, "paper_2004_13475_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2004_13475_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)  # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                # line comments
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
