@@ -322,12 +322,13 @@ def test_march_rejects_bad_tunings():
     del torch
 
 
-@pytest.mark.parametrize("flags", [11, 19, 35 | 16, 35 | 64, 35 | 128])
+@pytest.mark.parametrize("flags", [11, 19, 35 | 16, 35 | 64, 35 | 128, 35 | 128 | 256,
+                                   35 | 64 | 512])
 @pytest.mark.parametrize("rule", RULES)
 def test_fused_full_size_k16_sampled(rule, flags):
-    """Level 16 with two-, four- and eight-step launches (LDS and register
-    march engines), 200 steps, sampled against the oracle's light-cone
-    windows."""
+    """Level 16 with two-, four-, eight- and sixteen-step launches (LDS and
+    register march engines, single tiles and stacks of 2 or 4), 200 steps,
+    sampled against the oracle's light-cone windows."""
     if flags & 128 and rule != fi.RULE_CA:
         pytest.skip("sixteen-step launches are for the automaton")
     k = 16
