@@ -595,6 +595,35 @@ def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_one_thread(k=12, steps=20):
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1;
+    it touches no GPU): level-12 automaton steps over the whole array."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import fractal_inputs as fi, oracle; "
+            "s = fi.full_state(%d, 0, 1); t = time.perf_counter(); oracle.ca_run(%d, s, %d); "
+            "print(time.perf_counter() - t, oracle.threads())" % (ROOT, k, k, steps))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=300, check=True).stdout.split()
+        sec, thr = float(out[0]), int(out[1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
+    return {"value": 3 ** k * steps / sec, "unit": "cells/s", "threads": thr,
+            "sample": f"level-{k} gasket, whole array: {steps} automaton steps ({sec:.1f} s)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -690,7 +719,8 @@ def main() -> int:
         cpu = {"value": 3 ** ck * (nsteps[0] + nsteps[1]) / dtc, "unit": "cells/s",
                "cores": oracle.threads(), "kind": "oracle",
                "sample": f"level-14 gasket, whole array: {nsteps[0]} automaton steps + "
-                         f"{nsteps[1]} float64 heat steps ({dtc:.1f} s)"}
+                         f"{nsteps[1]} float64 heat steps ({dtc:.1f} s)",
+               "cpu_model": cpu_model(), "one_thread": oracle_one_thread()}
 
     line = {
         "metric": "fractal cells updated/s and HBM GB/s (% peak), lambda vs BB; "
