@@ -103,6 +103,11 @@ def test_tuning_defaults_and_validation():
     F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 0, 4, 256, 2, 33 | 64, stream=0)  # valid, 0 steps
     F.step_tuned(1, 10, 1, 0.2, FAKE0, FAKE1, 0, 2, 256, 0, 33 | 16, stream=0)
     F.step_tuned(0, 10, 0, 0.2, FAKE0, FAKE1, 0, 4, 256, 2, 33 | 64 | 1024, stream=0)
+    # stacks: lambda march only in effect; the BB map accepts and ignores them
+    F.step_tuned(1, 10, 1, 0.2, FAKE0, FAKE1, 0, 4, 256, 2, 33 | 2 | 64 | 512, stream=0)
+    for fl in (1 | 512, 33 | 256 | 1024):  # no march / two stack heights
+        with pytest.raises(F.FractalError):
+            F.step_tuned(1, 10, 1, 0.2, FAKE0, FAKE1, 1, 4, 256, 2, fl, stream=0)
 
 
 def test_batch_validation():
@@ -115,6 +120,8 @@ def test_batch_validation():
         F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 8), stream=0)
     with pytest.raises(F.FractalError):  # bad thread count
         F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 128, 2, 0), stream=0)
+    # stack flags are accepted by batches (and ignored there)
+    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], tuning=(4, 256, 2, 33 | 64 | 256), stream=0)
     F.batch_step([], stream=0)
     F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], stream=0)  # no steps: no-op
 
