@@ -157,6 +157,37 @@ __global__ __launch_bounds__(256) void swrd_kernel(SwRdArgs a)
     const uint64_t pitch = (uint64_t)n * G::S;
     uint32_t acc_u = 0u;
     double acc_d = 0.0;
+    if constexpr (OP == OP_RD && G::CB == 16) {
+        // rows in groups of UR: every lane issues the group's loads before
+        // it adds (a chunk without a member reads the buffer's first chunk,
+        // always valid, and is skipped), so UR loads are in flight at once
+        constexpr int UR = G::RHO < 8 ? G::RHO : 8;
+        using gu32x4 = const __attribute__((address_space(1))) u32x4;
+        for (int j0 = 0; j0 < G::RHO; j0 += UR) {
+            u32x4 v[UR];
+            bool has[UR];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const uint32_t y = y0 + (uint32_t)(j0 + u);
+                has[u] = active && (x & y) == 0u;
+                v[u] = *(gu32x4 *)(has[u] ? base + (uint64_t)(j0 + u) * pitch : a.buf);
+            }
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                if (!has[u])
+                    continue;
+                const uint32_t y = y0 + (uint32_t)(j0 + u);
+#pragma unroll
+                for (int c = 0; c < G::CC; ++c) {
+                    const bool m = (((uint32_t)c) & y) == 0u;
+                    if constexpr (RULE == RULE_CA)
+                        acc_u += m ? ((v[u][c >> 2] >> (8 * (c & 3))) & 0xFFu) : 0u;
+                    else
+                        acc_d += m ? (double)__uint_as_float(v[u][c]) : 0.0;
+                }
+            }
+        }
+    } else
     for (int j = 0; j < G::RHO; ++j) {
         const uint32_t y = y0 + (uint32_t)j;
         uint8_t *p = base + (uint64_t)j * pitch;
