@@ -97,9 +97,11 @@ extern "C" {
                                    FRACTAL_FLAG_MARCH only) */
 #define FRACTAL_FLAG_FUSE16 128 /* sixteen steps per launch (with
                                    FRACTAL_FLAG_MARCH, automaton only) */
-#define FRACTAL_FLAG_PERSISTENT 4 /* batch only: persistent workgroups walking
-                                     contiguous ranges of the tile list, instead
-                                     of one workgroup per tile */
+#define FRACTAL_FLAG_PERSISTENT 4 /* batch only: register-march launches run
+                                     a persistent grid (as many workgroups as
+                                     the chip holds) striding through each
+                                     die's share of the tile list, instead of
+                                     one workgroup per group of tiles */
 #define FRACTAL_FLAG_STACK2 256  /* lambda-map march launches of one gasket:
                                     walk vertical stacks of up to 2 tiles
                                     (the tiles of a column split into runs;
@@ -141,6 +143,19 @@ int fractal_lambda_map(int k, int r, uint32_t *d_xy, void *stream);
  * float16, columns 0 and 1 of B hold tau_x and tau_y; D[0][0..1] is lambda
  * before mirroring).  Exact for k - r <= 16; larger levels give E_INVAL. */
 int fractal_lambda_map_mfma(int k, int r, uint32_t *d_xy, void *stream);
+
+/* lambda as the register-march step kernels evaluate it, one tile per lane
+ * (their wavefronts hold several tiles side by side, so every lane group
+ * computes its own tile's block with a loop over its id's base-3 digits
+ * rather than sharing one ballot): for every tile id i in [0, 3^(k-r)),
+ * d_xy[2*i + 0] = block x, d_xy[2*i + 1] = block y of the tile that id i
+ * stands for in dispatch order `order`.  FRACTAL_ORDER_NATURAL: omega =
+ * (i mod gx, i div gx), so the result equals fractal_lambda_map's; the
+ * CURVE orders: base-3 digit mu-1 of i is beta_mu (Theorem 1's map taken
+ * along the gasket's self-similar order, as compact storage numbers its
+ * tiles).  d_xy: device array of 2 * 3^(k-r) uint32, caller-owned.
+ * 0 <= r <= k, k - r <= 20. */
+int fractal_lambda_map_tiles(int k, int r, int order, uint32_t *d_xy, void *stream);
 
 /* Seeded initial state: writes all n*n cells of d_buf.  Members get
  * SplitMix64 output number i+1 (state 0), i = stream_id * 2^32 + y*n + x:
@@ -337,24 +352,38 @@ typedef struct fractal_instance {
     void *d_buf1;
 } fractal_instance;
 
-/* Advance many gaskets of uneven levels together.  Each step is one launch
- * over the combined tile list of all instances: a tile id is turned into
- * (instance, local omega) with a device table of per-instance prefix offsets
- * of 3^(k_i - r_i), then into a tile by that instance's lambda.  By default
- * every tile gets a workgroup; with FRACTAL_FLAG_PERSISTENT in tuning->flags
- * a persistent grid (CUs x 32 workgroups) walks contiguous ranges of the
- * list.  The max_i steps_i launches are captured once into a HIP graph and
- * the graph is launched on `stream`.  Instances with fewer steps drop out of
- * later launches.  `tuning` may be NULL (per-level defaults / cached tuning);
- * otherwise tuning->r applies to every instance (clamped per level), or
- * FRACTAL_R_AUTO keeps the per-level defaults, tuning->threads 0 keeps the
- * default thread count, and tuning->flags applies to every instance
- * (FRACTAL_FLAG_FUSE2 falls back to single steps where tiles are too narrow).
- * Results are bit-identical to one fractal_lambda_step call per instance.
- * The call allocates a device table (freed when the graph has run) and
- * returns after enqueuing; it synchronises nothing else.  count <= 65536. */
+/* Bytes of device workspace fractal_batch_step needs for `count` instances
+ * (0 <= count <= 65536): the per-instance offset table. */
+int fractal_batch_workspace(int count, size_t *bytes);
+
+/* Advance many gaskets of uneven levels together.  Instances are grouped
+ * by their tile launch; each group's tiles form one work list: a tile id is
+ * turned into (instance, local id) with a device table of per-instance
+ * prefix offsets of 3^(k_i - r_i), then into a tile by that instance's
+ * lambda.  Each launch is one kernel per group over its whole list; all
+ * max_i steps_i launches are captured once into a HIP graph and the graph
+ * is launched on `stream`.  Instances with fewer steps drop out of later
+ * launches.  `tuning` may be NULL (per-level defaults or cached tuning);
+ * otherwise tuning->r applies to every instance (clamped per level) or
+ * FRACTAL_R_AUTO keeps the per-level tile size, tuning->threads 0 keeps the
+ * default thread count, and tuning->flags, where any flag besides
+ * FRACTAL_FLAG_PERSISTENT is set, applies to every instance (FUSE flags fall
+ * back to what narrow tiles allow; STACK flags are ignored).  With
+ * FRACTAL_FLAG_PERSISTENT the register-march launches run a persistent grid
+ * (as many workgroups as the chip holds at once, the workgroups of each die
+ * striding through that die's contiguous share of the list); LDS-engine
+ * launches always take one workgroup per tile.
+ * d_work: caller-owned device workspace of at least
+ * fractal_batch_workspace(count) bytes, 16-byte aligned; the table is
+ * copied into it on `stream`, so it must stay allocated and unused by
+ * other work until the batch's work on `stream` has completed.  The library
+ * allocates no device memory (a pinned host staging copy of the table is
+ * kept until the graph has run).  Results are bit-identical to one
+ * fractal_lambda_step call per instance.  Instance buffers must not overlap
+ * one another.  E_INVAL on a short workspace. */
 int fractal_batch_step(const fractal_instance *inst, int count,
-                       const fractal_tuning *tuning, void *stream);
+                       const fractal_tuning *tuning, void *d_work,
+                       size_t work_bytes, void *stream);
 
 /* ---------------------------------------------------------------- serving
  * A request server keeps gasket simulations resident in a caller-provided
@@ -388,13 +417,21 @@ typedef struct fractal_result {
 double fractal_now(void);
 
 /* Create a server over d_arena (arena_bytes of device memory owned by the
- * caller, 256-byte aligned) with at most max_slots concurrently admitted
- * requests, working on `stream`.  steps_per_iter (>= 1) is the number of
- * steps each admitted request advances per scheduling iteration; they are
- * fused into launches of up to 16 (automaton) or 8 (heat) steps, so 16 lets
- * every launch take its longest form.  A host thread is started. */
+ * caller, 256-byte aligned; a small header of it holds the server's device
+ * tables, the rest request states) with at most max_slots concurrently
+ * admitted requests (1..4096), working on `stream`.  Each admitted request
+ * advances 16 steps per scheduling iteration until
+ * fractal_serve_set_steps_per_iter changes it.  Host threads are started;
+ * the library allocates no device memory.  E_NOMEM if the arena cannot hold
+ * the header. */
 int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots,
-                         int steps_per_iter, void *stream, void **server);
+                         void *stream, void **server);
+
+/* Steps each admitted request advances per scheduling iteration (1..2^20),
+ * from the next iteration on.  They are fused into launches of up to 16
+ * (automaton) or 8 (heat) steps, so multiples of 16 let every launch take
+ * its longest form; smaller values admit arriving requests sooner. */
+int fractal_serve_set_steps_per_iter(void *server, int steps_per_iter);
 
 /* Queue a request; never waits for the GPU.  A request whose footprint
  * (2 * 4^k cells, plus alignment) exceeds the arena fails with

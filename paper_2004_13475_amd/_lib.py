@@ -26,15 +26,15 @@ R_AUTO = -1
 
 EXPORTED = [
     "fractal_grid_dims", "fractal_lambda_map", "fractal_lambda_map_mfma",
-    "fractal_seed_fill", "fractal_bb_step", "fractal_lambda_step",
+    "fractal_lambda_map_tiles", "fractal_seed_fill", "fractal_bb_step", "fractal_lambda_step",
     "fractal_lambda_step_mfma", "fractal_step_tuned", "fractal_autotune",
-    "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_step",
+    "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_workspace", "fractal_batch_step",
     "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
     "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
     "fractal_compact_step", "fractal_nbb_builtin", "fractal_nbb_lambda_map",
     "fractal_nbb_single_write", "fractal_nbb_reduce_workspace", "fractal_nbb_reduce",
     "fractal_nbb_ca_step",
-    "fractal_now", "fractal_serve_create", "fractal_serve_submit",
+    "fractal_now", "fractal_serve_create", "fractal_serve_set_steps_per_iter", "fractal_serve_submit",
     "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
 ]
 
@@ -99,6 +99,7 @@ def load():
         "fractal_grid_dims": ([i, i, pu32, pu32], i),
         "fractal_lambda_map": ([i, i, vp, vp], i),
         "fractal_lambda_map_mfma": ([i, i, vp, vp], i),
+        "fractal_lambda_map_tiles": ([i, i, i, vp, vp], i),
         "fractal_seed_fill": ([i, i, u32, vp, vp], i),
         "fractal_bb_step": ([i, i, i, f, vp, vp, i, vp], i),
         "fractal_lambda_step": ([i, i, i, f, vp, vp, i, vp], i),
@@ -107,7 +108,9 @@ def load():
         "fractal_autotune": ([i, i, f, vp, vp, vp, ctypes.POINTER(Tuning)], i),
         "fractal_get_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
         "fractal_set_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
-        "fractal_batch_step": ([ctypes.POINTER(Instance), i, ctypes.POINTER(Tuning), vp], i),
+        "fractal_batch_workspace": ([i, ctypes.POINTER(ctypes.c_size_t)], i),
+        "fractal_batch_step": ([ctypes.POINTER(Instance), i, ctypes.POINTER(Tuning), vp,
+                                ctypes.c_size_t, vp], i),
         "fractal_single_write": ([i, i, i, i, u32, vp, vp], i),
         "fractal_reduce_workspace": ([i, i, ctypes.POINTER(ctypes.c_size_t)], i),
         "fractal_reduce": ([i, i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
@@ -123,7 +126,8 @@ def load():
         "fractal_nbb_reduce": ([ctypes.POINTER(Nbb), i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
         "fractal_nbb_ca_step": ([ctypes.POINTER(Nbb), i, i, i, vp, vp, i, vp], i),
         "fractal_now": ([], ctypes.c_double),
-        "fractal_serve_create": ([vp, ctypes.c_size_t, i, i, vp, ctypes.POINTER(vp)], i),
+        "fractal_serve_create": ([vp, ctypes.c_size_t, i, vp, ctypes.POINTER(vp)], i),
+        "fractal_serve_set_steps_per_iter": ([vp, i], i),
         "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
         "fractal_serve_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(Result)], i),
         "fractal_serve_destroy": ([vp], i),
@@ -183,6 +187,12 @@ def lambda_map_mfma(k, r, out, stream=None):
     return _check(load().fractal_lambda_map_mfma(k, r, _ptr(out), _stream(stream)))
 
 
+def lambda_map_tiles(k, r, order, out, stream=None):
+    """The per-lane form of lambda the march kernels use: out[2i], out[2i+1]
+    = block of tile id i in dispatch order `order`."""
+    return _check(load().fractal_lambda_map_tiles(k, r, order, _ptr(out), _stream(stream)))
+
+
 def seed_fill(k, rule, stream_id, buf, stream=None):
     return _check(load().fractal_seed_fill(k, rule, stream_id, _ptr(buf), _stream(stream)))
 
@@ -227,15 +237,48 @@ def set_tuning(k, rule, r, threads, order, flags=0):
     return _check(load().fractal_set_tuning(k, rule, ctypes.byref(t)))
 
 
-def batch_step(instances, tuning=None, stream=None):
-    """instances: list of (k, rule, steps, alpha, buf0, buf1)."""
+def _nbytes(buf, nbytes, what):
+    """Size in bytes of a device buffer: a tensor's own size, else the
+    caller's `nbytes` (required for raw addresses)."""
+    if hasattr(buf, "numel"):
+        size = buf.numel() * buf.element_size()
+        return size if nbytes is None else min(size, int(nbytes))
+    if nbytes is None:
+        raise ValueError(f"{what}: a raw device address needs its size in bytes (nbytes=)")
+    return int(nbytes)
+
+
+def batch_workspace(count) -> int:
+    """Bytes of device workspace batch_step needs for `count` instances."""
+    b = ctypes.c_size_t()
+    _check(load().fractal_batch_workspace(count, ctypes.byref(b)))
+    return b.value
+
+
+def batch_step(instances, tuning=None, work=None, stream=None, work_bytes=None):
+    """instances: list of (k, rule, steps, alpha, buf0, buf1).  `work`: the
+    device workspace of batch_workspace(len(instances)) bytes (a tensor, or a
+    raw address with its size in `work_bytes`).  When None, a torch tensor
+    of that size is allocated on the current device and marked as used by
+    the (torch) stream, so torch does not hand its memory out again before
+    the batch's work on that stream has run; a raw stream needs an explicit
+    workspace."""
     arr = (Instance * len(instances))()
     for j, (k, rule, steps, alpha, b0, b1) in enumerate(instances):
         arr[j] = Instance(k, rule, steps, alpha, _ptr(b0), _ptr(b1))
     tp = None
     if tuning is not None:
         tp = ctypes.byref(Tuning(*tuning) if len(tuning) == 4 else Tuning(*tuning, 0))
-    return _check(load().fractal_batch_step(arr, len(instances), tp, _stream(stream)))
+    if work is None:
+        if isinstance(stream, int):
+            raise ValueError("batch_step on a raw stream needs an explicit workspace")
+        import torch
+        work = torch.empty(max(batch_workspace(len(instances)), 16), dtype=torch.uint8,
+                           device="cuda")
+        work.record_stream(torch.cuda.current_stream() if stream is None else stream)
+    nbytes = _nbytes(work, work_bytes, "batch_step workspace")
+    return _check(load().fractal_batch_step(arr, len(instances), tp, _ptr(work), nbytes,
+                                            _stream(stream)))
 
 
 def single_write(map_, k, r, rule, value, buf, stream=None):
@@ -252,11 +295,12 @@ def reduce_workspace(k, r) -> int:
     return b.value
 
 
-def reduce(map_, k, r, rule, buf, work, out, stream=None):
+def reduce(map_, k, r, rule, buf, work, out, stream=None, work_bytes=None):
     """Test RD: the sum of the gasket cells of `buf` into the 8-byte device
     buffer `out` (uint64 for uint8 cells, float64 for float32 cells); `work`
-    is a device buffer of at least reduce_workspace(k, r) bytes."""
-    nbytes = work.numel() * work.element_size() if hasattr(work, "numel") else 1 << 62
+    is a device buffer of at least reduce_workspace(k, r) bytes (a tensor,
+    or a raw address with its size in `work_bytes`)."""
+    nbytes = _nbytes(work, work_bytes, "reduce workspace")
     return _check(load().fractal_reduce(map_, k, r, rule, _ptr(buf), _ptr(work), nbytes,
                                         _ptr(out), _stream(stream)))
 
@@ -319,8 +363,8 @@ def nbb_reduce_workspace(f, level, r) -> int:
     return b.value
 
 
-def nbb_reduce(f, map_, level, r, buf, work, out, stream=None):
-    nbytes = work.numel() * work.element_size() if hasattr(work, "numel") else 1 << 62
+def nbb_reduce(f, map_, level, r, buf, work, out, stream=None, work_bytes=None):
+    nbytes = _nbytes(work, work_bytes, "nbb_reduce workspace")
     return _check(load().fractal_nbb_reduce(ctypes.byref(f), map_, level, r, _ptr(buf),
                                             _ptr(work), nbytes, _ptr(out), _stream(stream)))
 
@@ -337,12 +381,18 @@ def now() -> float:
 class Server:
     """Handle on a libfractal request server (continuous batching)."""
 
-    def __init__(self, arena, arena_bytes, max_slots, steps_per_iter=16, stream=None):
+    def __init__(self, arena, arena_bytes, max_slots, steps_per_iter=None, stream=None):
         h = ctypes.c_void_p()
         _check(load().fractal_serve_create(_ptr(arena), arena_bytes, max_slots,
-                                           steps_per_iter, _stream(stream), ctypes.byref(h)))
+                                           _stream(stream), ctypes.byref(h)))
         self._h = h
         self._keep = {}
+        if steps_per_iter is not None:
+            self.set_steps_per_iter(steps_per_iter)
+
+    def set_steps_per_iter(self, steps_per_iter):
+        """Steps each admitted request advances per scheduling iteration."""
+        _check(load().fractal_serve_set_steps_per_iter(self._h, steps_per_iter))
 
     def submit(self, k, rule, steps, alpha=0.2, seed=0, h_init=None, h_out=None,
                t_arrival=-1.0):

@@ -119,9 +119,10 @@ static int clamp_r(int k, int r)
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
 // launches measured on MI355X, all on the register-march engine with omega
 // in the curve order split over the dies.  Level >= 15: automaton 64 x 64
-// tiles with sixteen steps per launch, heat 32 x 32 tiles with eight, both
-// with non-temporal stores.  Below: automaton 16 x 16 and heat 32 x 32
-// tiles, eight steps, plain stores (the state stays in the last-level cache).
+// tiles with sixteen steps per launch, heat 16 x 16 tiles with eight, both
+// with non-temporal stores.  Below: automaton and heat 16 x 16 tiles, eight
+// steps, plain stores (the state stays in the last-level cache); level 14
+// automaton: sixteen steps on stacks of two tiles.
 static fractal_tuning builtin_default(int k, int rule)
 {
     const bool big = k >= 15;
@@ -208,8 +209,11 @@ static int step_entry(int map, int k, int r, int rule, float alpha, void *b0, vo
     fractal_tuning t;
     if (r == FRACTAL_R_AUTO) {
         t = default_tuning(k, rule);
-        if (map == MAP_BB)
-            t = tuning_for_r(MAP_BB, k, rule, t.r);
+        // the tuned lambda launch fixes the tile size; the bounding box and
+        // the matrix-core map take their own launch form at that size (the
+        // matrix-core map has no march form)
+        if (map != MAP_LAMBDA)
+            t = tuning_for_r(map, k, rule, t.r);
     } else {
         t = tuning_for_r(map, k, rule, r);
     }
@@ -259,6 +263,17 @@ int fractal_lambda_map(int k, int r, uint32_t *d_xy, void *stream)
 int fractal_lambda_map_mfma(int k, int r, uint32_t *d_xy, void *stream)
 {
     return map_entry(k, r, d_xy, stream, true);
+}
+
+int fractal_lambda_map_tiles(int k, int r, int order, uint32_t *d_xy, void *stream)
+{
+    if (!d_xy)
+        return set_error(FRACTAL_E_INVAL, "null output buffer");
+    if (k < 0 || r < 0 || r > k || k - r > 20)
+        return set_error(FRACTAL_E_INVAL, "need 0 <= r <= k and k-r <= 20 (k=%d r=%d)", k, r);
+    if (order < FRACTAL_ORDER_NATURAL || order > FRACTAL_ORDER_CURVE_XCD)
+        return set_error(FRACTAL_E_INVAL, "unknown order %d", order);
+    return launch_lambda_tiles(k - r, order, d_xy, static_cast<hipStream_t>(stream));
 }
 
 int fractal_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf, void *stream)

@@ -5,8 +5,10 @@
 // instance j owns tile ids [tile_begin_j, tile_begin_j + 3^(k_j - r)); a tile
 // id is turned into (instance, local omega) with the per-instance offset
 // table and then into a tile by that instance's lambda.  Each launch slot is
-// one launch per class (of 1, 2, 4 or 8 steps); the launches of a
-// fractal_batch_step call are captured once into a HIP graph.
+// one launch per class (of 1, 2, 4, 8 or 16 steps); the launches of a
+// fractal_batch_step call are captured once into a HIP graph.  The device
+// table lives in a caller-owned workspace: the library allocates no device
+// memory here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,16 +23,25 @@
 
 namespace fractal {
 
-static int batch_grid_size()
+// Workgroups of `fn` (256 threads) the whole chip holds at once, a multiple
+// of the 8 dies; 0 if the runtime cannot say.
+static uint32_t resident_groups(const void *fn)
 {
-    static int grid = 0;
-    if (grid == 0) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = cus * 8; // resident workgroups per die-share of the chip
-    }
-    return grid;
+    static std::mutex mu;
+    static std::map<const void *, uint32_t> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end())
+        return it->second;
+    int dev = 0, cus = 0, per_cu = 0;
+    uint32_t g = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) == hipSuccess &&
+        cus > 0 && per_cu > 0)
+        g = (uint32_t)cus * (uint32_t)per_cu / 8u * 8u;
+    cache[fn] = g;
+    return g;
 }
 
 fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
@@ -41,7 +52,9 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
             t = tuning_for_r(MAP_LAMBDA, k, rule, forced->r);
         if (forced->threads == 64 || forced->threads == 256)
             t.threads = forced->threads;
-        t.flags = forced->flags;
+        // launch flags apply where any besides the persistent mode are given
+        if (forced->flags & ~FRACTAL_FLAG_PERSISTENT)
+            t.flags = forced->flags;
     }
     t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags;
     if (t.flags & (FRACTAL_FLAG_MARCH | kFuseFlags))
@@ -169,31 +182,40 @@ int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hi
                                  c.rule, c.r, list.T);
             const int bl = march_band_log(c.rule, c.r, list.T, total);
             const uint64_t waves = ((total << bl) + (uint64_t)P - 1) / (uint64_t)P;
-            const uint64_t grid = (waves + 3) / 4;
+            const uint64_t groups = (waves + 3) / 4;
+            if (groups > 0xFFFFFFFFull)
+                return set_error(FRACTAL_E_INVAL, "batch list of %llu tiles is too long",
+                                 (unsigned long long)total);
+            // persistent: as many workgroups as the chip holds, each walking
+            // several items (also where one item per workgroup would exceed
+            // the launch limit)
+            uint64_t grid = groups;
+            const uint32_t res = (persistent || groups > (1u << 24))
+                                     ? resident_groups((const void *)fn) : 0u;
+            if (res > 0 && res < grid)
+                grid = res;
+            if (grid > (1u << 24))
+                return set_error(FRACTAL_E_INVAL, "batch list of %llu tiles is too long",
+                                 (unsigned long long)total);
             hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), 0, s, tab, (int)active, total,
-                               bl, j);
+                               bl, j, (uint32_t)groups);
         } else {
+            // the LDS engine: one workgroup per tile (persistent applies to
+            // march classes only)
             const int flags = list.T > 1 ? c.flags : (c.flags & ~kFuseFlags);
-            TileFn tf = nullptr;
-            PersistFn pf = nullptr;
-            if (c.rule == FRACTAL_RULE_CA)
-                pick_batch_ca(c.r, c.threads, flags, &tf, &pf);
-            else
-                pick_batch_heat(c.r, c.threads, flags, &tf, &pf);
-            if (!tf || !pf)
+            TileFn tf = c.rule == FRACTAL_RULE_CA ? pick_batch_ca(c.r, c.threads, flags)
+                                                  : pick_batch_heat(c.r, c.threads, flags);
+            if (!tf)
                 return set_error(FRACTAL_E_INVAL, "no batch kernel for r=%d threads=%d flags=%d",
                                  c.r, c.threads, flags);
-            if (!persistent && total < 0x7FFFFFFFull) {
-                const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
-                const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
-                hipLaunchKernelGGL(tf, dim3(gx, gy), dim3(c.threads), 0, s, tab, (int)active,
-                                   (uint32_t)total, j);
-            } else {
-                const uint64_t grid = std::min<uint64_t>(
-                    total, (uint64_t)batch_grid_size() * (c.threads == 64 ? 4 : 1));
-                hipLaunchKernelGGL(pf, dim3((unsigned)grid), dim3(c.threads), 0, s, tab,
-                                   (int)active, total, j);
-            }
+            if (total >= 0x7FFFFFFFull)
+                return set_error(FRACTAL_E_INVAL,
+                                 "batch list of %llu tiles is too long for the LDS engine",
+                                 (unsigned long long)total);
+            const uint32_t gx = total < 65536u ? (uint32_t)total : 65536u;
+            const uint32_t gy = (uint32_t)((total + gx - 1) / gx);
+            hipLaunchKernelGGL(tf, dim3(gx, gy), dim3(c.threads), 0, s, tab, (int)active,
+                               (uint32_t)total, j);
         }
         int rc = hip_error(hipGetLastError(), "batch kernel launch");
         if (rc)
@@ -231,8 +253,27 @@ static void reap_pending()
 
 using namespace fractal;
 
+// Device table of a batch of `count` instances: one entry per list of its
+// launch class (at most one list per launch size), 256-byte granules.
+static size_t batch_table_bytes(int count)
+{
+    const size_t b = sizeof(BatchEntry) * kMaxListsPerItem * (size_t)count;
+    return (b + 255) / 256 * 256;
+}
+
+extern "C" int fractal_batch_workspace(int count, size_t *bytes)
+{
+    if (!bytes)
+        return set_error(FRACTAL_E_INVAL, "null output");
+    if (count < 0 || count > 65536)
+        return set_error(FRACTAL_E_INVAL, "instance count %d outside [0, 65536]", count);
+    *bytes = batch_table_bytes(count);
+    return FRACTAL_OK;
+}
+
 extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
-                                  const fractal_tuning *tuning, void *stream)
+                                  const fractal_tuning *tuning, void *d_work, size_t work_bytes,
+                                  void *stream)
 {
     if (count < 0 || count > 65536)
         return set_error(FRACTAL_E_INVAL, "instance count %d outside [0, 65536]", count);
@@ -240,6 +281,13 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         return FRACTAL_OK;
     if (!inst)
         return set_error(FRACTAL_E_INVAL, "null instance array");
+    if (!d_work)
+        return set_error(FRACTAL_E_INVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_work) % 16)
+        return set_error(FRACTAL_E_INVAL, "workspace must be 16-byte aligned");
+    if (work_bytes < batch_table_bytes(count))
+        return set_error(FRACTAL_E_INVAL, "workspace of %zu bytes, %zu needed", work_bytes,
+                         batch_table_bytes(count));
     if (tuning) {
         if (tuning->r != FRACTAL_R_AUTO && (tuning->r < 0 || tuning->r > kMaxR))
             return set_error(FRACTAL_E_INVAL, "tuning r=%d outside [0, %d]", tuning->r, kMaxR);
@@ -293,7 +341,7 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     BatchPlan plan;
     plan.build(items, host);
 
-    BatchEntry *d_table = nullptr;
+    BatchEntry *d_table = static_cast<BatchEntry *>(d_work);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -315,14 +363,9 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
             (void)hipGraphExecDestroy(exec);
         if (done)
             (void)hipEventDestroy(done);
-        if (d_table)
-            (void)hipFree(d_table);
         (void)hipHostFree(host);
         return code;
     };
-    if ((rc = hip_error(hipMallocAsync((void **)&d_table, sizeof(BatchEntry) * cap, s),
-                        "device table")))
-        return fail(rc);
     if ((rc = hip_error(hipMemcpyAsync(d_table, host, sizeof(BatchEntry) * plan.entries(),
                                        hipMemcpyHostToDevice, s),
                         "table copy")))
@@ -346,9 +389,6 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
     graph = nullptr;
     if ((rc = hip_error(hipGraphLaunch(exec, s), "graph launch")))
         return fail(rc);
-    if ((rc = hip_error(hipFreeAsync(d_table, s), "table free")))
-        return fail(rc);
-    d_table = nullptr;
     if ((rc = hip_error(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event")))
         return fail(rc);
     if ((rc = hip_error(hipEventRecord(done, s), "event record")))

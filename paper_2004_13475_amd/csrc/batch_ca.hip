@@ -1,11 +1,11 @@
-// batch_ca.hip -- batched step kernels for rule RULE_CA.
+// batch_ca.hip -- batched LDS-engine step kernels for rule RULE_CA.
 #include "batch_kernels.hpp"
 
 namespace fractal {
 
-void pick_batch_ca(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
+TileFn pick_batch_ca(int r, int threads, int flags)
 {
-    pick_batch_kernel<RULE_CA>(r, threads, flags, tf, pf);
+    return pick_batch_kernel<RULE_CA>(r, threads, flags);
 }
 
 } // namespace fractal

@@ -1,11 +1,11 @@
-// batch_heat.hip -- batched step kernels for rule RULE_HEAT.
+// batch_heat.hip -- batched LDS-engine step kernels for rule RULE_HEAT.
 #include "batch_kernels.hpp"
 
 namespace fractal {
 
-void pick_batch_heat(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
+TileFn pick_batch_heat(int r, int threads, int flags)
 {
-    pick_batch_kernel<RULE_HEAT>(r, threads, flags, tf, pf);
+    return pick_batch_kernel<RULE_HEAT>(r, threads, flags);
 }
 
 } // namespace fractal

@@ -1,6 +1,6 @@
-// batch_kernels.hpp -- kernels of the batched step (one workgroup per tile,
-// or persistent) and the table that picks an instantiation; each rule is
-// instantiated in its own translation unit.
+// batch_kernels.hpp -- the LDS-engine kernel of the batched step (one
+// workgroup per tile) and the table that picks an instantiation; each rule
+// is instantiated in its own translation unit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,46 +61,15 @@ __global__ __launch_bounds__(NT) void batch_tile_kernel(const BatchEntry *__rest
     batch_tile<RULE, R, NT, FL>(lds, e, (uint32_t)(w - e.tile_begin), local_step);
 }
 
-// Persistent form: workgroup b walks the contiguous tile ids
-// [b*per, (b+1)*per) in order, so tiles that are neighbours in the gasket's
-// self-similar order stay on one die and share its L2.
-template <int RULE, int R, int NT, int FL>
-__global__ __launch_bounds__(NT) void batch_persistent_kernel(
-    const BatchEntry *__restrict__ table, int count, uint64_t total, int local_step)
-{
-    __shared__ __align__(16) uint8_t lds[tile_lds_bytes<RULE, R, FL>()];
-    const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const uint64_t w0 = (uint64_t)blockIdx.x * per;
-    const uint64_t w1 = w0 + per < total ? w0 + per : total;
-    if (w0 >= w1)
-        return;
-    int j = find_instance(table, count, w0);
-    uint64_t next = j + 1 < count ? table[j + 1].tile_begin : ~0ull;
-    for (uint64_t w = w0; w < w1; ++w) {
-        while (w >= next) {
-            ++j;
-            next = j + 1 < count ? table[j + 1].tile_begin : ~0ull;
-        }
-        const BatchEntry e = table[j];
-        __syncthreads(); // the previous tile's LDS reads are done
-        batch_tile<RULE, R, NT, FL>(lds, e, (uint32_t)(w - e.tile_begin), local_step);
-    }
-}
-
-
 template <int RULE, int NT, int FL>
-static void pick_r(int r, TileFn *tf, PersistFn *pf)
+static TileFn pick_r(int r)
 {
-    *tf = nullptr;
-    *pf = nullptr;
     switch (r) {
 #define FRACTAL_BATCH_CASE(RR)                                                                     \
     case RR:                                                                                       \
-        if constexpr (!(fused_steps<FL>() > 1 && !Geom<RULE, RR>::FUSABLE) && !(NT == 256 && RR < 3)) { \
-            *tf = batch_tile_kernel<RULE, RR, NT, FL>;                                             \
-            *pf = batch_persistent_kernel<RULE, RR, NT, FL>;                                       \
-        }                                                                                          \
-        break;
+        if constexpr (!(fused_steps<FL>() > 1 && !Geom<RULE, RR>::FUSABLE) && !(NT == 256 && RR < 3)) \
+            return batch_tile_kernel<RULE, RR, NT, FL>;                                            \
+        return nullptr;
         FRACTAL_BATCH_CASE(0)
         FRACTAL_BATCH_CASE(1)
         FRACTAL_BATCH_CASE(2)
@@ -110,34 +79,29 @@ static void pick_r(int r, TileFn *tf, PersistFn *pf)
         FRACTAL_BATCH_CASE(6)
         FRACTAL_BATCH_CASE(7)
 #undef FRACTAL_BATCH_CASE
-    default: break;
+    default: return nullptr;
     }
 }
 
 template <int RULE, int FL>
-static void pick_threads(int r, int threads, TileFn *tf, PersistFn *pf)
+static TileFn pick_threads(int r, int threads)
 {
-    if (threads == 256)
-        pick_r<RULE, 256, FL>(r, tf, pf);
-    else
-        pick_r<RULE, 64, FL>(r, tf, pf);
+    return threads == 256 ? pick_r<RULE, 256, FL>(r) : pick_r<RULE, 64, FL>(r);
 }
 
 template <int RULE>
-static void pick_batch_kernel(int r, int threads, int flags, TileFn *tf, PersistFn *pf)
+static TileFn pick_batch_kernel(int r, int threads, int flags)
 {
     switch (flags) {
-    case 0: pick_threads<RULE, 0>(r, threads, tf, pf); break;
-    case 1: pick_threads<RULE, 1>(r, threads, tf, pf); break;
-    case 2: pick_threads<RULE, 2>(r, threads, tf, pf); break;
-    case 3: pick_threads<RULE, 3>(r, threads, tf, pf); break;
-    case 9: pick_threads<RULE, 9>(r, threads, tf, pf); break;
-    case 11: pick_threads<RULE, 11>(r, threads, tf, pf); break;
-    case 17: pick_threads<RULE, 17>(r, threads, tf, pf); break;
-    case 19: pick_threads<RULE, 19>(r, threads, tf, pf); break;
-    default:
-        *tf = nullptr;
-        *pf = nullptr;
+    case 0: return pick_threads<RULE, 0>(r, threads);
+    case 1: return pick_threads<RULE, 1>(r, threads);
+    case 2: return pick_threads<RULE, 2>(r, threads);
+    case 3: return pick_threads<RULE, 3>(r, threads);
+    case 9: return pick_threads<RULE, 9>(r, threads);
+    case 11: return pick_threads<RULE, 11>(r, threads);
+    case 17: return pick_threads<RULE, 17>(r, threads);
+    case 19: return pick_threads<RULE, 19>(r, threads);
+    default: return nullptr;
     }
 }
 

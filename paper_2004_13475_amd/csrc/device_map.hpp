@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/fractal.h"
+
 namespace fractal {
 
 struct TileXY {
@@ -71,6 +73,38 @@ __device__ __forceinline__ TileXY lambda_wave_curve(uint32_t L, int rb)
 {
     const uint32_t q = L / pow3_u32(lane_id());
     return ballot_assemble(q - 3u * (q / 3u), rb);
+}
+
+// lambda for one tile per lane, as the register-march kernels evaluate it
+// (their wavefronts hold several tiles, so each lane group needs its own
+// lambda): block coordinates of tile `id`, where base-3 digit mu-1 of the id
+// (CURVE orders) or of omega_x / omega_y for odd / even mu (NATURAL,
+// omega = (id mod gx, id div gx)) is beta_mu; bit mu-1 of x is [beta == 2]
+// and of y is [beta == 0] (the mirrored replica table).  rb <= 20.
+__device__ __forceinline__ TileXY lambda_lane(uint32_t id, int rb, int order)
+{
+    uint32_t a = id, b = 0u;
+    if (order == FRACTAL_ORDER_NATURAL) {
+        const uint32_t gx = pow3_u32((uint32_t)(rb + 1) / 2u);
+        b = id / gx;
+        a = id - b * gx;
+    }
+    uint32_t x = 0u, y = 0u;
+    for (int mu = 0; mu < rb; ++mu) {
+        uint32_t d;
+        if (order == FRACTAL_ORDER_NATURAL && (mu & 1)) {
+            const uint32_t q = b / 3u;
+            d = b - 3u * q;
+            b = q;
+        } else {
+            const uint32_t q = a / 3u;
+            d = a - 3u * q;
+            a = q;
+        }
+        x |= (uint32_t)(d == 2u) << mu;
+        y |= (uint32_t)(d == 0u) << mu;
+    }
+    return TileXY{x, y};
 }
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));

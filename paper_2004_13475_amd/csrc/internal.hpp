@@ -108,8 +108,9 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s);
 
-// lambda map kernels.
+// lambda map kernels: per wavefront (ballots or matrix core), and per lane.
 int launch_lambda_map(int k, int r, uint32_t *d_xy, bool mfma, hipStream_t s);
+int launch_lambda_tiles(int rb, int order, uint32_t *d_xy, hipStream_t s);
 
 // Seeded state fill.
 int launch_seed_fill(int k, int rule, uint32_t stream_id, void *d_buf,
@@ -194,7 +195,7 @@ uint64_t reduce_tree_words(uint64_t n0);
 int launch_reduce_tree(uint64_t *work, uint64_t n0, void *d_out, bool f64, hipStream_t s);
 
 // Batched march kernel for (rule, r, T steps, non-temporal stores).
-typedef void (*BatchMarchFn)(const BatchEntry *, int, uint64_t, int, int);
+typedef void (*BatchMarchFn)(const BatchEntry *, int, uint64_t, int, int, uint32_t);
 BatchMarchFn pick_batch_march_ca(int r, int T, bool nt);
 BatchMarchFn pick_batch_march_heat(int r, int T, bool nt);
 inline BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt)
@@ -203,12 +204,11 @@ inline BatchMarchFn pick_batch_march(int rule, int r, int T, bool nt)
                                    : pick_batch_march_heat(r, T, nt);
 }
 
-// Batched step kernels of one rule for (r, threads, flags): one workgroup
-// per tile (tf) and persistent (pf); nullptr if not instantiated.
+// Batched LDS-engine step kernel of one rule for (r, threads, flags): one
+// workgroup per tile; nullptr if not instantiated.
 typedef void (*TileFn)(const BatchEntry *, int, uint32_t, int);
-typedef void (*PersistFn)(const BatchEntry *, int, uint64_t, int);
-void pick_batch_ca(int r, int threads, int flags, TileFn *tf, PersistFn *pf);
-void pick_batch_heat(int r, int threads, int flags, TileFn *tf, PersistFn *pf);
+TileFn pick_batch_ca(int r, int threads, int flags);
+TileFn pick_batch_heat(int r, int threads, int flags);
 
 // Tile launch used for one batched instance: `forced` (may be NULL) overrides
 // the per-level cached or default tuning.

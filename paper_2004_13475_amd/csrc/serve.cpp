@@ -30,6 +30,11 @@
 
 namespace fractal {
 
+// Steps each admitted request advances per scheduling iteration until
+// fractal_serve_set_steps_per_iter changes it: the automaton's longest
+// launch (16 steps) then always fits.
+constexpr int kDefaultStepsPerIter = 16;
+
 static double now_s()
 {
     using namespace std::chrono;
@@ -175,6 +180,12 @@ class Server {
         return FRACTAL_OK;
     }
 
+    void set_steps_per_iter(int n)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        per_iter_ = n;
+    }
+
     int poll(uint64_t ticket, fractal_result *res)
     {
         if (!res)
@@ -302,7 +313,12 @@ class Server {
                                                          const std::pair<int, Slot> &b) {
                 return rem(a.second) > rem(b.second);
             });
-            const int c = std::min(per_iter_, rem(act[0].second));
+            int per_iter;
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                per_iter = per_iter_;
+            }
+            const int c = std::min(per_iter, rem(act[0].second));
             if (c > 0) {
                 // the table buffer of two iterations ago must be consumed
                 (void)hipEventSynchronize(table_ev_[parity]);
@@ -489,8 +505,8 @@ extern "C" {
 
 double fractal_now(void) { return now_s(); }
 
-int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots, int steps_per_iter,
-                         void *stream, void **server)
+int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots, void *stream,
+                         void **server)
 {
     if (!d_arena || !server)
         return set_error(FRACTAL_E_INVAL, "null arena or server pointer");
@@ -498,10 +514,8 @@ int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots, int s
         return set_error(FRACTAL_E_INVAL, "arena must be 256-byte aligned");
     if (max_slots < 1 || max_slots > 4096)
         return set_error(FRACTAL_E_INVAL, "max_slots=%d outside [1, 4096]", max_slots);
-    if (steps_per_iter < 1)
-        return set_error(FRACTAL_E_INVAL, "steps_per_iter must be >= 1");
     Server *s = new Server(static_cast<uint8_t *>(d_arena), arena_bytes, max_slots,
-                           steps_per_iter, static_cast<hipStream_t>(stream));
+                           kDefaultStepsPerIter, static_cast<hipStream_t>(stream));
     int rc = s->init();
     if (rc) {
         s->shutdown();
@@ -509,6 +523,16 @@ int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots, int s
         return rc;
     }
     *server = s;
+    return FRACTAL_OK;
+}
+
+int fractal_serve_set_steps_per_iter(void *server, int steps_per_iter)
+{
+    if (!server)
+        return set_error(FRACTAL_E_INVAL, "null server");
+    if (steps_per_iter < 1 || steps_per_iter > 1 << 20)
+        return set_error(FRACTAL_E_INVAL, "steps_per_iter=%d outside [1, 2^20]", steps_per_iter);
+    static_cast<Server *>(server)->set_steps_per_iter(steps_per_iter);
     return FRACTAL_OK;
 }
 

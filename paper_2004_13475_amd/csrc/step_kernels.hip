@@ -48,6 +48,30 @@ int launch_lambda_map(int k, int r, uint32_t *d_xy, bool mfma, hipStream_t s)
     return hip_error(hipGetLastError(), "lambda map launch");
 }
 
+// The per-lane form of the map (lambda_lane, as the register-march kernels
+// evaluate it): thread i writes the block of tile id i in dispatch order
+// `order`.
+__global__ __launch_bounds__(256) void lambda_tiles_kernel(uint32_t *xy, int rb, int order,
+                                                           uint32_t total)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const TileXY t = lambda_lane(i, rb, order);
+        xy[2 * (uint64_t)i + 0] = t.x;
+        xy[2 * (uint64_t)i + 1] = t.y;
+    }
+}
+
+int launch_lambda_tiles(int rb, int order, uint32_t *d_xy, hipStream_t s)
+{
+    const uint64_t total = pow3_u64(rb);
+    const uint64_t want = (total + 255) / 256;
+    const unsigned grid = (unsigned)(want < (1u << 20) ? want : (1u << 20));
+    hipLaunchKernelGGL(lambda_tiles_kernel, dim3(grid), dim3(256), 0, s, d_xy, rb, order,
+                       (uint32_t)total);
+    return hip_error(hipGetLastError(), "lambda tiles launch");
+}
+
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s)
 {

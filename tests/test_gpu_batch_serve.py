@@ -44,8 +44,15 @@ MARCH = F.FLAG_MARCH | F.FLAG_SEGMENTS
                                     (4, 256, 0, MARCH | F.FLAG_FUSE2),
                                     (7, 64, 0, MARCH),
                                     (6, 0, 0, MARCH | F.FLAG_FUSE8 | F.FLAG_PERSISTENT),
-                                    (5, 0, 2, MARCH | F.FLAG_FUSE16)])
+                                    (5, 0, 2, MARCH | F.FLAG_FUSE16),
+                                    (F.R_AUTO, 0, 0, F.FLAG_PERSISTENT),
+                                    (F.R_AUTO, 0, 0, MARCH | F.FLAG_FUSE16 | F.FLAG_PERSISTENT)])
 def test_batch_alone_equals_in_mix(tuning):
+    """Every instance of a mixed batch (levels 1..11, both rules, 0..37
+    steps) gives the bits of its own plain lambda step call, for per-level
+    defaults, explicit tile sizes and flags, both engines and the persistent
+    march grid; small ones also match the oracle.  The workspace is a
+    torch-owned device buffer."""
     torch = torch_dev()
     specs = _mix(40, 3, 1, 11, 37)
     inst, inits = [], []
@@ -53,7 +60,8 @@ def test_batch_alone_equals_in_mix(tuning):
         init = fi.window_values(k, rule, sid)
         inits.append(init)
         inst.append((k, rule, steps, ALPHA, to_device(init), zeros_state(k, rule)))
-    F.batch_step(inst, tuning=tuning)
+    work = torch.empty(F.batch_workspace(len(inst)), dtype=torch.uint8, device="cuda")
+    F.batch_step(inst, tuning=tuning, work=work)
     _sync()
     for (k, rule, steps, sid), init, (_, _, _, _, b0, b1) in zip(specs, inits, inst):
         got = b0 if steps % 2 == 0 else b1
@@ -76,7 +84,7 @@ def test_batch_level8_to_13_many_steps(persistent):
         b0, b1 = zeros_state(k, rule), zeros_state(k, rule)
         F.seed_fill(k, rule, 50 + j, b0)
         inst.append((k, rule, 120, ALPHA, b0, b1))
-    F.batch_step(inst, tuning=(5, 64, 2, F.FLAG_PERSISTENT) if persistent else None)
+    F.batch_step(inst, tuning=(F.R_AUTO, 0, 0, F.FLAG_PERSISTENT) if persistent else None)
     _sync()
     for j, (k, rule) in enumerate(pairs):
         a0, a1 = zeros_state(k, rule), zeros_state(k, rule)
@@ -85,6 +93,25 @@ def test_batch_level8_to_13_many_steps(persistent):
         _sync()
         assert torch.equal(inst[j][4].view(torch.uint8), a0.view(torch.uint8)), (j, k, rule)
         del a0, a1
+
+
+def test_batch_workspace_size_and_short_workspace():
+    """The workspace holds the per-instance offset table (5 entries of 48
+    bytes per instance, rounded to 256 bytes); a short one is refused before
+    anything is enqueued."""
+    torch = torch_dev()
+    assert F.batch_workspace(0) == 0
+    assert F.batch_workspace(1) == 256
+    assert F.batch_workspace(40) == (40 * 5 * 48 + 255) // 256 * 256
+    k, rule = 6, fi.RULE_CA
+    init = fi.window_values(k, rule, 2)
+    b0, b1 = to_device(init), zeros_state(k, rule)
+    short = torch.empty(128, dtype=torch.uint8, device="cuda")
+    with pytest.raises(F.FractalError) as e:
+        F.batch_step([(k, rule, 3, ALPHA, b0, b1)], work=short)
+    assert e.value.code == F.E_INVAL
+    _sync()
+    assert torch.equal(b0.cpu(), torch.from_numpy(init)), "a refused call changed the state"
 
 
 def test_batch_repeated_calls_reuse_state():
@@ -182,6 +209,11 @@ def test_serve_fifo_under_memory_pressure_and_host_init():
 def test_serve_rejections():
     arena, nbytes = _arena(0.01)
     with F.Server(arena, nbytes, max_slots=2) as srv:
+        for bad in (0, -3):
+            with pytest.raises(F.FractalError) as e:
+                srv.set_steps_per_iter(bad)
+            assert e.value.code == F.E_INVAL
+        srv.set_steps_per_iter(5)
         with pytest.raises(F.FractalError) as e:
             srv.submit(14, 1, 5)  # 2 GiB footprint > 10 MiB arena
         assert e.value.code == F.E_NOMEM

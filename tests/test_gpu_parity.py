@@ -444,3 +444,167 @@ def test_max_block_level_k16(rule):
 def test_heat_error_metric_sane():
     a = np.array([1.0, 2.0, 0.0], dtype=np.float32)
     assert heat_err(a, a.astype(np.float64)) == 0.0
+
+
+# ------------------------------------------------ per-lane map, all orders
+@pytest.mark.parametrize("order", [F.ORDER_NATURAL, F.ORDER_CURVE, F.ORDER_CURVE_XCD])
+def test_lambda_lane_map_matches_oracle(order):
+    """The map as the register-march kernels evaluate it (one tile per lane,
+    a digit loop per id) against the oracle for every block level up to 15:
+    the natural order equals Theorem 1's lambda on omega = (i mod gx,
+    i div gx); the curve orders are the bijection whose inverse is the
+    oracle's compact index (base-3 digit mu-1 of the id is beta_mu)."""
+    torch = torch_dev()
+    for rb in range(0, 16):
+        for r in ((0, 2) if rb <= 12 else (1,)):
+            k = rb + r
+            total = 3 ** rb
+            out = torch.zeros(2 * total, dtype=torch.int32, device="cuda")
+            F.lambda_map_tiles(k, r, order, out)
+            _sync()
+            got = out.cpu().numpy().view(np.uint32).reshape(total, 2).astype(np.int64)
+            if order == F.ORDER_NATURAL:
+                want = oracle.lambda_grid(rb).reshape(total, 2).astype(np.int64)
+                assert np.array_equal(got, want), f"rb={rb}"
+            else:
+                assert np.all((got[:, 0] & got[:, 1]) == 0), f"rb={rb}: empty block"
+                ids = oracle.compact_index(rb, 0, got[:, 0], got[:, 1])
+                assert np.array_equal(ids, np.arange(total)), f"rb={rb}: not the curve order"
+
+
+def test_lambda_lane_map_rejects_bad_arguments():
+    torch = torch_dev()
+    out = torch.zeros(16, dtype=torch.int32, device="cuda")
+    for (k, r, order) in ((22, 1, 0), (3, 4, 0), (5, 1, 3)):
+        with pytest.raises(F.FractalError) as e:
+            F.lambda_map_tiles(k, r, order, out)
+        assert e.value.code == F.E_INVAL
+
+
+# ------------------------------------------- matrix-core map, auto tiles
+@pytest.mark.parametrize("rule", RULES)
+def test_lambda_step_mfma_auto_tile_bit_identical(rule):
+    """The matrix-core lambda step at FRACTAL_R_AUTO takes the tuned tile
+    size with its own (LDS-engine) launch and gives the bits of the default
+    lambda step."""
+    torch = torch_dev()
+    for k in (10, 12):
+        init = fi.window_values(k, rule, 31 + k)
+        for steps in (1, 9, 20):
+            a0, a1 = to_device(init), zeros_state(k, rule)
+            F.lambda_step_mfma(k, F.R_AUTO, rule, ALPHA, a0, a1, steps)
+            b0, b1 = to_device(init), zeros_state(k, rule)
+            F.lambda_step(k, F.R_AUTO, rule, ALPHA, b0, b1, steps)
+            _sync()
+            fa = a0 if steps % 2 == 0 else a1
+            fb = b0 if steps % 2 == 0 else b1
+            assert torch.equal(fa.view(torch.uint8), fb.view(torch.uint8)), (k, steps)
+
+
+# ------------------------------------------- whole arrays at full size
+def _off_gasket_zero(k, buf):
+    """Every cell off the gasket holds 0 (bit pattern), checked on the
+    device row band by row band."""
+    torch = torch_dev()
+    n = 1 << k
+    xs = torch.arange(n, device="cuda", dtype=torch.int64)
+    step = max(1, (1 << 24) // n)
+    for y0 in range(0, n, step):
+        ys = torch.arange(y0, min(n, y0 + step), device="cuda", dtype=torch.int64)
+        off = (ys[:, None] & xs[None, :]) != 0
+        band = buf[y0:y0 + ys.numel()].view(torch.uint8 if buf.dtype == torch.uint8
+                                           else torch.int32)
+        if bool((band[off] != 0).any()):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_full_size_k14_whole_array(rule):
+    """Level 14 (n = 16384, 4,782,969 cells) at the default launch the
+    benchmark uses, against the oracle over the WHOLE array: the automaton
+    after every step t = 1..32 (the transient and the entry into its period-6
+    attractor) and at t = 100; heat at t = 1, 10, 100, 200; every off-gasket
+    cell 0 at each checkpoint."""
+    k = 14
+    torch = torch_dev()
+    init = fi.full_state(k, rule, 9)
+    cur, other = to_device(init), zeros_state(k, rule)
+    ref = init if rule == fi.RULE_CA else init.astype(np.float64)
+    del init
+    checkpoints = list(range(1, 33)) + [100] if rule == fi.RULE_CA else [1, 10, 100, 200]
+    t = 0
+    for target in checkpoints:
+        dt = target - t
+        F.lambda_step(k, F.R_AUTO, rule, ALPHA, cur, other, dt)
+        if dt % 2 == 1:
+            cur, other = other, cur
+        ref = oracle_steps(k, rule, ref, dt)
+        _sync()
+        assert_match(k, rule, cur.cpu().numpy(), ref, f"k14 whole array t={target}")
+        assert _off_gasket_zero(k, cur), f"k14 t={target}: off-gasket cell not 0"
+        t = target
+    del torch
+
+
+def _bb_lds(k, rule, b0, b1, steps):
+    """The structurally different reference launch: bounding-box map, LDS
+    engine, one step per launch, 32 x 32 tiles."""
+    F.step_tuned(F.MAP_BB, k, rule, ALPHA, b0, b1, steps, 5, 256, F.ORDER_NATURAL,
+                 F.FLAG_SEGMENTS)
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_full_size_k16_whole_array_lambda_equals_bb(rule):
+    """Level 16 (n = 65536, 43,046,721 cells; 17 GB per float32 buffer):
+    the default lambda launch (register march, lambda per lane, die-aware
+    curve order, non-temporal stores) and the bounding-box LDS launch one
+    step at a time give the same bits over the whole array at t = 1, 2, 16
+    and 200; the off-gasket cells stay 0."""
+    k = 16
+    torch = torch_dev()
+    lam = [zeros_state(k, rule), zeros_state(k, rule)]
+    bb = [zeros_state(k, rule), zeros_state(k, rule)]
+    F.seed_fill(k, rule, 21, lam[0])
+    F.seed_fill(k, rule, 21, bb[0])
+    t = 0
+    for target in (1, 2, 16, 200):
+        dt = target - t
+        F.lambda_step(k, F.R_AUTO, rule, ALPHA, lam[0], lam[1], dt)
+        _bb_lds(k, rule, bb[0], bb[1], dt)
+        if dt % 2 == 1:
+            lam.reverse()
+            bb.reverse()
+        _sync()
+        assert torch.equal(lam[0].view(torch.uint8), bb[0].view(torch.uint8)), f"t={target}"
+        t = target
+    assert _off_gasket_zero(k, lam[0])
+    del lam, bb
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_full_size_k16_full_width_bands(rule):
+    """Level 16, default launch, 200 steps, against the oracle on full-width
+    bands of 48 rows: across the middle of the array (row 32768 splits the
+    gasket's top-level replicas, where every tile stack class and every
+    die's share of the curve order meet) and across row 49152."""
+    k = 16
+    n = 1 << k
+    steps = 200
+    torch = torch_dev()
+    b0, b1 = zeros_state(k, rule), zeros_state(k, rule)
+    F.seed_fill(k, rule, 4, b0)
+    F.lambda_step(k, F.R_AUTO, rule, ALPHA, b0, b1, steps)
+    _sync()
+    for cy in (32768 - 24, 49152 - 24):
+        y0, h = cy - steps, 48 + 2 * steps
+        win = fi.window_values(k, rule, 4, 0, y0, n, h)
+        ref = oracle_steps(k, rule, win if rule == fi.RULE_CA else win.astype(np.float64),
+                           steps, 0, y0)
+        rs, cs = oracle.valid_interior(k, 0, y0, n, h, steps)
+        assert (rs.stop - rs.start, cs.stop - cs.start) == (48, n)
+        got = b0[y0 + rs.start:y0 + rs.stop].cpu().numpy()
+        assert_match(k, rule, got, ref[rs, cs], f"k16 band rows {cy}..{cy + 47}")
+    del b0, b1
+    torch.cuda.empty_cache()

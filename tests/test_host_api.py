@@ -110,20 +110,74 @@ def test_tuning_defaults_and_validation():
             F.step_tuned(1, 10, 1, 0.2, FAKE0, FAKE1, 1, 4, 256, 2, fl, stream=0)
 
 
+FAKEW = 0x20000000  # a fake workspace address
+
+
 def test_batch_validation():
+    w = dict(work=FAKEW, work_bytes=1 << 20, stream=0)
     with pytest.raises(F.FractalError):
-        F.batch_step([(17, 0, 5, 0.2, FAKE0, FAKE1)], stream=0)
+        F.batch_step([(17, 0, 5, 0.2, FAKE0, FAKE1)], **w)
     with pytest.raises(F.FractalError):  # two instances share a buffer
         F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1),
-                      (10, 0, 5, 0.2, FAKE1, FAKE1 + (1 << 22))], stream=0)
+                      (10, 0, 5, 0.2, FAKE1, FAKE1 + (1 << 22))], **w)
     with pytest.raises(F.FractalError):  # unknown flag bits are refused
-        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 8), stream=0)
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 64, 2, 8), **w)
     with pytest.raises(F.FractalError):  # bad thread count
-        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 128, 2, 0), stream=0)
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], tuning=(4, 128, 2, 0), **w)
+    with pytest.raises(F.FractalError) as e:  # short workspace
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], work=FAKEW, work_bytes=16, stream=0)
+    assert "workspace" in str(e.value)
+    with pytest.raises(F.FractalError):  # null workspace
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], work=0, work_bytes=1 << 20, stream=0)
+    with pytest.raises(F.FractalError):  # misaligned workspace
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], work=FAKEW + 8, work_bytes=1 << 20,
+                     stream=0)
+    with pytest.raises(ValueError):  # a raw workspace address needs its size
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], work=FAKEW, stream=0)
+    with pytest.raises(ValueError):  # a raw stream needs an explicit workspace
+        F.batch_step([(10, 0, 5, 0.2, FAKE0, FAKE1)], stream=0)
     # stack flags are accepted by batches (and ignored there)
-    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], tuning=(4, 256, 2, 33 | 64 | 256), stream=0)
-    F.batch_step([], stream=0)
-    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], stream=0)  # no steps: no-op
+    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], tuning=(4, 256, 2, 33 | 64 | 256), **w)
+    F.batch_step([], **w)
+    F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], **w)  # no steps: no-op
+    assert F.batch_workspace(0) == 0 and F.batch_workspace(1) == 256
+    assert F.batch_workspace(65536) == 65536 * 5 * 48
+    with pytest.raises(F.FractalError):
+        F.batch_workspace(65537)
+
+
+def _header_prototype(name):
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"\b" + name + r"\s*\(([^)]*)\)", txt)
+    assert m, name
+    return [a.strip() for a in m.group(1).split(",")]
+
+
+def test_boundary_signatures():
+    """The serving and batch calls take the arguments the boundary names:
+    serve_create(arena, bytes, slots, stream, server) with steps per
+    iteration a setter of its own, and batch_step with a caller workspace."""
+    create = _header_prototype("fractal_serve_create")
+    assert [a.split()[-1].lstrip("*") for a in create] == \
+        ["d_arena", "arena_bytes", "max_slots", "stream", "server"]
+    setter = _header_prototype("fractal_serve_set_steps_per_iter")
+    assert [a.split()[-1].lstrip("*") for a in setter] == ["server", "steps_per_iter"]
+    batch = _header_prototype("fractal_batch_step")
+    assert [a.split()[-1].lstrip("*") for a in batch] == \
+        ["inst", "count", "tuning", "d_work", "work_bytes", "stream"]
+    assert [a.split()[-1].lstrip("*") for a in _header_prototype("fractal_batch_workspace")] == \
+        ["count", "bytes"]
+
+
+def test_reduce_raw_workspace_needs_size():
+    with pytest.raises(ValueError):
+        F.reduce(0, 10, 4, 0, FAKE0, FAKEW, FAKE1, stream=0)
+    with pytest.raises(F.FractalError) as e:  # the library sees the short size
+        F.reduce(0, 10, 4, 0, FAKE0, FAKEW, FAKE1, stream=0, work_bytes=8)
+    assert "workspace" in str(e.value)
+    f = F.nbb_builtin(F.NBB_CARPET)
+    with pytest.raises(ValueError):
+        F.nbb_reduce(f, 0, 4, 1, FAKE0, FAKEW, FAKE1, stream=0)
 
 
 def test_serving_scheduler_unit(tmp_path):
