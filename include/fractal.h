@@ -444,6 +444,25 @@ int fractal_serve_submit(void *server, const fractal_request *rq,
  * unknown ticket. */
 int fractal_serve_poll(void *server, uint64_t ticket, fractal_result *res);
 
+/* Latency and throughput of a server's requests so far.  Latency is
+ * t_done - t_arrival of each request that completed with FRACTAL_OK;
+ * percentiles are nearest-rank over those requests. */
+typedef struct fractal_serve_report {
+    uint64_t submitted;  /* requests accepted by fractal_serve_submit       */
+    uint64_t completed;  /* finished with FRACTAL_OK                         */
+    uint64_t failed;     /* finished with an error status                    */
+    uint64_t pending;    /* queued, active or retiring                       */
+    uint64_t iterations; /* scheduling iterations run                        */
+    double p50_latency;  /* seconds                                          */
+    double p99_latency;
+    double mean_latency;
+    double cell_updates; /* sum over completed requests of 3^k * steps       */
+    double t_first_arrival; /* earliest arrival stamp of a completed request */
+    double t_last_done;     /* latest completion stamp                        */
+} fractal_serve_report;
+
+int fractal_serve_stats(void *server, fractal_serve_report *out);
+
 /* Stop the server thread after the queued work has drained and free its
  * host state.  Outstanding tickets are completed first. */
 int fractal_serve_destroy(void *server);

@@ -35,7 +35,7 @@ EXPORTED = [
     "fractal_nbb_single_write", "fractal_nbb_reduce_workspace", "fractal_nbb_reduce",
     "fractal_nbb_ca_step",
     "fractal_now", "fractal_serve_create", "fractal_serve_set_steps_per_iter", "fractal_serve_submit",
-    "fractal_serve_poll", "fractal_serve_destroy", "fractal_last_error",
+    "fractal_serve_poll", "fractal_serve_stats", "fractal_serve_destroy", "fractal_last_error",
 ]
 
 
@@ -78,6 +78,18 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("checksum", ctypes.c_uint64)]
+
+
+class ServeReport(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("iterations", ctypes.c_uint64), ("p50_latency", ctypes.c_double),
+                ("p99_latency", ctypes.c_double), ("mean_latency", ctypes.c_double),
+                ("cell_updates", ctypes.c_double), ("t_first_arrival", ctypes.c_double),
+                ("t_last_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -130,6 +142,7 @@ def load():
         "fractal_serve_set_steps_per_iter": ([vp, i], i),
         "fractal_serve_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], i),
         "fractal_serve_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(Result)], i),
+        "fractal_serve_stats": ([vp, ctypes.POINTER(ServeReport)], i),
         "fractal_serve_destroy": ([vp], i),
         "fractal_last_error": ([], ctypes.c_char_p),
     }
@@ -414,6 +427,13 @@ class Server:
         _check(rc)
         self._keep.pop(ticket, None)
         return (res.status, res.t_arrival, res.t_admit, res.t_done, res.checksum)
+
+    def stats(self):
+        """Latency (p50, p99, mean of done minus arrival) and throughput of
+        the requests completed so far, as a dict."""
+        rep = ServeReport()
+        _check(load().fractal_serve_stats(self._h, ctypes.byref(rep)))
+        return rep.as_dict()
 
     def close(self):
         if self._h is not None and self._h.value:

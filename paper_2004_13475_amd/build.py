@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -33,15 +34,27 @@ SOURCES = ["api.cpp", "step_kernels.hip", "step_lambda.hip", "step_bb.hip", "ste
            "serve.cpp"]
 
 
+def _local_deps(path: str, seen: set) -> set:
+    """The file and every project header it includes (quoted includes,
+    followed recursively)."""
+    path = os.path.normpath(path)
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path, encoding="utf-8") as fh:
+        for line in fh:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                _local_deps(os.path.join(os.path.dirname(path), m.group(1)), seen)
+    return seen
+
+
 def _up_to_date(src: str, obj: str) -> bool:
-    """The object is newer than its source and every header it may include."""
+    """The object is newer than its source and every header it includes."""
     if not os.path.exists(obj):
         return False
-    deps = [os.path.join(CSRC, src)]
-    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
-    deps.append(os.path.join(HERE, "..", "include", "fractal.h"))
     t = os.path.getmtime(obj)
-    return all(os.path.getmtime(d) < t for d in deps)
+    return all(os.path.getmtime(d) < t for d in _local_deps(os.path.join(CSRC, src), set()))
 
 
 def _compile(src: str, incremental: bool = False) -> str:

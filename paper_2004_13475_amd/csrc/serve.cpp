@@ -1,28 +1,22 @@
 // serve.cpp -- request server: continuous batching of gasket simulations
 // resident in a caller-provided device arena.
 //
-// A scheduler thread admits queued requests first come first served when a
-// slot and arena space are free, initialises their state on the device (on
-// a stream of its own, so that the memory-bound clear and seed of new
-// requests overlap the compute-bound steps of the running ones; the step
-// stream waits for it only before the iteration that first uses them),
-// and then repeatedly enqueues one iteration: steps_per_iter steps of every
-// active slot, as the batched plan's fused launches (slots with fewer
-// remaining steps drop out of the later launches of the iteration).  Requests that
-// arrive meanwhile join the next iteration.  A finished slot leaves the table
-// at once; a retire thread waits for its last step, computes nothing on the
-// host, copies the final state (if asked) and the checksum back, stamps the
-// result and returns the arena range.
+// The scheduling (tickets, FIFO admission by arena space and slot,
+// iterations, retirement, statistics) is ServeCore in serve_sched.hpp; this
+// file is its device side and its two threads.  The executor initialises
+// admitted requests on a stream of its own, so that the memory-bound clear
+// and seed of new requests overlap the compute-bound steps of the running
+// ones (the step stream waits for it only before the iteration that first
+// uses them), enqueues each iteration as the batched plan's fused launches
+// over every active slot, and retires a finished slot by a checksum on the
+// device, then a copy of the final state and the checksum to the host.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -41,92 +35,27 @@ static double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-namespace {
-
-enum TicketState { QUEUED, ACTIVE, RETIRING, DONE };
-
-struct Ticket {
-    fractal_request rq;
-    fractal_result res;
-    TicketState state;
-    size_t bytes; // arena footprint (both buffers)
-};
-
-struct Slot {
-    bool busy = false;
-    uint64_t ticket = 0;
-    size_t offset = 0;
-    int k = 0, rule = 0, steps = 0, done = 0;
-    fractal_tuning tuning = {0, 64, 0, 0};
-    float alpha = 0.0f;
-    uint8_t *buf0 = nullptr, *buf1 = nullptr;
-};
-
-struct RetireJob {
-    uint64_t ticket;
-    int slot;
-    hipEvent_t ready;        // last step and checksum of this slot done
-    const uint8_t *final_buf;
-    size_t state_bytes;
-};
-
-} // namespace
-
-class Server {
+class SteadyClock : public ServeClock {
   public:
-    Server(uint8_t *arena, size_t bytes, int max_slots, int per_iter, hipStream_t s)
-        : arena_(arena), arena_bytes_(bytes), max_slots_(max_slots), per_iter_(per_iter),
-          stream_(s)
-    {
-    }
+    double now() override { return now_s(); }
+};
 
-    int init()
+// The arena starts with a header: two device tables (the iteration being
+// enqueued and the one before it may still be read) and one checksum per
+// slot; request states follow at state_base_.
+class HipExecutor : public ServeExecutor {
+  public:
+    HipExecutor(uint8_t *arena, size_t bytes, int max_slots, hipStream_t s)
+        : arena_(arena), arena_bytes_(bytes), max_slots_(max_slots), stream_(s)
     {
-        int dev = 0;
-        int rc = hip_error(hipGetDevice(&dev), "get device");
-        if (rc)
-            return rc;
-        device_ = dev;
-        // header of the arena: two device tables (double-buffered) and the
-        // per-slot checksums; the rest holds request states
-        const size_t table_bytes = sizeof(BatchEntry) * kMaxListsPerItem * (size_t)(max_slots_ + 1);
+        table_bytes_ = sizeof(BatchEntry) * kMaxListsPerItem * (size_t)(max_slots + 1);
         table_off_[0] = 0;
-        table_off_[1] = align(table_bytes);
-        sums_off_ = table_off_[1] + align(table_bytes);
-        const size_t header = align(sums_off_ + sizeof(unsigned long long) * max_slots_);
-        if (arena_bytes_ <= header)
-            return set_error(FRACTAL_E_NOMEM, "arena of %zu bytes is smaller than the %zu-byte header",
-                             arena_bytes_, header);
-        state_base_ = header;
-        alloc_.reset(arena_bytes_ - header, 256);
-        slots_.assign(max_slots_, Slot());
-        slot_free_.assign(max_slots_, true);
-        for (int i = 0; i < 2; ++i) {
-            if ((rc = hip_error(hipHostMalloc((void **)&host_table_[i], table_bytes), "pinned table")))
-                return rc;
-            if ((rc = hip_error(hipEventCreateWithFlags(&table_ev_[i], hipEventDisableTiming),
-                                "event")))
-                return rc;
-            if ((rc = hip_error(hipEventRecord(table_ev_[i], stream_), "event record")))
-                return rc;
-        }
-        if ((rc = hip_error(hipHostMalloc((void **)&host_sums_, sizeof(unsigned long long) * max_slots_),
-                            "pinned sums")))
-            return rc;
-        if ((rc = hip_error(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking),
-                            "copy stream")))
-            return rc;
-        if ((rc = hip_error(hipStreamCreateWithFlags(&init_stream_, hipStreamNonBlocking),
-                            "init stream")))
-            return rc;
-        if ((rc = hip_error(hipEventCreateWithFlags(&init_ev_, hipEventDisableTiming), "event")))
-            return rc;
-        worker_ = std::thread([this] { run(); });
-        retirer_ = std::thread([this] { retire_loop(); });
-        return FRACTAL_OK;
+        table_off_[1] = align(table_bytes_);
+        sums_off_ = table_off_[1] + align(table_bytes_);
+        state_base_ = align(sums_off_ + sizeof(unsigned long long) * (size_t)max_slots);
     }
 
-    ~Server()
+    ~HipExecutor() override
     {
         for (int i = 0; i < 2; ++i) {
             if (host_table_[i])
@@ -144,356 +73,221 @@ class Server {
             (void)hipEventDestroy(init_ev_);
     }
 
-    int submit(const fractal_request *rq, uint64_t *ticket)
+    int init()
     {
-        if (!rq || !ticket)
-            return set_error(FRACTAL_E_INVAL, "null request or ticket pointer");
-        if (rq->k < 0 || rq->k > kMaxStepLevel)
-            return set_error(FRACTAL_E_INVAL, "level k=%d outside [0, %d]", rq->k, kMaxStepLevel);
-        if (rq->rule != FRACTAL_RULE_CA && rq->rule != FRACTAL_RULE_HEAT)
-            return set_error(FRACTAL_E_INVAL, "unknown rule %d", rq->rule);
-        if (rq->steps < 0)
-            return set_error(FRACTAL_E_INVAL, "negative step count %d", rq->steps);
-        if (rq->rule == FRACTAL_RULE_HEAT &&
-            !(rq->alpha > 0.0f && rq->alpha <= 0.25f)) // also rejects NaN
-            return set_error(FRACTAL_E_INVAL, "heat coefficient alpha=%g outside (0, 0.25]",
-                             (double)rq->alpha);
-        const size_t one = align(state_bytes(rq->k, rq->rule));
-        const size_t bytes = 2 * one;
-        if (!alloc_.fits_ever(bytes))
-            return set_error(FRACTAL_E_NOMEM, "request needs %zu bytes, arena holds %zu", bytes,
-                             alloc_.capacity());
-        std::lock_guard<std::mutex> lk(mu_);
-        if (stopping_)
-            return set_error(FRACTAL_E_INVAL, "server is shutting down");
-        const uint64_t id = ++next_ticket_;
-        Ticket t;
-        t.rq = *rq;
-        std::memset(&t.res, 0, sizeof t.res);
-        t.res.t_arrival = rq->t_arrival >= 0.0 ? rq->t_arrival : now_s();
-        t.state = QUEUED;
-        t.bytes = bytes;
-        tickets_[id] = t;
-        queue_.push(id, bytes);
-        *ticket = id;
-        cv_.notify_all();
+        if (arena_bytes_ <= state_base_)
+            return set_error(FRACTAL_E_NOMEM,
+                             "arena of %zu bytes is smaller than the %zu-byte header", arena_bytes_,
+                             state_base_);
+        int dev = 0;
+        int rc = hip_error(hipGetDevice(&dev), "get device");
+        if (rc)
+            return rc;
+        device_ = dev;
+        for (int i = 0; i < 2; ++i) {
+            if ((rc = hip_error(hipHostMalloc((void **)&host_table_[i], table_bytes_),
+                                "pinned table")))
+                return rc;
+            if ((rc = hip_error(hipEventCreateWithFlags(&table_ev_[i], hipEventDisableTiming),
+                                "event")))
+                return rc;
+            if ((rc = hip_error(hipEventRecord(table_ev_[i], stream_), "event record")))
+                return rc;
+        }
+        if ((rc = hip_error(hipHostMalloc((void **)&host_sums_,
+                                          sizeof(unsigned long long) * (size_t)max_slots_),
+                            "pinned sums")))
+            return rc;
+        if ((rc = hip_error(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking),
+                            "copy stream")))
+            return rc;
+        if ((rc = hip_error(hipStreamCreateWithFlags(&init_stream_, hipStreamNonBlocking),
+                            "init stream")))
+            return rc;
+        return hip_error(hipEventCreateWithFlags(&init_ev_, hipEventDisableTiming), "event");
+    }
+
+    int device() const { return device_; }
+    size_t state_capacity() const override
+    {
+        return arena_bytes_ > state_base_ ? arena_bytes_ - state_base_ : 0;
+    }
+
+    int init_slot(int, const ServeSlot &s, const fractal_request &rq) override
+    {
+        const size_t sb = state_bytes(s.k, s.rule);
+        uint8_t *b0 = buf(s, 0), *b1 = buf(s, 1);
+        int rc = hip_error(hipMemsetAsync(b1, 0, sb, init_stream_), "state clear");
+        if (!rc) {
+            if (rq.h_init)
+                rc = hip_error(hipMemcpyAsync(b0, rq.h_init, sb, hipMemcpyHostToDevice,
+                                              init_stream_),
+                               "state upload");
+            else
+                rc = launch_seed_fill(s.k, s.rule, rq.seed, b0, init_stream_);
+        }
+        return rc;
+    }
+
+    int join_init() override
+    {
+        int rc = hip_error(hipEventRecord(init_ev_, init_stream_), "event record");
+        if (!rc)
+            rc = hip_error(hipStreamWaitEvent(stream_, init_ev_, 0), "stream wait");
+        return rc;
+    }
+
+    int run(const std::vector<ServeIterItem> &items) override
+    {
+        // the table buffer of two iterations ago must have been consumed
+        (void)hipEventSynchronize(table_ev_[parity_]);
+        BatchEntry *ht = host_table_[parity_];
+        BatchEntry *dt = reinterpret_cast<BatchEntry *>(arena_ + table_off_[parity_]);
+        std::vector<BatchItem> bi;
+        bi.reserve(items.size());
+        for (const ServeIterItem &it : items) {
+            const ServeSlot &s = it.s;
+            bi.push_back(BatchItem{s.k, s.rule, it.steps, s.done, s.alpha, buf(s, 0), buf(s, 1),
+                                   batch_item_tuning(s.k, s.rule, nullptr)});
+        }
+        BatchPlan plan;
+        plan.build(bi, ht);
+        int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * plan.entries(),
+                                          hipMemcpyHostToDevice, stream_),
+                           "table upload");
+        for (int j = 0; j < plan.slots() && !rc; ++j)
+            rc = plan.launch_slot(dt, j, false, stream_);
+        if (!rc)
+            rc = hip_error(hipEventRecord(table_ev_[parity_], stream_), "event record");
+        parity_ ^= 1;
+        return rc;
+    }
+
+    int finish(int slot, const ServeSlot &s, uint64_t *token) override
+    {
+        const uint8_t *final_buf = buf(s, s.steps & 1);
+        unsigned long long *dsum = sums() + slot;
+        int rc = hip_error(hipMemsetAsync(dsum, 0, sizeof *dsum, stream_), "sum clear");
+        if (!rc)
+            rc = launch_checksum(s.k, s.rule, final_buf, dsum, stream_);
+        hipEvent_t ev = nullptr;
+        if (!rc)
+            rc = hip_error(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        if (!rc)
+            rc = hip_error(hipEventRecord(ev, stream_), "event record");
+        if (rc) {
+            if (ev)
+                (void)hipEventDestroy(ev);
+            return rc;
+        }
+        *token = reinterpret_cast<uint64_t>(ev);
         return FRACTAL_OK;
     }
 
-    void set_steps_per_iter(int n)
+    int collect(uint64_t token, int slot, const ServeSlot &s, void *h_out,
+                uint64_t *checksum) override
     {
-        std::lock_guard<std::mutex> lk(mu_);
-        per_iter_ = n;
+        hipEvent_t ev = reinterpret_cast<hipEvent_t>(token);
+        int rc = hip_error(hipEventSynchronize(ev), "wait for slot");
+        (void)hipEventDestroy(ev);
+        if (!rc && h_out)
+            rc = hip_error(hipMemcpyAsync(h_out, buf(s, s.steps & 1), state_bytes(s.k, s.rule),
+                                          hipMemcpyDeviceToHost, copy_stream_),
+                           "state download");
+        if (!rc)
+            rc = hip_error(hipMemcpyAsync(&host_sums_[slot], sums() + slot,
+                                          sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                          copy_stream_),
+                           "checksum download");
+        if (!rc)
+            rc = hip_error(hipStreamSynchronize(copy_stream_), "copy sync");
+        *checksum = rc ? 0 : host_sums_[slot];
+        return rc;
     }
 
-    int poll(uint64_t ticket, fractal_result *res)
+    void drain() override
     {
-        if (!res)
-            return set_error(FRACTAL_E_INVAL, "null result pointer");
-        std::lock_guard<std::mutex> lk(mu_);
-        auto it = tickets_.find(ticket);
-        if (it == tickets_.end())
-            return set_error(FRACTAL_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
-        if (it->second.state != DONE)
-            return FRACTAL_E_AGAIN;
-        *res = it->second.res;
-        tickets_.erase(it);
+        (void)hipStreamSynchronize(init_stream_);
+        (void)hipStreamSynchronize(stream_);
+    }
+
+  private:
+    static size_t align(size_t b) { return (b + 255) / 256 * 256; }
+    uint8_t *buf(const ServeSlot &s, int which) const
+    {
+        return arena_ + state_base_ + s.offset + (which ? align(state_bytes(s.k, s.rule)) : 0);
+    }
+    unsigned long long *sums() const
+    {
+        return reinterpret_cast<unsigned long long *>(arena_ + sums_off_);
+    }
+
+    uint8_t *arena_;
+    size_t arena_bytes_;
+    int max_slots_;
+    hipStream_t stream_, copy_stream_ = nullptr, init_stream_ = nullptr;
+    hipEvent_t init_ev_ = nullptr; // the newest admissions' initialisation
+    int device_ = 0;
+    int parity_ = 0;
+    size_t table_bytes_ = 0, table_off_[2] = {0, 0}, sums_off_ = 0, state_base_ = 0;
+    BatchEntry *host_table_[2] = {nullptr, nullptr};
+    hipEvent_t table_ev_[2] = {nullptr, nullptr};
+    unsigned long long *host_sums_ = nullptr;
+};
+
+// The executor, the clock, the scheduler core and its two threads.
+class Server {
+  public:
+    Server(uint8_t *arena, size_t bytes, int max_slots, hipStream_t s)
+        : ex_(arena, bytes, max_slots, s), max_slots_(max_slots)
+    {
+    }
+
+    int init()
+    {
+        int rc = ex_.init();
+        if (rc)
+            return rc;
+        core_.reset(new ServeCore(ex_, clock_, max_slots_, kDefaultStepsPerIter));
+        worker_ = std::thread([this] { schedule_loop(); });
+        retirer_ = std::thread([this] { retire_loop(); });
         return FRACTAL_OK;
     }
+
+    ServeCore &core() { return *core_; }
 
     void shutdown()
     {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            stopping_ = true;
-            cv_.notify_all();
-        }
+        if (!core_)
+            return;
+        core_->stop_scheduling();
         if (worker_.joinable())
             worker_.join();
-        {
-            std::lock_guard<std::mutex> lk(rmu_);
-            rstop_ = true;
-            rcv_.notify_all();
-        }
+        core_->stop_retiring();
         if (retirer_.joinable())
             retirer_.join();
     }
 
   private:
-    static size_t align(size_t b) { return (b + 255) / 256 * 256; }
-
-    void fail_ticket(uint64_t id, int code)
+    void schedule_loop()
     {
-        auto it = tickets_.find(id);
-        if (it == tickets_.end())
-            return;
-        it->second.res.status = code;
-        it->second.res.t_done = now_s();
-        it->second.state = DONE;
+        (void)hipSetDevice(ex_.device());
+        bool waiting = false;
+        while (core_->wait_work(waiting, 1))
+            waiting = core_->iterate() == ServeCore::WAITING;
     }
 
-    // Scheduler thread.  Slots are read and written under mu_; GPU work is
-    // enqueued from snapshots taken under the lock.
-    void run()
-    {
-        (void)hipSetDevice(device_);
-        int parity = 0;
-        for (;;) {
-            std::vector<Admitted> adm;
-            std::vector<std::pair<int, Slot>> act; // (slot index, snapshot)
-            std::vector<fractal_request> adm_rq;
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [&] { return stopping_ || !queue_.empty() || active_count() > 0; });
-                adm = queue_.admit(slot_free_, alloc_);
-                if (stopping_ && queue_.empty() && active_count() == 0 && adm.empty())
-                    break;
-                if (adm.empty() && active_count() == 0) {
-                    // queued work waits for a retiring slot to return memory
-                    cv_.wait_for(lk, std::chrono::milliseconds(1));
-                    continue;
-                }
-                const double t = now_s();
-                for (const Admitted &a : adm) {
-                    Ticket &tk = tickets_[a.ticket];
-                    tk.state = ACTIVE;
-                    tk.res.t_admit = t;
-                    Slot &sl = slots_[a.slot];
-                    sl.busy = true;
-                    sl.ticket = a.ticket;
-                    sl.offset = a.offset;
-                    sl.k = tk.rq.k;
-                    sl.rule = tk.rq.rule;
-                    sl.tuning = batch_item_tuning(sl.k, sl.rule, nullptr);
-                    sl.steps = tk.rq.steps;
-                    sl.done = 0;
-                    sl.alpha = tk.rq.alpha;
-                    const size_t one = align(state_bytes(sl.k, sl.rule));
-                    sl.buf0 = arena_ + state_base_ + a.offset;
-                    sl.buf1 = sl.buf0 + one;
-                    adm_rq.push_back(tk.rq);
-                }
-            }
-            // initialise admitted states on the device
-            for (size_t q = 0; q < adm.size(); ++q) {
-                Slot sl = slot_copy(adm[q].slot);
-                const fractal_request &rq = adm_rq[q];
-                const size_t sb = state_bytes(sl.k, sl.rule);
-                int rc = hip_error(hipMemsetAsync(sl.buf1, 0, sb, init_stream_), "state clear");
-                if (!rc) {
-                    if (rq.h_init)
-                        rc = hip_error(hipMemcpyAsync(sl.buf0, rq.h_init, sb, hipMemcpyHostToDevice,
-                                                      init_stream_),
-                                       "state upload");
-                    else
-                        rc = launch_seed_fill(sl.k, sl.rule, rq.seed, sl.buf0, init_stream_);
-                }
-                if (rc)
-                    abort_slot(adm[q].slot, rc);
-            }
-            if (!adm.empty()) {
-                // the next launches on the step stream use the new states
-                int rc = hip_error(hipEventRecord(init_ev_, init_stream_), "event record");
-                if (!rc)
-                    rc = hip_error(hipStreamWaitEvent(stream_, init_ev_, 0), "stream wait");
-                if (rc)
-                    for (const Admitted &a : adm)
-                        abort_slot(a.slot, rc);
-            }
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                for (int i = 0; i < max_slots_; ++i)
-                    if (slots_[i].busy && slots_[i].done <= slots_[i].steps)
-                        act.push_back({i, slots_[i]});
-            }
-            if (act.empty())
-                continue;
-            auto rem = [](const Slot &x) { return x.steps - x.done; };
-            std::stable_sort(act.begin(), act.end(), [&](const std::pair<int, Slot> &a,
-                                                         const std::pair<int, Slot> &b) {
-                return rem(a.second) > rem(b.second);
-            });
-            int per_iter;
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                per_iter = per_iter_;
-            }
-            const int c = std::min(per_iter, rem(act[0].second));
-            if (c > 0) {
-                // the table buffer of two iterations ago must be consumed
-                (void)hipEventSynchronize(table_ev_[parity]);
-                BatchEntry *ht = host_table_[parity];
-                BatchEntry *dt = reinterpret_cast<BatchEntry *>(arena_ + table_off_[parity]);
-                std::vector<BatchItem> items;
-                items.reserve(act.size());
-                for (const auto &a : act) {
-                    const Slot &sl = a.second;
-                    items.push_back(BatchItem{sl.k, sl.rule, std::min(c, rem(sl)), sl.done, sl.alpha,
-                                              sl.buf0, sl.buf1, sl.tuning});
-                }
-                BatchPlan plan;
-                plan.build(items, ht);
-                int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * plan.entries(),
-                                                  hipMemcpyHostToDevice, stream_),
-                                   "table upload");
-                for (int j = 0; j < plan.slots() && !rc; ++j)
-                    rc = plan.launch_slot(dt, j, false, stream_);
-                if (!rc)
-                    rc = hip_error(hipEventRecord(table_ev_[parity], stream_), "event record");
-                parity ^= 1;
-                if (rc) {
-                    for (auto &a : act)
-                        abort_slot(a.first, rc);
-                    continue;
-                }
-            }
-            std::vector<std::pair<int, Slot>> fin;
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                for (auto &a : act) {
-                    Slot &sl = slots_[a.first];
-                    sl.done += std::min(c, sl.steps - sl.done);
-                    if (sl.done >= sl.steps)
-                        fin.push_back({a.first, sl});
-                }
-            }
-            // retire finished slots: checksum on the device, then hand over
-            for (auto &f : fin) {
-                const int i = f.first;
-                const Slot &sl = f.second;
-                const uint8_t *final_buf = (sl.steps & 1) ? sl.buf1 : sl.buf0;
-                unsigned long long *dsum =
-                    reinterpret_cast<unsigned long long *>(arena_ + sums_off_) + i;
-                int rc = hip_error(hipMemsetAsync(dsum, 0, sizeof *dsum, stream_), "sum clear");
-                if (!rc)
-                    rc = launch_checksum(sl.k, sl.rule, final_buf, dsum, stream_);
-                hipEvent_t ev = nullptr;
-                if (!rc)
-                    rc = hip_error(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
-                if (!rc)
-                    rc = hip_error(hipEventRecord(ev, stream_), "event record");
-                if (rc) {
-                    if (ev)
-                        (void)hipEventDestroy(ev);
-                    abort_slot(i, rc);
-                    continue;
-                }
-                {
-                    std::lock_guard<std::mutex> lk(mu_);
-                    slots_[i].done = slots_[i].steps + 1; // leaves the active set
-                    tickets_[sl.ticket].state = RETIRING;
-                }
-                std::lock_guard<std::mutex> lk(rmu_);
-                rq_.push_back(RetireJob{sl.ticket, i, ev, final_buf, state_bytes(sl.k, sl.rule)});
-                rcv_.notify_all();
-            }
-        }
-    }
-
-    Slot slot_copy(int i)
-    {
-        std::lock_guard<std::mutex> lk(mu_);
-        return slots_[i];
-    }
-
-    int active_count() const
-    {
-        int c = 0;
-        for (const Slot &s : slots_)
-            if (s.busy && s.done <= s.steps)
-                ++c;
-        return c;
-    }
-
-    // Give up on a slot after a device error (its ticket reports the error).
-    void abort_slot(int i, int code)
-    {
-        (void)hipStreamSynchronize(init_stream_);
-        (void)hipStreamSynchronize(stream_);
-        std::lock_guard<std::mutex> lk(mu_);
-        Slot &s = slots_[i];
-        if (!s.busy)
-            return; // already given up
-        fail_ticket(s.ticket, code);
-        alloc_.release(s.offset);
-        s = Slot();
-        slot_free_[i] = true;
-        cv_.notify_all();
-    }
-
-    // Retire thread: wait for a finished slot, copy results, free its range.
     void retire_loop()
     {
-        (void)hipSetDevice(device_);
-        for (;;) {
-            RetireJob job;
-            {
-                std::unique_lock<std::mutex> lk(rmu_);
-                rcv_.wait(lk, [&] { return rstop_ || !rq_.empty(); });
-                if (rq_.empty() && rstop_)
-                    break;
-                job = rq_.front();
-                rq_.pop_front();
-            }
-            int rc = hip_error(hipEventSynchronize(job.ready), "wait for slot");
-            (void)hipEventDestroy(job.ready);
-            void *h_out = nullptr;
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                h_out = tickets_[job.ticket].rq.h_out;
-            }
-            if (!rc && h_out)
-                rc = hip_error(hipMemcpyAsync(h_out, job.final_buf, job.state_bytes,
-                                              hipMemcpyDeviceToHost, copy_stream_),
-                               "state download");
-            if (!rc)
-                rc = hip_error(hipMemcpyAsync(&host_sums_[job.slot],
-                                              reinterpret_cast<unsigned long long *>(arena_ + sums_off_) + job.slot,
-                                              sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                              copy_stream_),
-                               "checksum download");
-            if (!rc)
-                rc = hip_error(hipStreamSynchronize(copy_stream_), "copy sync");
-            std::lock_guard<std::mutex> lk(mu_);
-            Ticket &tk = tickets_[job.ticket];
-            tk.res.status = rc;
-            tk.res.checksum = rc ? 0 : host_sums_[job.slot];
-            tk.res.t_done = now_s();
-            tk.state = DONE;
-            Slot &s = slots_[job.slot];
-            alloc_.release(s.offset);
-            s = Slot();
-            slot_free_[job.slot] = true;
-            cv_.notify_all();
-        }
+        (void)hipSetDevice(ex_.device());
+        while (core_->wait_retire())
+            (void)core_->retire_one();
     }
 
-    uint8_t *arena_;
-    size_t arena_bytes_;
-    int max_slots_, per_iter_;
-    hipStream_t stream_, copy_stream_ = nullptr, init_stream_ = nullptr;
-    hipEvent_t init_ev_ = nullptr; // the newest admissions' initialisation
-    int device_ = 0;
-    size_t table_off_[2] = {0, 0}, sums_off_ = 0, state_base_ = 0;
-    BatchEntry *host_table_[2] = {nullptr, nullptr};
-    hipEvent_t table_ev_[2] = {nullptr, nullptr};
-    unsigned long long *host_sums_ = nullptr;
-
-    std::mutex mu_; // tickets_, queue_, alloc_, slot_free_, slot ownership
-    std::condition_variable cv_;
-    bool stopping_ = false;
-    uint64_t next_ticket_ = 0;
-    std::unordered_map<uint64_t, Ticket> tickets_;
-    AdmissionQueue queue_;
-    ArenaAllocator alloc_;
-    std::vector<Slot> slots_;
-    std::vector<bool> slot_free_;
-
-    std::mutex rmu_;
-    std::condition_variable rcv_;
-    bool rstop_ = false;
-    std::deque<RetireJob> rq_;
-
+    HipExecutor ex_;
+    SteadyClock clock_;
+    int max_slots_;
+    std::unique_ptr<ServeCore> core_;
     std::thread worker_, retirer_;
 };
 
@@ -515,7 +309,7 @@ int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots, void 
     if (max_slots < 1 || max_slots > 4096)
         return set_error(FRACTAL_E_INVAL, "max_slots=%d outside [1, 4096]", max_slots);
     Server *s = new Server(static_cast<uint8_t *>(d_arena), arena_bytes, max_slots,
-                           kDefaultStepsPerIter, static_cast<hipStream_t>(stream));
+                           static_cast<hipStream_t>(stream));
     int rc = s->init();
     if (rc) {
         s->shutdown();
@@ -532,7 +326,7 @@ int fractal_serve_set_steps_per_iter(void *server, int steps_per_iter)
         return set_error(FRACTAL_E_INVAL, "null server");
     if (steps_per_iter < 1 || steps_per_iter > 1 << 20)
         return set_error(FRACTAL_E_INVAL, "steps_per_iter=%d outside [1, 2^20]", steps_per_iter);
-    static_cast<Server *>(server)->set_steps_per_iter(steps_per_iter);
+    static_cast<Server *>(server)->core().set_steps_per_iter(steps_per_iter);
     return FRACTAL_OK;
 }
 
@@ -540,14 +334,34 @@ int fractal_serve_submit(void *server, const fractal_request *rq, uint64_t *tick
 {
     if (!server)
         return set_error(FRACTAL_E_INVAL, "null server");
-    return static_cast<Server *>(server)->submit(rq, ticket);
+    if (!rq || !ticket)
+        return set_error(FRACTAL_E_INVAL, "null request or ticket pointer");
+    const char *msg = "";
+    const int rc = static_cast<Server *>(server)->core().submit(*rq, ticket, &msg);
+    if (rc)
+        return set_error(rc, "request (k=%d rule=%d steps=%d): %s", rq->k, rq->rule, rq->steps,
+                         msg);
+    return FRACTAL_OK;
 }
 
 int fractal_serve_poll(void *server, uint64_t ticket, fractal_result *res)
 {
     if (!server)
         return set_error(FRACTAL_E_INVAL, "null server");
-    return static_cast<Server *>(server)->poll(ticket, res);
+    if (!res)
+        return set_error(FRACTAL_E_INVAL, "null result pointer");
+    const int rc = static_cast<Server *>(server)->core().poll(ticket, res);
+    if (rc == FRACTAL_E_INVAL)
+        return set_error(rc, "unknown ticket %llu", (unsigned long long)ticket);
+    return rc;
+}
+
+int fractal_serve_stats(void *server, fractal_serve_report *out)
+{
+    if (!server || !out)
+        return set_error(FRACTAL_E_INVAL, "null server or output");
+    static_cast<Server *>(server)->core().stats(out);
+    return FRACTAL_OK;
 }
 
 int fractal_serve_destroy(void *server)

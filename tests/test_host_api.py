@@ -190,6 +190,23 @@ def test_serving_scheduler_unit(tmp_path):
     assert "serve_sched ok" in out.stdout
 
 
+@pytest.mark.parametrize("san", [["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
+                                 ["-fsanitize=thread"]])
+def test_serving_core_fake_executor(tmp_path, san):
+    """The server's scheduler core against a fake executor and a fake clock:
+    budget, FIFO without skip-ahead, slot reuse, iteration sizes, p50/p99
+    bookkeeping, failures confined to the requests they touch, and the two
+    scheduling threads -- under ASan/UBSan, and under TSan."""
+    exe = tmp_path / "serve_core_test"
+    src = os.path.join(ROOT, "tests", "serve_core_test.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", *san, "-fno-omit-frame-pointer",
+                    "-pthread", "-Wall", "-Wextra", src, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "serve_core ok" in out.stdout
+    assert "ThreadSanitizer" not in out.stderr, out.stderr[-4000:]
+
+
 def test_oracle_and_product_share_nothing():
     """The oracle never imports the GPU package and vice versa."""
     prod = os.path.join(ROOT, "paper_2004_13475_amd")
