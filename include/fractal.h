@@ -116,6 +116,16 @@ extern "C" {
                                     / 8 are exclusive */
 #define FRACTAL_FLAG_STACK4 512  /* as STACK2, stacks of up to 4 tiles */
 #define FRACTAL_FLAG_STACK8 1024 /* as STACK2, stacks of up to 8 tiles */
+#define FRACTAL_FLAG_OCC_ALT 2048 /* lambda-map march launches of 8 or 16
+                                     steps on tiles of side 16..64: the kernel
+                                     compiled for the other occupancy (heat and
+                                     the automaton's 8 steps: 2 wavefronts per
+                                     SIMD instead of 3, so more registers per
+                                     lane; the automaton's 16 steps: 3 instead
+                                     of 2).  Launches of fewer steps, other
+                                     tile sizes, the BB map, batches and
+                                     compact states ignore it.  Needs
+                                     FRACTAL_FLAG_MARCH */
 
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */
@@ -202,8 +212,11 @@ int fractal_step_tuned(int map, int k, int rule, float alpha, void *d_buf0,
                        void *d_buf1, int steps, const fractal_tuning *tuning,
                        void *stream);
 
-/* Autotuner: times every supported (r, threads, order, flags) for this level and
- * rule on the given buffers (a few steps each, synchronising `stream`) and
+/* Autotuner: times every supported (r, threads, order, flags) for this level
+ * and rule on the given buffers (a few steps each, synchronising `stream`):
+ * tile sizes, both engines, dispatch orders, workgroup sizes, steps per
+ * launch, stacks, non-temporal stores and, for the long march launches, the
+ * occupancy the kernel is compiled for (FRACTAL_FLAG_OCC_ALT) -- and
  * records the fastest lambda launch in a per-process cache keyed by
  * (device, k, rule).  The buffers must satisfy the step contract; they end up
  * holding a state advanced by some number of steps.  `out` may be NULL. */
@@ -216,6 +229,21 @@ int fractal_get_tuning(int k, int rule, fractal_tuning *out);
 
 /* Replace the cached entry for (current device, k, rule). */
 int fractal_set_tuning(int k, int rule, const fractal_tuning *tuning);
+
+/* Tuning file: one text line per cached entry, "device<TAB>k<TAB>rule<TAB>r
+ * <TAB>threads<TAB>order<TAB>flags", where device is the device's product
+ * and architecture name (so a file tuned on one MI355X serves every MI355X);
+ * lines starting with '#' are comments.  fractal_tuning_save writes every
+ * cached entry (replacing the file through a temporary one; E_DEVICE on an
+ * I/O error).  fractal_tuning_load adds the entries named for the current
+ * device to the cache, replacing entries of the same (k, rule); other
+ * devices' lines are skipped; E_DEVICE if the file cannot be read, E_INVAL
+ * on a malformed line or an invalid tuning (then nothing is added).  If the
+ * environment variable FRACTAL_TUNING_FILE names a file, it is loaded before
+ * the first lookup of the process (a missing or malformed file is then
+ * ignored) and rewritten after every fractal_autotune. */
+int fractal_tuning_save(const char *path);
+int fractal_tuning_load(const char *path);
 
 /* Test SW of Section 6.2 (single write): every member cell of the level-k
  * gasket in d_buf (n x n, row-major, uint8 for FRACTAL_RULE_CA, float32 for

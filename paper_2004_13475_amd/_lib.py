@@ -21,6 +21,7 @@ ORDER_NATURAL, ORDER_CURVE, ORDER_CURVE_XCD = 0, 1, 2
 FLAG_SEGMENTS, FLAG_NT_STORE, FLAG_PERSISTENT, FLAG_FUSE2, FLAG_FUSE4 = 1, 2, 4, 8, 16
 FLAG_MARCH, FLAG_FUSE8, FLAG_FUSE16 = 32, 64, 128
 FLAG_STACK2, FLAG_STACK4, FLAG_STACK8 = 256, 512, 1024
+FLAG_OCC_ALT = 2048
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 
@@ -28,7 +29,8 @@ EXPORTED = [
     "fractal_grid_dims", "fractal_lambda_map", "fractal_lambda_map_mfma",
     "fractal_lambda_map_tiles", "fractal_seed_fill", "fractal_bb_step", "fractal_lambda_step",
     "fractal_lambda_step_mfma", "fractal_step_tuned", "fractal_autotune",
-    "fractal_get_tuning", "fractal_set_tuning", "fractal_batch_workspace", "fractal_batch_step",
+    "fractal_get_tuning", "fractal_set_tuning", "fractal_tuning_save", "fractal_tuning_load",
+    "fractal_batch_workspace", "fractal_batch_step",
     "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
     "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
     "fractal_compact_step", "fractal_nbb_builtin", "fractal_nbb_lambda_map",
@@ -120,6 +122,8 @@ def load():
         "fractal_autotune": ([i, i, f, vp, vp, vp, ctypes.POINTER(Tuning)], i),
         "fractal_get_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
         "fractal_set_tuning": ([i, i, ctypes.POINTER(Tuning)], i),
+        "fractal_tuning_save": ([ctypes.c_char_p], i),
+        "fractal_tuning_load": ([ctypes.c_char_p], i),
         "fractal_batch_workspace": ([i, ctypes.POINTER(ctypes.c_size_t)], i),
         "fractal_batch_step": ([ctypes.POINTER(Instance), i, ctypes.POINTER(Tuning), vp,
                                 ctypes.c_size_t, vp], i),
@@ -259,6 +263,16 @@ def _nbytes(buf, nbytes, what):
     if nbytes is None:
         raise ValueError(f"{what}: a raw device address needs its size in bytes (nbytes=)")
     return int(nbytes)
+
+
+def tuning_save(path):
+    """Write every cached tuning to a tuning file."""
+    return _check(load().fractal_tuning_save(os.fsencode(path)))
+
+
+def tuning_load(path):
+    """Add a tuning file's entries for the current device to the cache."""
+    return _check(load().fractal_tuning_load(os.fsencode(path)))
 
 
 def batch_workspace(count) -> int:

@@ -5,8 +5,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -141,7 +144,8 @@ static fractal_tuning builtin_default(int k, int rule)
 }
 
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, fractal_tuning> g_tune;
+static std::map<std::tuple<int, int, int>, fractal_tuning> g_tune; // (device, k, rule)
+static bool g_tune_env_loaded = false;
 
 static int current_device()
 {
@@ -151,9 +155,129 @@ static int current_device()
     return d;
 }
 
+// Name a tuning file gives device `dev`: its product name and architecture
+// ("none" where the runtime reports no device, for host-only use).  Tabs
+// and newlines are replaced, so the name is one field of a line.
+static std::string device_key(int dev)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return "none";
+    std::string s = std::string(p.name) + "|" + p.gcnArchName;
+    for (char &c : s)
+        if (c == '\t' || c == '\n' || c == '\r')
+            c = ' ';
+    return s;
+}
+
+static const char *kTuneHeader =
+    "# libfractal tuning v1: device\tk\trule\tr\tthreads\torder\tflags";
+
+// Reads `path` into (k, rule) -> tuning for devices named `key`; other
+// devices' lines are skipped.  E_INVAL on a malformed line or an invalid
+// tuning, E_DEVICE if the file cannot be read.
+static int read_tuning_file(const char *path, const std::string &key,
+                            std::map<std::pair<int, int>, fractal_tuning> *out)
+{
+    std::ifstream in(path);
+    if (!in)
+        return set_error(FRACTAL_E_DEVICE, "cannot read tuning file %s", path);
+    std::string line;
+    int lineno = 0;
+    while (std::getline(in, line)) {
+        ++lineno;
+        if (line.empty() || line[0] == '#')
+            continue;
+        std::vector<std::string> f;
+        std::stringstream ss(line);
+        std::string cell;
+        while (std::getline(ss, cell, '\t'))
+            f.push_back(cell);
+        if (f.size() != 7)
+            return set_error(FRACTAL_E_INVAL, "%s:%d: expected 7 tab-separated fields", path,
+                             lineno);
+        int v[6];
+        for (int i = 0; i < 6; ++i) {
+            char *end = nullptr;
+            const long x = std::strtol(f[i + 1].c_str(), &end, 10);
+            if (!end || *end || f[i + 1].empty() || x < -1000000 || x > 1000000)
+                return set_error(FRACTAL_E_INVAL, "%s:%d: field %d is not an integer", path,
+                                 lineno, i + 2);
+            v[i] = (int)x;
+        }
+        const int k = v[0], rule = v[1];
+        if (k < 0 || k > kMaxStepLevel || (rule != FRACTAL_RULE_CA && rule != FRACTAL_RULE_HEAT))
+            return set_error(FRACTAL_E_INVAL, "%s:%d: bad level or rule", path, lineno);
+        const fractal_tuning t{v[2], v[3], v[4], v[5]};
+        if (check_tuning(MAP_LAMBDA, k, rule, &t))
+            return set_error(FRACTAL_E_INVAL, "%s:%d: %s", path, lineno, fractal_last_error());
+        if (f[0] == key)
+            (*out)[std::make_pair(k, rule)] = t;
+    }
+    return FRACTAL_OK;
+}
+
+// Adds a file's entries for the current device to the cache.
+static int load_tuning_locked(const char *path)
+{
+    const int dev = current_device();
+    std::map<std::pair<int, int>, fractal_tuning> got;
+    const int rc = read_tuning_file(path, device_key(dev), &got);
+    if (rc)
+        return rc;
+    for (const auto &e : got)
+        g_tune[std::make_tuple(dev, e.first.first, e.first.second)] = e.second;
+    return FRACTAL_OK;
+}
+
+// Writes the whole cache (every device) to `path` through a temporary file.
+static int save_tuning_locked(const char *path)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream out(tmp, std::ios::trunc);
+        if (!out)
+            return set_error(FRACTAL_E_DEVICE, "cannot write tuning file %s", tmp.c_str());
+        out << kTuneHeader << "\n";
+        for (const auto &e : g_tune) {
+            const fractal_tuning &t = e.second;
+            out << device_key(std::get<0>(e.first)) << "\t" << std::get<1>(e.first) << "\t"
+                << std::get<2>(e.first) << "\t" << t.r << "\t" << t.threads << "\t" << t.order
+                << "\t" << t.flags << "\n";
+        }
+        if (!out)
+            return set_error(FRACTAL_E_DEVICE, "write error on %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0)
+        return set_error(FRACTAL_E_DEVICE, "cannot rename %s to %s", tmp.c_str(), path);
+    return FRACTAL_OK;
+}
+
+// FRACTAL_TUNING_FILE, if set, names a tuning file read before the first
+// lookup (once per process; a missing or malformed file is ignored) and
+// rewritten after every autotuner run.
+static const char *env_tuning_file()
+{
+    const char *p = std::getenv("FRACTAL_TUNING_FILE");
+    return (p && *p) ? p : nullptr;
+}
+
+static void load_env_tuning_locked()
+{
+    if (g_tune_env_loaded)
+        return;
+    g_tune_env_loaded = true;
+    if (const char *p = env_tuning_file()) {
+        const std::string saved = g_error;
+        (void)load_tuning_locked(p);
+        g_error = saved;
+    }
+}
+
 fractal_tuning default_tuning(int k, int rule)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tuning_locked();
     auto it = g_tune.find(std::make_tuple(current_device(), k, rule));
     if (it != g_tune.end())
         return it->second;
@@ -176,7 +300,7 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
     const bool march = (t->flags & FRACTAL_FLAG_MARCH) != 0;
     const int stack = t->flags & kStackFlags;
     if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH |
-                     kFuseFlags | kStackFlags))
+                     kFuseFlags | kStackFlags | FRACTAL_FLAG_OCC_ALT))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
     if (fuse & (fuse - 1))
         return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
@@ -184,6 +308,8 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "the STACK flags are exclusive");
     if (stack && !march)
         return set_error(FRACTAL_E_INVAL, "STACK flags need FRACTAL_FLAG_MARCH");
+    if ((t->flags & FRACTAL_FLAG_OCC_ALT) && !march)
+        return set_error(FRACTAL_E_INVAL, "FRACTAL_FLAG_OCC_ALT needs FRACTAL_FLAG_MARCH");
     if ((fuse & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)) && !march)
         return set_error(FRACTAL_E_INVAL, "FUSE8 and FUSE16 need FRACTAL_FLAG_MARCH");
     if ((fuse & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
@@ -342,8 +468,27 @@ int fractal_set_tuning(int k, int rule, const fractal_tuning *t)
     if (rc)
         return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tuning_locked();
     g_tune[std::make_tuple(current_device(), k, rule)] = *t;
     return FRACTAL_OK;
+}
+
+int fractal_tuning_save(const char *path)
+{
+    if (!path || !*path)
+        return set_error(FRACTAL_E_INVAL, "null or empty path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tuning_locked();
+    return save_tuning_locked(path);
+}
+
+int fractal_tuning_load(const char *path)
+{
+    if (!path || !*path)
+        return set_error(FRACTAL_E_INVAL, "null or empty path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tuning_locked();
+    return load_tuning_locked(path);
 }
 
 int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, void *stream,
@@ -392,9 +537,14 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                         if ((fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA) &&
                             (stack == 0 || fuse == FRACTAL_FLAG_FUSE8 ||
                              fuse == FRACTAL_FLAG_FUSE16))
-                            cands.push_back(fractal_tuning{
-                                r, 256, FRACTAL_ORDER_CURVE_XCD,
-                                FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse | stack});
+                            for (int occ : {0, (int)FRACTAL_FLAG_OCC_ALT})
+                                if (occ == 0 || ((fuse == FRACTAL_FLAG_FUSE8 ||
+                                                  fuse == FRACTAL_FLAG_FUSE16) &&
+                                                 r >= 4 && r <= 6))
+                                    cands.push_back(fractal_tuning{
+                                        r, 256, FRACTAL_ORDER_CURVE_XCD,
+                                        FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse |
+                                            stack | occ});
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)
@@ -423,7 +573,11 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
         return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_env_tuning_locked();
         g_tune[std::make_tuple(current_device(), k, rule)] = best;
+        if (const char *p = env_tuning_file())
+            if ((rc = save_tuning_locked(p)))
+                return rc;
     }
     if (out)
         *out = best;

@@ -297,7 +297,7 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         const int fuse = tuning->flags & kFuseFlags;
         if ((tuning->flags & ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS |
                                FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags |
-                               kStackFlags)) ||
+                               kStackFlags | FRACTAL_FLAG_OCC_ALT)) ||
             (fuse & (fuse - 1)))
             return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
     }

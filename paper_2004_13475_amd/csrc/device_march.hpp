@@ -52,6 +52,13 @@ constexpr int march_hl(int rule, int T)
 // halo), 8 for heat.
 constexpr bool march_supported(int rule, int T) { return T <= (rule == RULE_CA ? 16 : 8); }
 constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
+// The other occupancy the autotuner may try for the long launches: 3
+// wavefronts per SIMD for 16 steps (fewer registers per lane), 2 for 8 steps
+// (more registers: room for the row state of the wider tiles without spills).
+constexpr int march_wpe_alt(int T) { return T >= 16 ? 3 : 2; }
+// Launch shapes with a kernel for the other occupancy: 8 or 16 steps, tiles
+// of side 16, 32 or 64.
+constexpr bool march_has_alt(int T, int R) { return T >= 8 && R >= 4 && R <= 6; }
 // Rows loaded ahead of the walk: a whole number of them per unrolled pass
 // (16 rows for the automaton, 12 for heat).  Heat launches of 8 steps keep a
 // whole pass in flight: at 16 x 16 tiles that costs a wavefront per SIMD of

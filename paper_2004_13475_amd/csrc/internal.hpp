@@ -97,7 +97,8 @@ struct MarchArgs {
 };
 typedef void (*MarchFn)(MarchArgs);
 // Kernel for (map, rule, r, T steps, non-temporal stores); nullptr if none.
-MarchFn pick_march(int map, int rule, int r, int T, bool nt);
+// alt: the kernel compiled for the other occupancy where one exists.
+MarchFn pick_march(int map, int rule, int r, int T, bool nt, bool alt);
 // Tiles one wavefront handles (0: no march kernel for this shape).
 int march_tiles_per_wave(int rule, int r, int T);
 int march_band_log(int rule, int r, int T, uint64_t tiles);

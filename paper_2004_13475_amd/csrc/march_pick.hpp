@@ -9,28 +9,34 @@
 
 namespace fractal {
 
-template <int MAP, int RULE, int R, int T, int FL>
+// The kernel for a launch shape; ALT selects the other occupancy where
+// the lambda map has a kernel for it (march_has_alt), else the default one.
+template <int MAP, int RULE, int R, int T, int FL, bool ALT>
 static MarchFn march_fn()
 {
     constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
-        return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;
-    else
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T)) {
+        if constexpr (ALT && MAP == MAP_LAMBDA && march_has_alt(T, R))
+            return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe_alt(T), march_depth(RULE, T)>;
+        else
+            return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;
+    } else {
         return nullptr;
+    }
 }
 
-template <int MAP, int RULE, int FL>
+template <int MAP, int RULE, int FL, bool ALT>
 static MarchFn march_pick_rt(int r, int T)
 {
     switch (r) {
 #define FRACTAL_MARCH_R(RR)                                                                        \
     case RR:                                                                                       \
         switch (T) {                                                                               \
-        case 1: return march_fn<MAP, RULE, RR, 1, FL>();                                           \
-        case 2: return march_fn<MAP, RULE, RR, 2, FL>();                                           \
-        case 4: return march_fn<MAP, RULE, RR, 4, FL>();                                           \
-        case 8: return march_fn<MAP, RULE, RR, 8, FL>();                                           \
-        case 16: return march_fn<MAP, RULE, RR, 16, FL>();                                         \
+        case 1: return march_fn<MAP, RULE, RR, 1, FL, false>();                                    \
+        case 2: return march_fn<MAP, RULE, RR, 2, FL, false>();                                    \
+        case 4: return march_fn<MAP, RULE, RR, 4, FL, false>();                                    \
+        case 8: return march_fn<MAP, RULE, RR, 8, FL, ALT>();                                      \
+        case 16: return march_fn<MAP, RULE, RR, 16, FL, ALT>();                                    \
         default: return nullptr;                                                                   \
         }
         FRACTAL_MARCH_R(2)
@@ -45,14 +51,17 @@ static MarchFn march_pick_rt(int r, int T)
 }
 
 template <int RULE>
-static MarchFn march_pick_rule(int map, int r, int T, bool nt)
+static MarchFn march_pick_rule(int map, int r, int T, bool nt, bool alt)
 {
+    if (map == MAP_LAMBDA && alt)
+        return nt ? march_pick_rt<MAP_LAMBDA, RULE, TILE_NT_STORE, true>(r, T)
+                  : march_pick_rt<MAP_LAMBDA, RULE, 0, true>(r, T);
     if (map == MAP_LAMBDA)
-        return nt ? march_pick_rt<MAP_LAMBDA, RULE, TILE_NT_STORE>(r, T)
-                  : march_pick_rt<MAP_LAMBDA, RULE, 0>(r, T);
+        return nt ? march_pick_rt<MAP_LAMBDA, RULE, TILE_NT_STORE, false>(r, T)
+                  : march_pick_rt<MAP_LAMBDA, RULE, 0, false>(r, T);
     if (map == MAP_BB)
-        return nt ? march_pick_rt<MAP_BB, RULE, TILE_NT_STORE>(r, T)
-                  : march_pick_rt<MAP_BB, RULE, 0>(r, T);
+        return nt ? march_pick_rt<MAP_BB, RULE, TILE_NT_STORE, false>(r, T)
+                  : march_pick_rt<MAP_BB, RULE, 0, false>(r, T);
     return nullptr;
 }
 

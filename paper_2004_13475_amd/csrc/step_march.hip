@@ -8,13 +8,13 @@
 
 namespace fractal {
 
-MarchFn pick_march_ca(int map, int r, int T, bool nt);
-MarchFn pick_march_heat(int map, int r, int T, bool nt);
+MarchFn pick_march_ca(int map, int r, int T, bool nt, bool alt);
+MarchFn pick_march_heat(int map, int r, int T, bool nt, bool alt);
 
-MarchFn pick_march(int map, int rule, int r, int T, bool nt)
+MarchFn pick_march(int map, int rule, int r, int T, bool nt, bool alt)
 {
-    return rule == FRACTAL_RULE_CA ? pick_march_ca(map, r, T, nt)
-                                   : pick_march_heat(map, r, T, nt);
+    return rule == FRACTAL_RULE_CA ? pick_march_ca(map, r, T, nt, alt)
+                                   : pick_march_heat(map, r, T, nt, alt);
 }
 
 int march_tiles_per_wave(int rule, int r, int T)
@@ -71,6 +71,7 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
 {
     const int Tmax = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
+    const bool alt = (t.flags & FRACTAL_FLAG_OCC_ALT) != 0;
     int counts[kMaxListsPerItem];
     march_split(steps, Tmax, counts);
     std::vector<int> plan;
@@ -93,7 +94,7 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     const int wpg = t.threads / 64;
     for (size_t i = 0; i < plan.size(); ++i) {
         const int T = plan[i];
-        MarchFn fn = pick_march(map, rule, t.r, T, nt);
+        MarchFn fn = pick_march(map, rule, t.r, T, nt, alt);
         const int P = march_tiles_per_wave(rule, t.r, T);
         if (!fn || P < 1)
             return set_error(FRACTAL_E_INVAL, "no march kernel for rule %d r %d T %d", rule, t.r, T);

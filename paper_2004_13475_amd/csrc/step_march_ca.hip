@@ -3,9 +3,9 @@
 
 namespace fractal {
 
-MarchFn pick_march_ca(int map, int r, int T, bool nt)
+MarchFn pick_march_ca(int map, int r, int T, bool nt, bool alt)
 {
-    return march_pick_rule<RULE_CA>(map, r, T, nt);
+    return march_pick_rule<RULE_CA>(map, r, T, nt, alt);
 }
 
 } // namespace fractal

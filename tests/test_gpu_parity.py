@@ -289,7 +289,7 @@ def test_autotune_picks_a_valid_launch(rule):
     assert tuple(F.get_tuning(k, rule)) == tuple(t)
     r, th, order, fl = t
     assert 0 <= r <= 7 and th in (64, 256) and order in (0, 1, 2)
-    assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024) == 0
+    assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024 | 2048) == 0
     for steps in (5, 40):
         a0, a1 = to_device(init), zeros_state(k, rule)
         F.lambda_step(k, F.R_AUTO, rule, ALPHA, a0, a1, steps)
@@ -301,6 +301,33 @@ def test_autotune_picks_a_valid_launch(rule):
         assert torch.equal(got.view(torch.uint8), ref.view(torch.uint8)), (t, steps)
     F.set_tuning(k, rule, *before)
     assert tuple(F.get_tuning(k, rule)) == tuple(before)
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_march_other_occupancy_bit_identical(rule):
+    """The long march launches compiled for the other occupancy
+    (FRACTAL_FLAG_OCC_ALT, a dimension of the autotuner) give the bits of
+    the default kernels, on every tile size that has them (and are ignored
+    where none exists), with non-temporal stores and stacks."""
+    torch = torch_dev()
+    k = 12
+    init = fi.window_values(k, rule, 55)
+    fuses = (F.FLAG_FUSE8,) + ((F.FLAG_FUSE16,) if rule == fi.RULE_CA else ())
+    for r in range(2 if rule == fi.RULE_HEAT else 4, 8):
+        for fuse in fuses:
+            for extra in (0, F.FLAG_NT_STORE, F.FLAG_STACK2):
+                fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | fuse | extra
+                for steps in (16, 21):
+                    a0, a1 = to_device(init), zeros_state(k, rule)
+                    F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, a0, a1, steps, r, 256, 2, fl)
+                    b0, b1 = to_device(init), zeros_state(k, rule)
+                    F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, b0, b1, steps, r, 256, 2,
+                                 fl | F.FLAG_OCC_ALT)
+                    _sync()
+                    fa = a0 if steps % 2 == 0 else a1
+                    fb = b0 if steps % 2 == 0 else b1
+                    assert torch.equal(fa.view(torch.uint8), fb.view(torch.uint8)), \
+                        (r, fl, steps)
 
 
 def test_march_rejects_bad_tunings():

@@ -4,6 +4,7 @@ scheduler's allocator and admission queue (g++ with sanitizers)."""
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -80,8 +81,9 @@ def test_tuning_defaults_and_validation():
             assert 0 <= r <= min(k, 7) and k - r <= 15
             assert th in (64, 256) and order in (0, 1, 2)
             lds = (0, 1, 2, 3, 9, 11, 17, 19)
-            march = tuple(32 | 1 | nt | fuse | st for nt in (0, 2) for fuse in (0, 8, 16, 64, 128)
-                          for st in (0, 256, 512, 1024))
+            march = tuple(32 | 1 | nt | fuse | st | occ for nt in (0, 2)
+                          for fuse in (0, 8, 16, 64, 128) for st in (0, 256, 512, 1024)
+                          for occ in (0, 2048))
             assert flags in lds + march, (k, rule, flags)
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
@@ -111,6 +113,62 @@ def test_tuning_defaults_and_validation():
 
 
 FAKEW = 0x20000000  # a fake workspace address
+
+
+def test_tuning_file_round_trip(tmp_path):
+    """Tuned launches persist in a text file keyed by device name, level and
+    rule: saved, overwritten in the cache, loaded back; lines for other
+    devices are skipped; a malformed file is refused and changes nothing."""
+    path = tmp_path / "tuning.txt"
+    before = {(k, rule): F.get_tuning(k, rule) for k in (12, 13) for rule in (0, 1)}
+    tuned = {(12, 0): (5, 256, 2, 32 | 1 | 64 | 2048), (12, 1): (4, 256, 0, 32 | 1 | 64 | 2),
+             (13, 0): (6, 256, 2, 32 | 1 | 128 | 256), (13, 1): (3, 64, 1, 1)}
+    try:
+        for (k, rule), t in tuned.items():
+            F.set_tuning(k, rule, *t)
+        F.tuning_save(path)
+        lines = path.read_text().splitlines()
+        assert lines[0].startswith("#")
+        for (k, rule) in tuned:
+            F.set_tuning(k, rule, *before[(k, rule)])
+        F.tuning_load(path)
+        for (k, rule), t in tuned.items():
+            assert tuple(F.get_tuning(k, rule)) == t
+        # another device's entry is skipped; the current device's is taken
+        me = next(ln.split("\t")[0] for ln in lines[1:])
+        other = tmp_path / "other.txt"
+        other.write_text(f"other-device|gfx000\t12\t0\t7\t64\t0\t1\n"
+                         f"{me}\t12\t1\t5\t256\t2\t{32 | 1 | 64}\n")
+        F.tuning_load(other)
+        assert tuple(F.get_tuning(12, 0)) == tuned[(12, 0)]
+        assert tuple(F.get_tuning(12, 1)) == (5, 256, 2, 32 | 1 | 64)
+        for bad in ("x\t12\t0\t5\n", f"{me}\t12\t0\t9\t256\t2\t1\n",
+                    f"{me}\t12\tzero\t5\t256\t2\t1\n", f"{me}\t12\t0\t5\t128\t2\t1\n"):
+            p = tmp_path / "bad.txt"
+            p.write_text(bad)
+            with pytest.raises(F.FractalError) as e:
+                F.tuning_load(p)
+            assert e.value.code == F.E_INVAL
+        assert tuple(F.get_tuning(12, 1)) == (5, 256, 2, 32 | 1 | 64)
+        with pytest.raises(F.FractalError) as e:
+            F.tuning_load(tmp_path / "missing.txt")
+        assert e.value.code == F.E_DEVICE
+    finally:
+        for (k, rule), t in before.items():
+            F.set_tuning(k, rule, *t)
+
+
+def test_tuning_file_from_environment(tmp_path):
+    """FRACTAL_TUNING_FILE is read before a process's first lookup."""
+    path = tmp_path / "env_tuning.txt"
+    code = ("import sys; sys.path.insert(0, %r); import paper_2004_13475_amd as F; "
+            "F.set_tuning(11, 1, 5, 256, 2, 32 | 1 | 64 | 2); F.tuning_save(%r)" % (ROOT, str(path)))
+    subprocess.run([sys.executable, "-c", code], check=True)
+    code = ("import sys; sys.path.insert(0, %r); import paper_2004_13475_amd as F; "
+            "print(tuple(F.get_tuning(11, 1)))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], check=True, capture_output=True, text=True,
+                         env=dict(os.environ, FRACTAL_TUNING_FILE=str(path)))
+    assert out.stdout.strip() == str((5, 256, 2, 32 | 1 | 64 | 2))
 
 
 def test_batch_validation():
