@@ -96,7 +96,8 @@ extern "C" {
 #define FRACTAL_FLAG_FUSE8 64   /* eight steps per launch (with
                                    FRACTAL_FLAG_MARCH only) */
 #define FRACTAL_FLAG_FUSE16 128 /* sixteen steps per launch (with
-                                   FRACTAL_FLAG_MARCH, automaton only) */
+                                   FRACTAL_FLAG_MARCH; heat on tiles of
+                                   side >= 16 only) */
 #define FRACTAL_FLAG_PERSISTENT 4 /* batch only: register-march launches run
                                      a persistent grid (as many workgroups as
                                      the chip holds) striding through each

@@ -312,8 +312,8 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         return set_error(FRACTAL_E_INVAL, "FRACTAL_FLAG_OCC_ALT needs FRACTAL_FLAG_MARCH");
     if ((fuse & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)) && !march)
         return set_error(FRACTAL_E_INVAL, "FUSE8 and FUSE16 need FRACTAL_FLAG_MARCH");
-    if ((fuse & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
-        return set_error(FRACTAL_E_INVAL, "FUSE16 is for the automaton only");
+    if ((fuse & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA && t->r < 4)
+        return set_error(FRACTAL_E_INVAL, "heat FUSE16 needs tiles of side >= 16");
     if ((fuse || march) && !(t->flags & FRACTAL_FLAG_SEGMENTS))
         return set_error(FRACTAL_E_INVAL, "fused and march launches need FRACTAL_FLAG_SEGMENTS");
     if ((fuse || march) && ((1 << t->r) * (int)cell_bytes(rule)) < 16)
@@ -534,12 +534,13 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                              (int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16})
                 for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
                     for (int stack : {0, (int)FRACTAL_FLAG_STACK2, (int)FRACTAL_FLAG_STACK4})
-                        if ((fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA) &&
+                        if ((fuse != FRACTAL_FLAG_FUSE16 || rule == FRACTAL_RULE_CA || r >= 4) &&
                             (stack == 0 || fuse == FRACTAL_FLAG_FUSE8 ||
                              fuse == FRACTAL_FLAG_FUSE16))
                             for (int occ : {0, (int)FRACTAL_FLAG_OCC_ALT})
                                 if (occ == 0 || ((fuse == FRACTAL_FLAG_FUSE8 ||
-                                                  fuse == FRACTAL_FLAG_FUSE16) &&
+                                                  (fuse == FRACTAL_FLAG_FUSE16 &&
+                                                   rule == FRACTAL_RULE_CA)) &&
                                                  r >= 4 && r <= 6))
                                     cands.push_back(fractal_tuning{
                                         r, 256, FRACTAL_ORDER_CURVE_XCD,

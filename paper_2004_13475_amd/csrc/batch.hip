@@ -69,8 +69,8 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         t.flags &= ~(kFuseFlags | FRACTAL_FLAG_MARCH);
     if (!(t.flags & FRACTAL_FLAG_MARCH) && (t.flags & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)))
         t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE4; // LDS engine: 4 at most
-    if ((t.flags & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA)
-        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8; // heat marches 8 at most
+    if ((t.flags & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA && t.r < 4)
+        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8; // narrow heat tiles: 8 at most
     if (t.flags & FRACTAL_FLAG_MARCH)
         t.threads = 256;
     else if (t.threads == 256 && t.r < 3)

@@ -68,7 +68,7 @@ template <int RULE, int R, int T, int FL>
 static BatchMarchFn bm_fn()
 {
     constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T))
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T, R))
         return batch_march_kernel<RULE, R, T, HL, FL, march_wpe(T), march_depth(RULE, T)>;
     else
         return nullptr;

@@ -69,7 +69,7 @@ template <int RULE, int R, int T, int HL>
 constexpr bool compact_shape_ok()
 {
     using M = MGeom<RULE, R, T, HL>;
-    return M::VALID && march_supported(RULE, T) && T <= M::RHO && HL * M::CC <= M::RHO;
+    return M::VALID && march_supported(RULE, T, R) && T <= M::RHO && HL * M::CC <= M::RHO;
 }
 
 template <int RULE, int R, int T, int HL, int FL, int WPE, int D>

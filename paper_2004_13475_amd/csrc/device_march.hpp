@@ -48,21 +48,33 @@ constexpr int march_hl(int rule, int T)
 {
     return T <= (rule == RULE_CA ? 16 : 4) ? 1 : (T <= 8 ? 2 : 4);
 }
-// Step counts a march launch takes: 16 for the automaton (one chunk of
-// halo), 8 for heat.
-constexpr bool march_supported(int rule, int T) { return T <= (rule == RULE_CA ? 16 : 8); }
+// Step counts a march launch takes: up to 16 for the automaton (one chunk
+// of halo); up to 8 for heat, and 16 on tiles of side >= 16 (four halo
+// lanes per side: narrower tiles would be mostly halo).
+constexpr bool march_supported(int rule, int T, int R)
+{
+    return T <= 8 || (T == 16 && (rule == RULE_CA || R >= 4));
+}
 constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
 // The other occupancy the autotuner may try for the long launches: 3
-// wavefronts per SIMD for 16 steps (fewer registers per lane), 2 for 8 steps
-// (more registers: room for the row state of the wider tiles without spills).
+// wavefronts per SIMD for the automaton's 16 steps (fewer registers per
+// lane), 2 for 8 steps (more registers: room for the row state of the wider
+// tiles without spills).
 constexpr int march_wpe_alt(int T) { return T >= 16 ? 3 : 2; }
-// Launch shapes with a kernel for the other occupancy: 8 or 16 steps, tiles
-// of side 16, 32 or 64.
-constexpr bool march_has_alt(int T, int R) { return T >= 8 && R >= 4 && R <= 6; }
+// Launch shapes with a kernel for the other occupancy: 8 steps, or the
+// automaton's 16 (heat's 16-step row state, 16 levels of 3 rows of 4
+// words, needs the registers of 2 wavefronts per SIMD), tiles of side 16,
+// 32 or 64.
+constexpr bool march_has_alt(int rule, int T, int R)
+{
+    return (T == 8 || (T == 16 && rule == RULE_CA)) && R >= 4 && R <= 6;
+}
 // Rows loaded ahead of the walk: a whole number of them per unrolled pass
-// (16 rows for the automaton, 12 for heat).  Heat launches of 8 steps keep a
-// whole pass in flight: at 16 x 16 tiles that costs a wavefront per SIMD of
-// occupancy (4 -> 3) and still measured 3-10% faster than 6 or 4 rows.
+// (16 rows for the automaton, 12 for heat).  Heat launches of 8 and 16
+// steps keep a whole pass in flight: at 16 x 16 tiles and 8 steps that
+// costs a wavefront per SIMD of occupancy (4 -> 3) and still measured 3-10%
+// faster than 6 or 4 rows; at 16 steps the 12 rows fit the 2 wavefronts per
+// SIMD the row state needs anyway (240 registers).
 constexpr int march_depth(int rule, int T)
 {
     return rule == RULE_CA ? (T <= 4 ? 8 : 4) : (T >= 8 ? 12 : 4);

@@ -15,8 +15,8 @@ template <int MAP, int RULE, int R, int T, int FL, bool ALT>
 static MarchFn march_fn()
 {
     constexpr int HL = march_hl(RULE, T);
-    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T)) {
-        if constexpr (ALT && MAP == MAP_LAMBDA && march_has_alt(T, R))
+    if constexpr (MGeom<RULE, R, T, HL>::VALID && march_supported(RULE, T, R)) {
+        if constexpr (ALT && MAP == MAP_LAMBDA && march_has_alt(RULE, T, R))
             return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe_alt(T), march_depth(RULE, T)>;
         else
             return march_kernel<RULE, R, T, HL, MAP, FL, march_wpe(T), march_depth(RULE, T)>;

@@ -98,7 +98,8 @@ def test_tuning_defaults_and_validation():
     # march: needs whole segments, 16-byte rows, a lambda or BB map; FUSE8
     # only with march; one fuse flag at a time
     for map_, rule, r, fl in ((0, 0, 4, 32), (0, 0, 3, 33), (2, 0, 4, 33), (0, 0, 4, 1 | 64),
-                              (0, 0, 4, 33 | 8 | 64), (0, 0, 4, 33 | 2048), (0, 1, 4, 33 | 128),
+                              (0, 0, 4, 33 | 8 | 64), (0, 0, 4, 33 | 4096), (0, 0, 4, 1 | 2048),
+                              (0, 1, 3, 33 | 128),
                               (0, 0, 4, 1 | 128), (0, 0, 4, 1 | 256), (0, 0, 4, 33 | 256 | 512)):
         with pytest.raises(F.FractalError):
             F.step_tuned(map_, 10, rule, 0.2, FAKE0, FAKE1, 1, r, 256, 2, fl, stream=0)
