@@ -58,8 +58,10 @@ def _valid(rule, r, T):
     rho = 1 << r
     if rule == fi.RULE_CA:
         return T <= 16
-    hl_cells = 4 if T <= 4 else 8
-    return T <= 8 and T <= rho and hl_cells <= rho
+    # heat: 1, 2 or 4 halo lanes of 4 cells per side for up to 4, 8 or 16
+    # steps; 16-step heat launches need tiles of side >= 16
+    hl_cells = 4 if T <= 4 else (8 if T <= 8 else 16)
+    return T <= 16 and T <= rho and hl_cells <= rho
 
 
 @pytest.mark.parametrize("rule", RULES)
