@@ -106,6 +106,15 @@ def load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with paper_2004_13475_amd.build "
             "(or __graft_entry__.build()); there is no non-HIP fallback")
+    # torch carries its own copy of the HIP runtime, whose file name differs
+    # from the system one the library is linked against: loaded first, torch's
+    # copy satisfies the library's dependency, while loading the library
+    # first would put two HIP runtimes in the process (the second one to
+    # start then finds no device).  So torch, when present, is imported first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     i, u32, f, vp = ctypes.c_int, ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p
     pu32 = ctypes.POINTER(u32)
