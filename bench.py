@@ -1,29 +1,36 @@
 """Benchmark: lambda(omega)-mapped gasket steps on one MI355X.
 
-Default workload (the one `value` is quoted on): a level-14 Sierpinski
-gasket (n = 16384, 4,782,969 cells); one benchmark step = one uint8 B3/S23
+Default workload (the one `value` is quoted on): a level-16 Sierpinski
+gasket (n = 65536, 43,046,721 cells; 4.3 GB uint8 / 17.2 GB float32 per
+buffer, far beyond the caches); one benchmark step = one uint8 B3/S23
 automaton step plus one float32 heat step (alpha = 0.2), both through the
 lambda kernels at the library's default launch for the level (the measured
-fastest; --autotune times every candidate first instead).  `value` = gasket cells updated per
-second over the timed K steps (both rules), state resident in HBM, timed with
-HIP events on the stream the kernels run on.
+fastest; --autotune times every candidate first instead).  `value` = gasket
+cells updated per second over the timed K steps (both rules), state resident
+in HBM, timed with HIP events on the stream the kernels run on.
 
 Also on the same JSON line:
-  roofline      dominant kernel's algorithmic HBM GB/s vs the 8 TB/s peak
+  roofline      dominant kernel's algorithmic HBM GB/s vs the 8 TB/s peak;
+                its launch duration is the mean (and standard error) of 10
+                sub-averages, each over 4 back-to-back whole launches
+  k14           level-14 gasket (cache-assisted: its member segments fit the
+                256 MB last-level cache): per-rule rates and rooflines
   bb            bounding-box steps at the same tile size and at BB's best
-  k16           level-16 gasket (17 GB float32 per buffer): per-rule rates
-                and roofline fractions
+  lambda_vs_bb_by_k  lambda vs the bounding box at levels 10, 12, 14, 16
+                (each at its best launch), plus the level-10, 16 x 16-tile,
+                100-step automaton in microseconds per step
   batch         256 gaskets of levels 8..14, 500 steps, one graph launch vs
                 256 plain lambda_step calls
-  serve         (with --serve SECONDS) Poisson request stream, p50/p99
+  serve         Poisson request stream (--serve SECONDS, 60 by default),
+                p50/p99 latency, saturated and sequential throughput
   sw_rd         tests SW (single write) and RD (reduction), lambda vs BB
   compact       compact storage through lambda^-1 at levels 16, 18, 20
   nbb           carpet and Vicsek fractals: SW, RD, CA, lambda vs BB
   cpu_baseline  the CPU oracle on a bounded sample of the default workload
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k14|k16]
-                    [--no-cpu] [--no-bb] [--no-k16] [--no-batch]
-                    [--serve SECONDS] [--sweep-k] [--copy-calibration]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload k16|k14]
+                    [--no-cpu] [--no-bb] [--no-k14] [--no-batch] [--no-sweep]
+                    [--serve SECONDS] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -153,33 +160,47 @@ def kernel_name(tuning):
     return "march_kernel" if fl & 32 else "step_kernel"
 
 
-def roofline(rule, cells, sec_per_launch, tuning, traffic=None, kernel=""):
+def roofline(rule, cells, stats, tuning, traffic=None, kernel=""):
     """Roofline of one launch.  A launch reads and writes every member
     segment once however many steps it advances (intermediate steps stay in
     LDS or registers), so its algorithmic bytes are the per-cell figure
-    times 3^k; `sec_per_launch` is the measured average duration of a launch
-    of the tuned step count."""
+    times 3^k; `stats` is launch_stats()'s measured launch duration (mean
+    and standard error of sub-averages) of the tuned step count."""
     spl = steps_per_launch(tuning)
+    sec_per_launch = stats["mean_s"]
     alg = BYTES_PER_CELL[rule] * cells
     achieved = alg / sec_per_launch / 1e9
     rate = None if traffic is None else traffic / sec_per_launch / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_GBs": rate, "traffic_frac": None if rate is None else rate / HBM_PEAK_GBS,
+            "traffic_over_alg": None if traffic is None else traffic / alg,
             "kernel": kernel,
             "steps_per_launch": spl, "alg_bytes_per_launch": alg,
             "avg_launch_us": sec_per_launch * 1e6,
+            "avg_launch_us_stderr": stats["stderr_s"] * 1e6,
+            "timing": f"{stats['reps']} sub-averages of {stats['launches']} back-to-back "
+                      f"{spl}-step launches (HIP events on the launch stream)",
             "per_step_equivalent_GBs": alg * spl / sec_per_launch / 1e9}
 
 
-def launch_time(g, rule, steps, map_=None, tuning=None):
-    """Average launch duration of the tuned T-step kernel: HIP events around
-    a run of 2T * floor(steps / 2T) steps, which the library issues as T-step
-    launches only."""
+def launch_stats(g, rule, map_=None, tuning=None, reps=10, pairs=2):
+    """Duration of one whole launch of the tuned T-step kernel, in the
+    spirit of Section 6.2's method (a mean of sub-averages of consecutive
+    synchronised calls): `reps` sub-averages, each HIP events around 2 *
+    `pairs` back-to-back T-step launches (runs of 2T steps, which the library
+    issues as two T-step launches), after one warm-up run; mean and standard
+    error of the sub-averages, independent of the benchmark's step count."""
+    torch = g.torch
     t = tuning or g.tunings[rule]
     T = steps_per_launch(t)
-    n = 2 * T * max(1, steps // (2 * T))
-    return g.time(rule, n, map_, t) * T
+    g.run(rule, 2 * T, map_, t)
+    torch.cuda.synchronize()
+    subs = [g.time(rule, 2 * T * pairs, map_, t) * T for _ in range(reps)]
+    mean = sum(subs) / reps
+    var = sum((x - mean) ** 2 for x in subs) / (reps - 1)
+    return {"mean_s": mean, "stderr_s": math.sqrt(var / reps), "reps": reps,
+            "launches": 2 * pairs}
 
 
 def bb_tuning(g, rule, r, lam=None):
@@ -199,7 +220,7 @@ def bb_leg(g, per_launch, nsteps):
     for rule in (0, 1):
         res = {}
         lds = {}
-        for r in range(max(2, g.k - 15), 8):
+        for r in range(max(2, g.k - 12), 8):
             tb = bb_tuning(g, rule, r)
             g.run(rule, 2 * steps_per_launch(tb), F.MAP_BB, tb)
             res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
@@ -387,18 +408,22 @@ def copy_ceiling(torch, nbytes=1 << 32, reps=5):
     return 2.0 * nbytes / sec / 1e9
 
 
-def sweep_k_leg(F, torch, kmin=8, kmax=16):
-    """lambda vs bounding box per level, each at its best launch: lambda
-    autotuned, the bounding box over tile sizes 16..128 (launch order, whole
-    segments, fused steps where allowed).  Seconds per step."""
+def sweep_k_leg(F, torch, levels=(10, 12, 14, 16)):
+    """lambda vs bounding box per level (Theorem 2: the margin grows with n),
+    each at its best launch: lambda at the library's default launch for the
+    level (--autotune: the autotuner's pick), the bounding box over tile
+    sizes 16..128 (launch order, whole segments, fused steps where allowed).
+    Seconds per step over runs of 64 (level >= 15) or 256 steps.  Level 10
+    also gives the small configuration as stated (16 x 16 tiles for both
+    maps, 100 automaton steps): microseconds per step."""
     out = {}
-    for k in range(kmin, kmax + 1):
+    for k in levels:
         g = Gasket(F, torch, k)
-        g.autotune(search=True)
+        g.autotune()
         steps = 64 if k >= 15 else 256
         row = {}
         for rule in (0, 1):
-            g.run(rule, 8)
+            g.run(rule, 16)
             lam = g.time(rule, steps)
             bbs = {}
             for r in range(4, min(k, 7) + 1):
@@ -410,7 +435,24 @@ def sweep_k_leg(F, torch, kmin=8, kmax=16):
             best = min(bbs, key=bbs.get)
             row[RULE_NAME[rule]] = {"lambda_us": lam * 1e6, "lambda_tuning": list(g.tunings[rule]),
                                     "bb_us": bbs[best] * 1e6, "bb_r": best,
-                                    "speedup": bbs[best] / lam}
+                                    "speedup": bbs[best] / lam,
+                                    "bb_us_by_r": {str(r): v * 1e6 for r, v in bbs.items()}}
+        if k == 10:
+            # 16 x 16 tiles, 100 automaton steps, lambda vs BB at that tile
+            lam_t = F.get_tuning(k, 0)
+            tl = (4, lam_t[1], lam_t[2], lam_t[3]) if lam_t[0] == 4 else \
+                (4, 256, F.ORDER_NATURAL, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16)
+            tb = bb_tuning(g, 0, 4, tl)
+            res = {}
+            for name, m, t in (("lambda", F.MAP_LAMBDA, tl), ("bb", F.MAP_BB, tb)):
+                g.reseed(0)
+                g.run(0, 16, m, t)
+                g.reseed(0)
+                res[name] = g.time(0, 100, m, t)
+            row["ca_r4_100_steps"] = {"lambda_us_per_step": res["lambda"] * 1e6,
+                                      "bb_us_per_step": res["bb"] * 1e6,
+                                      "speedup": res["bb"] / res["lambda"],
+                                      "lambda_tuning": list(tl), "bb_tuning": list(tb)}
         out[str(k)] = row
         g.free()
     return out
@@ -435,18 +477,20 @@ def mfma_leg(g, steps):
     return out
 
 
-def k16_leg(F, torch, steps):
-    g = Gasket(F, torch, 16)
+def level_leg(F, torch, k, steps, label):
+    """Per-rule rates and launch rooflines at level k with the default
+    launches, plus the bounding box at lambda's tile size and at rho = 32
+    (the paper's best BB block)."""
+    g = Gasket(F, torch, k)
     g.autotune()
-    out = {"k": 16, "cells": g.cells, "steps": steps}
+    out = {"k": k, "cells": g.cells, "steps": steps, "note": label}
     for rule in (0, 1):
         g.run(rule, 16)
         sec = g.time(rule, steps)
-        rf = roofline(rule, g.cells, launch_time(g, rule, steps), g.tunings[rule],
-                      read_traffic("k16", RULE_NAME[rule]), kernel_name(g.tunings[rule]))
-        out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]),
+        rf = roofline(rule, g.cells, launch_stats(g, rule), g.tunings[rule],
+                      read_traffic(f"k{k}", RULE_NAME[rule]), kernel_name(g.tunings[rule]))
+        out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]), "lambda_us": sec * 1e6,
                                 "cells_per_s": g.cells / sec, "roofline": rf}
-    # bounding box at lambda's tile size and at rho = 32 (the paper's best)
     for rule in (0, 1):
         r = g.tunings[rule][0]
         for rr in sorted({r, 5}):
@@ -454,7 +498,6 @@ def k16_leg(F, torch, steps):
             g.run(rule, 16, F.MAP_BB, tb)
             sec = g.time(rule, max(16, steps // 2), F.MAP_BB, tb)
             out[RULE_NAME[rule]][f"bb_r{rr}_us"] = sec * 1e6
-        out[RULE_NAME[rule]]["lambda_us"] = 1e6 * g.cells / out[RULE_NAME[rule]]["cells_per_s"]
     g.free()
     return out
 
@@ -624,20 +667,63 @@ def oracle_one_thread(k=12, steps=20):
             "sample": f"level-{k} gasket, whole array: {steps} automaton steps ({sec:.1f} s)"}
 
 
+def progress(msg: str) -> None:
+    """One line per finished leg on stderr (stdout carries only the JSON)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_leg(k, alpha, bands=4, h=512, ca_steps=64, heat_steps=32, seed=2004):
+    """The oracle on a bounded sample of the level-k workload: full-width
+    bands of h rows at seeded offsets, ca_steps automaton steps and
+    heat_steps float64 heat steps on each (the same seeded initial state as
+    the GPU run); cell-updates counted over the members of each band's exact
+    interior (rows farther than the step count from a cut edge)."""
+    import numpy as np
+
+    import fractal_inputs as fi
+    import oracle
+    n = 1 << k
+    rng = np.random.Generator(np.random.PCG64(seed))
+    offs = sorted(int(v) for v in rng.integers(h, n - 2 * h, size=bands))
+    upd = 0
+    sec = 0.0
+    for y0 in offs:
+        for rule, steps in ((0, ca_steps), (1, heat_steps)):
+            st = fi.window_values(k, rule, 1, 0, y0, n, h)
+            if rule == 1:
+                st = st.astype(np.float64)
+            t0 = time.perf_counter()
+            if rule == 0:
+                oracle.ca_run(k, st, steps, 0, y0)
+            else:
+                oracle.heat_run(k, st, alpha, steps, 0, y0)
+            sec += time.perf_counter() - t0
+            rs, cs = oracle.valid_interior(k, 0, y0, n, h, steps)
+            upd += int(fi.member_mask(k, 0, y0 + rs.start, n, rs.stop - rs.start).sum()) * steps
+    return {"value": upd / sec, "unit": "cells/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"level-{k} gasket: {bands} full-width bands of {h} rows at seeded "
+                      f"offsets {offs}, {ca_steps} automaton steps and {heat_steps} float64 "
+                      f"heat steps each; {upd} member cell-updates of the exact band "
+                      f"interiors in {sec:.1f} s",
+            "cpu_model": cpu_model(), "one_thread": oracle_one_thread()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="k14", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--workload", default="k16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--no-bb", action="store_true", help="skip the bounding-box leg")
-    ap.add_argument("--no-k16", action="store_true", help="skip the level-16 leg")
+    ap.add_argument("--no-bb", action="store_true",
+                    help="skip the bounding-box, matrix-core, SW/RD and NBB legs")
+    ap.add_argument("--no-k14", action="store_true", help="skip the level-14 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-gasket batch leg")
-    ap.add_argument("--serve", type=float, default=20.0,
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip lambda vs bounding box at levels 10, 12, 14, 16")
+    ap.add_argument("--no-compact", action="store_true", help="skip the compact-storage leg")
+    ap.add_argument("--serve", type=float, default=60.0,
                     help="seconds of Poisson arrivals for the serving leg (0 = skip)")
-    ap.add_argument("--sweep-k", action="store_true",
-                    help="add lambda vs bounding box for levels 8..16 (about a minute)")
     ap.add_argument("--autotune", action="store_true",
                     help="time every launch candidate first instead of the library defaults")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -682,45 +768,42 @@ def main() -> int:
     ms_ca, ms_heat = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     total_ms = ms_ca + ms_heat
     value = 2.0 * g.cells * K / (total_ms / 1e3)
-    per_launch = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}  # seconds per step
-    dom = 1 if per_launch[1] >= per_launch[0] else 0
-    launch_sec = {r: launch_time(g, r, K) for r in (0, 1)}
-    rfs = {r: roofline(r, g.cells, launch_sec[r], g.tunings[r],
+    per_step = {0: ms_ca / K * 1e-3, 1: ms_heat / K * 1e-3}  # seconds per step
+    progress(f"timed {K} steps of each rule at level {g.k}: {total_ms:.2f} ms")
+    stats = {r: launch_stats(g, r) for r in (0, 1)}
+    # the dominant kernel: the rule whose launches take the larger share of
+    # the timed region
+    dom = 1 if per_step[1] >= per_step[0] else 0
+    rfs = {r: roofline(r, g.cells, stats[r], g.tunings[r],
                        read_traffic(args.workload, RULE_NAME[r]), kernel_name(g.tunings[r]))
            for r in (0, 1)}
-    rf = rfs[dom]
+    rf = dict(rfs[dom], rule=RULE_NAME[dom])
 
-    bb = None if args.no_bb else bb_leg(g, per_launch, max(10, min(K, 200)))
-    mfma = None if args.no_bb else mfma_leg(g, max(16, min(K, 400)))
+    bb = None if args.no_bb else bb_leg(g, per_step, max(16, min(K, 64)))
+    mfma = None if args.no_bb else mfma_leg(g, 32)
     k, cells, tunings = g.k, g.cells, dict(g.tunings)
     g.free()
-    k16 = None if (args.no_k16 or k == 16) else k16_leg(F, torch, 64)
+    progress("bounding box and matrix-core legs done")
+    k14 = None if (args.no_k14 or k == 14) else level_leg(
+        F, torch, 14, 256, "cache-assisted: the level-14 member segments (23-161 MB per step) "
+        "fit the 256 MB last-level cache")
+    sweep = None if args.no_sweep else sweep_k_leg(F, torch)
+    progress("level-14 and per-level sweep legs done")
     batch = None if args.no_batch else batch_leg(F, torch)
+    progress("batch leg done")
     serve = serve_leg(F, torch, args.serve) if args.serve > 0 else None
-    sweep = sweep_k_leg(F, torch) if args.sweep_k else None
+    progress("serving leg done")
     swrd = None if args.no_bb else {f"k{kk}": sw_rd_leg(F, torch, kk) for kk in sorted({k, 16})}
-    compact = None if args.no_k16 else compact_leg(F, torch)
+    compact = None if args.no_compact else compact_leg(F, torch)
     nbb = None if args.no_bb else nbb_leg(F, torch)
     ceiling = None if args.no_bb else copy_ceiling(torch)
+    progress("SW/RD, compact, NBB and copy legs done")
 
     cpu = None
     if not args.no_cpu:
         import numpy as np
-
-        import fractal_inputs as fi
-        import oracle
-        ck = 14
-        states = {0: fi.full_state(ck, 0, 1), 1: fi.full_state(ck, 1, 1, dtype=np.float64)}
-        nsteps = {0: 160, 1: 50}
-        tc = time.perf_counter()
-        oracle.ca_run(ck, states[0], nsteps[0])
-        oracle.heat_run(ck, states[1], g.alpha, nsteps[1])
-        dtc = time.perf_counter() - tc
-        cpu = {"value": 3 ** ck * (nsteps[0] + nsteps[1]) / dtc, "unit": "cells/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": f"level-14 gasket, whole array: {nsteps[0]} automaton steps + "
-                         f"{nsteps[1]} float64 heat steps ({dtc:.1f} s)",
-               "cpu_model": cpu_model(), "one_thread": oracle_one_thread()}
+        cpu = cpu_leg(k, float(np.float32(ALPHA)))
+        progress("oracle leg done")
 
     line = {
         "metric": "fractal cells updated/s and HBM GB/s (% peak), lambda vs BB; "
@@ -732,14 +815,13 @@ def main() -> int:
                    "n": 1 << k, "cells": cells, "tuning_ca": list(tunings[0]),
                    "tuning_heat": list(tunings[1]), "wall_s": wall},
         "roofline": rf,
-        "per_rule": {RULE_NAME[r]: {"us_per_step": per_launch[r] * 1e6,
-                                    "cells_per_s": cells / per_launch[r],
+        "per_rule": {RULE_NAME[r]: {"us_per_step": per_step[r] * 1e6,
+                                    "cells_per_s": cells / per_step[r],
                                     "steps_per_launch": steps_per_launch(tunings[r]),
                                     "roofline": rfs[r]}
                      for r in (0, 1)},
-        "bb": bb, "mfma_lambda": mfma, "k16": k16, "batch": batch, "serve": serve,
-        "sw_rd": swrd, "compact": compact, "nbb": nbb,
-        "lambda_vs_bb_by_k": sweep,
+        "bb": bb, "mfma_lambda": mfma, "k14": k14, "lambda_vs_bb_by_k": sweep,
+        "batch": batch, "serve": serve, "sw_rd": swrd, "compact": compact, "nbb": nbb,
         "device_copy_GBs": ceiling,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_hash(),
