@@ -276,6 +276,24 @@ int fractal_reduce_workspace(int k, int r, size_t *bytes);
 int fractal_reduce(int map, int k, int r, int rule, const void *d_buf,
                    void *d_work, size_t work_bytes, void *d_out, void *stream);
 
+/* fractal_reduce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, bit for bit, with the slots and tree partials
+ * in a static scratch array of 16 MiB per device instead of a caller
+ * workspace, so k - r <= 13 (larger block levels fail with E_INVAL and a
+ * message naming fractal_reduce).  Nothing is allocated and nothing is
+ * freed: the scratch is part of the loaded code object, one copy per device,
+ * held until the process ends; its address is looked up once per device, on
+ * the first call made with that device current.  Every call on a device
+ * shares that device's scratch, and each call writes every slot it reads,
+ * so nothing carries over from an earlier call; calls that overlap in time
+ * on one device (different streams, or different host threads without
+ * ordering) race on the scratch and give undefined results -- order them on
+ * one stream.  d_out: 8 bytes of device memory, 8-byte aligned.  Other
+ * arguments and errors as fractal_reduce. */
+int fractal_reduce_noalloc(int map, int k, int r, int rule, const void *d_buf,
+                           void *d_out, void *stream);
+
 /* Compact storage through lambda^-1 (the compact manipulation that Section 7
  * names as future work): a state of level k with tiles of side rho = 2^r
  * keeps only its 3^(k-r) non-empty tiles.  Tile L (0 <= L < 3^(k-r)) is the

@@ -11,5 +11,6 @@ from ._lib import (  # noqa: F401
     NBB_XFRACTAL, NBB_HFRACTAL, NBB_CANTOR, nbb_builtin, nbb_make, nbb_lambda_map,
     nbb_single_write, nbb_reduce_workspace, nbb_reduce, nbb_ca_step,
     exported_symbols, get_tuning, grid_dims, lambda_map, lambda_map_mfma,
-    lambda_map_tiles, lambda_step, lambda_step_mfma, load, now, reduce, reduce_workspace, seed_fill, set_tuning,
+    lambda_map_tiles, lambda_step, lambda_step_mfma, load, now, reduce, reduce_noalloc, reduce_workspace,
+    seed_fill, set_tuning,
     single_write, step_tuned, tuning_load, tuning_save)

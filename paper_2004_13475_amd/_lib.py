@@ -32,7 +32,7 @@ EXPORTED = [
     "fractal_get_tuning", "fractal_set_tuning", "fractal_tuning_save", "fractal_tuning_load",
     "fractal_batch_workspace", "fractal_batch_step",
     "fractal_single_write", "fractal_reduce_workspace", "fractal_reduce",
-    "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
+    "fractal_reduce_noalloc", "fractal_compact_bytes", "fractal_pack", "fractal_unpack", "fractal_compact_seed_fill",
     "fractal_compact_step", "fractal_nbb_builtin", "fractal_nbb_lambda_map",
     "fractal_nbb_single_write", "fractal_nbb_reduce_workspace", "fractal_nbb_reduce",
     "fractal_nbb_ca_step",
@@ -139,6 +139,7 @@ def load():
         "fractal_single_write": ([i, i, i, i, u32, vp, vp], i),
         "fractal_reduce_workspace": ([i, i, ctypes.POINTER(ctypes.c_size_t)], i),
         "fractal_reduce": ([i, i, i, i, vp, vp, ctypes.c_size_t, vp, vp], i),
+        "fractal_reduce_noalloc": ([i, i, i, i, vp, vp, vp], i),
         "fractal_compact_bytes": ([i, i, i, ctypes.POINTER(ctypes.c_size_t)], i),
         "fractal_pack": ([i, i, i, vp, vp, vp], i),
         "fractal_unpack": ([i, i, i, vp, vp, vp], i),
@@ -339,6 +340,14 @@ def reduce(map_, k, r, rule, buf, work, out, stream=None, work_bytes=None):
     nbytes = _nbytes(work, work_bytes, "reduce workspace")
     return _check(load().fractal_reduce(map_, k, r, rule, _ptr(buf), _ptr(work), nbytes,
                                         _ptr(out), _stream(stream)))
+
+
+def reduce_noalloc(map_, k, r, rule, buf, out, stream=None):
+    """Test RD as `reduce`, with the library's static per-device scratch in
+    place of a caller workspace (nothing is allocated; k - r <= 13; calls
+    that overlap on one device race on that scratch)."""
+    return _check(load().fractal_reduce_noalloc(map_, k, r, rule, _ptr(buf), _ptr(out),
+                                                _stream(stream)))
 
 
 def compact_bytes(k, r, rule) -> int:

@@ -11,6 +11,8 @@
 // on which map dispatched a tile or when, so lambda and BB agree bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_map.hpp"
 #include "device_march.hpp"
 #include "internal.hpp"
@@ -333,43 +335,89 @@ static int launch_swrd(SwRdFn fn, int rule, int r, const SwRdArgs &a, hipStream_
 }
 
 // Sizes of the summation tree's levels: n_0 slots, then ceil(n_i / 4096)
-// until one value remains (that one is the result).
-static std::vector<uint64_t> tree_levels(uint64_t n0)
+// until one value remains (that one is the result).  A fixed-size record:
+// 4096-ary levels over at most 3^15 slots take four sizes.
+struct TreeLevels {
+    uint64_t n[8];
+    int count;
+};
+
+static TreeLevels tree_levels(uint64_t n0)
 {
-    std::vector<uint64_t> lv{n0};
-    while (lv.back() > 1)
-        lv.push_back((lv.back() + 4095) / 4096);
-    if (lv.size() == 1)
-        lv.push_back(1); // one slot still takes one pass
+    TreeLevels lv{};
+    lv.n[0] = n0;
+    lv.count = 1;
+    while (lv.n[lv.count - 1] > 1 && lv.count < 8) {
+        lv.n[lv.count] = (lv.n[lv.count - 1] + 4095) / 4096;
+        ++lv.count;
+    }
+    if (lv.count == 1)
+        lv.n[lv.count++] = 1; // one slot still takes one pass
     return lv;
 }
 
 uint64_t reduce_tree_words(uint64_t n0)
 {
-    const std::vector<uint64_t> lv = tree_levels(n0);
+    const TreeLevels lv = tree_levels(n0);
     uint64_t words = 0;
-    for (size_t i = 0; i + 1 < lv.size(); ++i)
-        words += lv[i];
+    for (int i = 0; i + 1 < lv.count; ++i)
+        words += lv.n[i];
     return words;
 }
 
 int launch_reduce_tree(uint64_t *work, uint64_t n0, void *d_out, bool f64, hipStream_t s)
 {
-    const std::vector<uint64_t> lv = tree_levels(n0);
+    const TreeLevels lv = tree_levels(n0);
     uint64_t *in = work;
-    for (size_t i = 0; i + 1 < lv.size(); ++i) {
-        uint64_t *out = (i + 2 == lv.size()) ? static_cast<uint64_t *>(d_out) : in + lv[i];
+    for (int i = 0; i + 1 < lv.count; ++i) {
+        uint64_t *out = (i + 2 == lv.count) ? static_cast<uint64_t *>(d_out) : in + lv.n[i];
         if (f64)
-            hipLaunchKernelGGL(tree_kernel<true>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
-                               lv[i], out);
+            hipLaunchKernelGGL(tree_kernel<true>, dim3((unsigned)lv.n[i + 1]), dim3(256), 0, s, in,
+                               lv.n[i], out);
         else
-            hipLaunchKernelGGL(tree_kernel<false>, dim3((unsigned)lv[i + 1]), dim3(256), 0, s, in,
-                               lv[i], out);
+            hipLaunchKernelGGL(tree_kernel<false>, dim3((unsigned)lv.n[i + 1]), dim3(256), 0, s, in,
+                               lv.n[i], out);
         int rc = hip_error(hipGetLastError(), "reduction tree launch");
         if (rc)
             return rc;
         in = out;
     }
+    return FRACTAL_OK;
+}
+
+// Workspace of fractal_reduce_noalloc: one per device, allocated with the
+// code object and held until the process ends.  Host code never uses this
+// name as an address (on the host it is only a stand-in for the symbol):
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) uint64_t scratch[kNoallocScratchBytes / 8];
+
+constexpr int kNoallocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t *g_scratch_ptr[kNoallocMaxDevices];
+
+// The calling thread's current device's copy of `scratch`, looked up on the
+// first call on that device.
+static int noalloc_scratch(uint64_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kNoallocMaxDevices)
+        return set_error(FRACTAL_E_DEVICE, "device %d beyond the %d devices the scratch table holds",
+                         dev, kNoallocMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return set_error(FRACTAL_E_DEVICE, "scratch has no device address");
+        g_scratch_ptr[dev] = static_cast<uint64_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return FRACTAL_OK;
 }
 
@@ -435,6 +483,40 @@ int fractal_reduce(int map, int k, int r, int rule, const void *d_buf, void *d_w
     if ((rc = launch_reduce_tree(w, pow3_u64(k - r), d_out, rule == FRACTAL_RULE_HEAT, s)))
         return rc;
     return FRACTAL_OK;
+}
+
+int fractal_reduce_noalloc(int map, int k, int r, int rule, const void *d_buf, void *d_out,
+                           void *stream)
+{
+    int rc = check_swrd(map, k, r, rule, d_buf);
+    if (rc)
+        return rc;
+    size_t need = 0;
+    if ((rc = fractal_reduce_workspace(k, r, &need)))
+        return rc;
+    if (need > kNoallocScratchBytes)
+        return set_error(FRACTAL_E_INVAL,
+                         "k=%d r=%d needs %zu bytes of scratch, the static scratch holds %zu "
+                         "(k - r <= 13); use fractal_reduce with a workspace",
+                         k, r, need, kNoallocScratchBytes);
+    if (!d_out || reinterpret_cast<uintptr_t>(d_out) % 8)
+        return set_error(FRACTAL_E_INVAL, "output must be non-null and 8-byte aligned");
+    uint64_t *w = nullptr;
+    if ((rc = noalloc_scratch(&w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SwRdArgs a;
+    a.buf = static_cast<uint8_t *>(const_cast<void *>(d_buf));
+    a.k = k;
+    a.rb = k - r;
+    a.total = map == MAP_BB ? (uint64_t)1 << (2 * (k - r)) : pow3_u64(k - r);
+    a.value = 0;
+    a.slots = w;
+    // every slot is written by the tile it belongs to before the tree reads
+    // it, so the scratch needs no clearing between calls
+    if ((rc = launch_swrd(swrd_pick<OP_RD>(map, rule, r), rule, r, a, s)))
+        return rc;
+    return launch_reduce_tree(w, pow3_u64(k - r), d_out, rule == FRACTAL_RULE_HEAT, s);
 }
 
 } // extern "C"
