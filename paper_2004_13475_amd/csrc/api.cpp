@@ -120,26 +120,35 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured on MI355X, all on the register-march engine with omega
-// in the curve order split over the dies.  Level >= 15: automaton 64 x 64
-// tiles with sixteen steps per launch, heat 16 x 16 tiles with eight, both
-// with non-temporal stores.  Below: automaton and heat 16 x 16 tiles, eight
-// steps, plain stores (the state stays in the last-level cache); level 14
-// automaton: sixteen steps on stacks of two tiles.
+// launches measured on MI355X (whole launches, levels 12 to 16), all on the
+// register-march engine with sixteen steps per launch:
+//   automaton  level >= 15: 64 x 64 tiles, non-temporal stores;
+//              level 14: 16 x 16 tiles on stacks of two (the 2T halo rows
+//              paid once per two tiles); below: 16 x 16 tiles;
+//   heat       level >= 16: 64 x 64 tiles, non-temporal stores; level 15:
+//              32 x 32 tiles on stacks of two, non-temporal stores; levels
+//              13 and 14: 32 x 32 tiles; below: 16 x 16 tiles (eight steps
+//              where the tile is narrower than 16 cells).
+// Non-temporal stores only from level 15: below it the state stays in the
+// last-level cache between launches.
 static fractal_tuning builtin_default(int k, int rule)
 {
-    const bool big = k >= 15;
-    const int r = clamp_r(k, (big && rule == FRACTAL_RULE_CA) ? 6 : 4);
+    const bool ca = rule == FRACTAL_RULE_CA;
+    int want_r = 4;
+    if (ca)
+        want_r = k >= 15 ? 6 : 4;
+    else
+        want_r = k >= 16 ? 6 : (k >= 13 ? 5 : 4);
+    const int r = clamp_r(k, want_r);
     fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
-    if (t.flags & FRACTAL_FLAG_MARCH)
+    if (t.flags & FRACTAL_FLAG_MARCH) {
+        const bool fuse16 = ca || r >= 4; // heat: 16 steps need tiles of side >= 16
         t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |
-                  ((big && rule == FRACTAL_RULE_CA) ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8) |
-                  (big ? FRACTAL_FLAG_NT_STORE : 0);
-    // level 14 automaton: 16 steps a launch on stacks of two 16 x 16 tiles
-    // (the halo rows of 16 steps are then paid once per two tiles)
-    if (k == 14 && rule == FRACTAL_RULE_CA && r == 4 && (t.flags & FRACTAL_FLAG_MARCH))
-        t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE16 |
-                  FRACTAL_FLAG_STACK2;
+                  (fuse16 ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8) |
+                  (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
+        if (r == want_r && ((ca && k == 14) || (!ca && k == 15)))
+            t.flags |= FRACTAL_FLAG_STACK2;
+    }
     return t;
 }
 
