@@ -82,6 +82,7 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
 void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
 {
     classes_.clear();
+    launches_.assign(items.size(), 0);
     slots_ = 0;
     std::map<std::tuple<int, int, int, int>, std::vector<size_t>> groups;
     for (size_t i = 0; i < items.size(); ++i) {
@@ -101,13 +102,15 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
             int cnt[kMaxListsPerItem] = {0, 0, 0, 0};
             const int steps = items[i].steps;
             if (march) {
-                march_split(steps, T, cnt);
+                march_split(steps, T, cnt, !items[i].any_parity);
             } else {
                 const int f = T > 1 ? 2 * (steps / (2 * T)) : 0;
                 cnt[0] = f;
                 cnt[T > 1 ? (T == 2 ? 1 : 2) : 0] += steps - T * f;
             }
             std::copy(cnt, cnt + kMaxListsPerItem, counts[i].begin());
+            for (int j = 0; j < kMaxListsPerItem; ++j)
+                launches_[i] += cnt[j];
         }
         std::vector<int> before(items.size(), 0); // launches in earlier lists
         for (int j = 0; j < kMaxListsPerItem && (T >> j) >= 1; ++j) {

@@ -49,13 +49,13 @@ constexpr int march_hl(int rule, int T)
     return T <= (rule == RULE_CA ? 16 : 4) ? 1 : (T <= 8 ? 2 : 4);
 }
 // Step counts a march launch takes: up to 16 for the automaton (one chunk
-// of halo); up to 8 for heat, and 16 on tiles of side >= 16 (four halo
-// lanes per side: narrower tiles would be mostly halo).
+// of halo); up to 8 for heat, and 10, 12 or 16 on tiles of side >= 16 (four
+// halo lanes per side: narrower tiles would be mostly halo).
 constexpr bool march_supported(int rule, int T, int R)
 {
-    return T <= 8 || (T == 16 && (rule == RULE_CA || R >= 4));
+    return T <= 8 || (T <= 16 && (rule == RULE_CA || R >= 4));
 }
-constexpr int march_wpe(int T) { return T >= 16 ? 2 : (T >= 8 ? 3 : 1); }
+constexpr int march_wpe(int T) { return T >= 10 ? 2 : (T >= 8 ? 3 : 1); }
 // The other occupancy the autotuner may try for the long launches: 3
 // wavefronts per SIMD for the automaton's 16 steps (fewer registers per
 // lane), 2 for 8 steps (more registers: room for the row state of the wider

@@ -99,6 +99,9 @@ typedef void (*MarchFn)(MarchArgs);
 // Kernel for (map, rule, r, T steps, non-temporal stores); nullptr if none.
 // alt: the kernel compiled for the other occupancy where one exists.
 MarchFn pick_march(int map, int rule, int r, int T, bool nt, bool alt);
+// Lambda-map kernels of 10 or 12 steps (the sizes between 8 and 16 that
+// even out a sixteen-step tuning's launches); nullptr if none.
+MarchFn pick_march_mid(int rule, int r, int T, bool nt);
 // Tiles one wavefront handles (0: no march kernel for this shape).
 int march_tiles_per_wave(int rule, int r, int T);
 int march_band_log(int rule, int r, int T, uint64_t tiles);
@@ -145,6 +148,10 @@ struct BatchItem {
     float alpha;
     uint8_t *buf0, *buf1;
     fractal_tuning tuning; // tile launch (r, threads, flags) for this item
+    // march classes: take as many T-step launches as fit and the rest in
+    // powers of two, whatever the parity of their count (the caller tracks
+    // which buffer holds the state: BatchPlan::launches gives the count)
+    bool any_parity = false;
 };
 
 // Instances grouped by launch class (rule, r, threads, step flags).  A class
@@ -153,7 +160,8 @@ struct BatchItem {
 // T-step launches and single steps for the rest; march classes (which have
 // every power of two up to T) take as many T-step launches as fit, the rest
 // in powers of two, and split the largest launch in two where the count's
-// parity differs from the steps' (so the result lands in buf[steps & 1]).
+// parity differs from the steps' (so the result lands in buf[steps & 1]),
+// except for items marked any_parity.
 // A class keeps one list per launch size, largest first, each sorted by how
 // many launches of that size an item makes, so the items taking part in any
 // launch form a prefix of the list.  Launch slot t runs, per class, launch
@@ -167,6 +175,8 @@ class BatchPlan {
     int launch_slot(const BatchEntry *d_table, int t, bool persistent, hipStream_t s) const;
     int slots() const { return slots_; }
     size_t entries() const { return entries_; }
+    // Launches item i takes part in (each swaps its two buffers once).
+    int launches(size_t i) const { return i < launches_.size() ? launches_[i] : 0; }
 
   private:
     struct List {
@@ -181,13 +191,16 @@ class BatchPlan {
         std::vector<List> lists;
     };
     std::vector<Class> classes_;
+    std::vector<int> launches_;
     int slots_ = 0;
     size_t entries_ = 0;
 };
 
 // Launch sizes of `steps` steps on the march engine with at most Tmax steps
-// per launch: counts[j] launches of Tmax >> j steps.
-void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem]);
+// per launch: counts[j] launches of Tmax >> j steps, as many Tmax-step
+// launches as fit and the rest in powers of two; with even_parity, a count
+// of the parity of `steps` (the largest launch split in two where needed).
+void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem], bool even_parity = true);
 
 // Deterministic sum of n0 8-byte slots (uint64, or float64 if f64) at the
 // start of `work` into *d_out by a fixed 4096-ary tree; `work` must hold

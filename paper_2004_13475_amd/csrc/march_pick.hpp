@@ -65,4 +65,32 @@ static MarchFn march_pick_rule(int map, int r, int T, bool nt, bool alt)
     return nullptr;
 }
 
+// Lambda-map kernels of 10 and 12 steps per launch, tiles of side 16, 32
+// and 64: the launch sizes between 8 and 16 that let a call of a
+// sixteen-step tuning split its steps evenly.
+template <int RULE, int FL>
+static MarchFn march_pick_mid_r(int r, int T)
+{
+    switch (r) {
+#define FRACTAL_MARCH_MID_R(RR)                                                                    \
+    case RR:                                                                                       \
+        switch (T) {                                                                               \
+        case 10: return march_fn<MAP_LAMBDA, RULE, RR, 10, FL, false>();                           \
+        case 12: return march_fn<MAP_LAMBDA, RULE, RR, 12, FL, false>();                           \
+        default: return nullptr;                                                                   \
+        }
+        FRACTAL_MARCH_MID_R(4)
+        FRACTAL_MARCH_MID_R(5)
+        FRACTAL_MARCH_MID_R(6)
+#undef FRACTAL_MARCH_MID_R
+    default: return nullptr;
+    }
+}
+
+template <int RULE>
+static MarchFn march_pick_mid_rule(int r, int T, bool nt)
+{
+    return nt ? march_pick_mid_r<RULE, TILE_NT_STORE>(r, T) : march_pick_mid_r<RULE, 0>(r, T);
+}
+
 } // namespace fractal

@@ -46,7 +46,8 @@ class SteadyClock : public ServeClock {
 class HipExecutor : public ServeExecutor {
   public:
     HipExecutor(uint8_t *arena, size_t bytes, int max_slots, hipStream_t s)
-        : arena_(arena), arena_bytes_(bytes), max_slots_(max_slots), stream_(s)
+        : arena_(arena), arena_bytes_(bytes), max_slots_(max_slots), stream_(s),
+          flips_(max_slots > 0 ? max_slots : 0, 0), final_(max_slots > 0 ? max_slots : 0, 0)
     {
         table_bytes_ = sizeof(BatchEntry) * kMaxListsPerItem * (size_t)(max_slots + 1);
         table_off_[0] = 0;
@@ -113,8 +114,9 @@ class HipExecutor : public ServeExecutor {
         return arena_bytes_ > state_base_ ? arena_bytes_ - state_base_ : 0;
     }
 
-    int init_slot(int, const ServeSlot &s, const fractal_request &rq) override
+    int init_slot(int slot, const ServeSlot &s, const fractal_request &rq) override
     {
+        flips_[slot] = 0;
         const size_t sb = state_bytes(s.k, s.rule);
         uint8_t *b0 = buf(s, 0), *b1 = buf(s, 1);
         int rc = hip_error(hipMemsetAsync(b1, 0, sb, init_stream_), "state clear");
@@ -145,13 +147,18 @@ class HipExecutor : public ServeExecutor {
         BatchEntry *dt = reinterpret_cast<BatchEntry *>(arena_ + table_off_[parity_]);
         std::vector<BatchItem> bi;
         bi.reserve(items.size());
+        // an iteration's launches need not come in the parity of its steps
+        // (sixteen steps run as one launch, not two of eight): each slot's
+        // count of launches so far says which buffer holds its state
         for (const ServeIterItem &it : items) {
             const ServeSlot &s = it.s;
-            bi.push_back(BatchItem{s.k, s.rule, it.steps, s.done, s.alpha, buf(s, 0), buf(s, 1),
-                                   batch_item_tuning(s.k, s.rule, nullptr)});
+            bi.push_back(BatchItem{s.k, s.rule, it.steps, flips_[it.slot], s.alpha, buf(s, 0),
+                                   buf(s, 1), batch_item_tuning(s.k, s.rule, nullptr), true});
         }
         BatchPlan plan;
         plan.build(bi, ht);
+        for (size_t i = 0; i < items.size(); ++i)
+            flips_[items[i].slot] += plan.launches(i);
         int rc = hip_error(hipMemcpyAsync(dt, ht, sizeof(BatchEntry) * plan.entries(),
                                           hipMemcpyHostToDevice, stream_),
                            "table upload");
@@ -165,7 +172,8 @@ class HipExecutor : public ServeExecutor {
 
     int finish(int slot, const ServeSlot &s, uint64_t *token) override
     {
-        const uint8_t *final_buf = buf(s, s.steps & 1);
+        final_[slot] = flips_[slot] & 1;
+        const uint8_t *final_buf = buf(s, final_[slot]);
         unsigned long long *dsum = sums() + slot;
         int rc = hip_error(hipMemsetAsync(dsum, 0, sizeof *dsum, stream_), "sum clear");
         if (!rc)
@@ -191,7 +199,7 @@ class HipExecutor : public ServeExecutor {
         int rc = hip_error(hipEventSynchronize(ev), "wait for slot");
         (void)hipEventDestroy(ev);
         if (!rc && h_out)
-            rc = hip_error(hipMemcpyAsync(h_out, buf(s, s.steps & 1), state_bytes(s.k, s.rule),
+            rc = hip_error(hipMemcpyAsync(h_out, buf(s, final_[slot]), state_bytes(s.k, s.rule),
                                           hipMemcpyDeviceToHost, copy_stream_),
                            "state download");
         if (!rc)
@@ -233,6 +241,10 @@ class HipExecutor : public ServeExecutor {
     BatchEntry *host_table_[2] = {nullptr, nullptr};
     hipEvent_t table_ev_[2] = {nullptr, nullptr};
     unsigned long long *host_sums_ = nullptr;
+    // per slot: launches enqueued so far (the state is in buf[flips & 1]),
+    // and the buffer of the final state once the slot is finished (set by
+    // the scheduler thread in finish, read by the retire thread in collect)
+    std::vector<int> flips_, final_;
 };
 
 // The executor, the clock, the scheduler core and its two threads.

@@ -1,7 +1,12 @@
 // step_march.hip -- host launcher of the register-march step kernels
 // (lambda and bounding-box maps); the kernels are instantiated per rule in
-// step_march_ca.hip and step_march_heat.hip.
+// step_march_ca.hip and step_march_heat.hip, those of 10 and 12 steps in
+// step_march_mid_ca.hip and step_march_mid_heat.hip.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "device_march.hpp"
 #include "internal.hpp"
@@ -15,6 +20,14 @@ MarchFn pick_march(int map, int rule, int r, int T, bool nt, bool alt)
 {
     return rule == FRACTAL_RULE_CA ? pick_march_ca(map, r, T, nt, alt)
                                    : pick_march_heat(map, r, T, nt, alt);
+}
+
+MarchFn pick_march_mid_ca(int r, int T, bool nt);
+MarchFn pick_march_mid_heat(int r, int T, bool nt);
+
+MarchFn pick_march_mid(int rule, int r, int T, bool nt)
+{
+    return rule == FRACTAL_RULE_CA ? pick_march_mid_ca(r, T, nt) : pick_march_mid_heat(r, T, nt);
 }
 
 int march_tiles_per_wave(int rule, int r, int T)
@@ -42,10 +55,11 @@ int march_band_log(int rule, int r, int T, uint64_t tiles)
 }
 
 // As many Tmax-step launches as fit, the rest in powers of two; if that
-// count's parity differs from steps', the largest launch is split in two
-// halves (the result then lands in buf[steps & 1]; splitting the largest
-// costs least, since a launch's time grows with its step count).
-void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem])
+// count's parity differs from steps' (and even_parity asks for it), the
+// largest launch is split in two halves (the result then lands in
+// buf[steps & 1]; splitting the largest costs least, since a launch's time
+// grows with its step count).
+void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem], bool even_parity)
 {
     for (int j = 0; j < kMaxListsPerItem; ++j)
         counts[j] = 0;
@@ -56,7 +70,7 @@ void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem])
             ++counts[j];
             ++total;
         }
-    if ((total & 1) != (steps & 1)) {
+    if (even_parity && (total & 1) != (steps & 1)) {
         for (int j = 0; j < kMaxListsPerItem - 1 && (Tmax >> j) >= 2; ++j)
             if (counts[j] > 0) {
                 --counts[j];
@@ -66,18 +80,101 @@ void march_split(int steps, int Tmax, int (&counts)[kMaxListsPerItem])
     }
 }
 
+// Launch sizes of a sixteen-step lambda tuning: a launch reads and writes
+// the state's member segments whatever its step count, so a short launch
+// costs about as much as a launch of ten steps (the level-16 automaton and
+// heat launches of 1 to 4 steps take 55-65% of a sixteen-step one, those of
+// ten steps 80%).  With a cost of max(10, T) per launch of T steps, the plan
+// is the cheapest set of launch sizes from `sizes` that adds up to `steps`
+// with a launch count of the parity of `steps` (the result lands in
+// buf[steps & 1]): 20 steps run as 10 + 10 rather than 16 + 4.  All but the
+// last 48-63 steps run as sixteen-step launches; the rest is a small exact
+// search.
+static void march_plan_cost(int steps, const std::vector<int> &sizes, std::vector<int> &plan)
+{
+    if (steps <= 0)
+        return;
+    const int q = steps / 16 > 3 ? steps / 16 - 3 : 0;
+    for (int i = 0; i < q; ++i)
+        plan.push_back(16);
+    const int rem = steps - 16 * q;
+    const int INF = 1 << 28;
+    // best[s][p]: least cost of launches adding up to s steps, count parity p
+    std::vector<int> best(2 * (rem + 1), INF), pick(2 * (rem + 1), 0);
+    best[0] = 0;
+    for (int t = 1; t <= rem; ++t)
+        for (int p = 0; p < 2; ++p)
+            for (int T : sizes) {
+                if (T > t || best[2 * (t - T) + (p ^ 1)] >= INF)
+                    continue;
+                const int c = best[2 * (t - T) + (p ^ 1)] + (T > 10 ? T : 10) * 64 + 1;
+                if (c < best[2 * t + p]) {
+                    best[2 * t + p] = c;
+                    pick[2 * t + p] = T;
+                }
+            }
+    int p = (steps & 1) ^ (q & 1), t = rem;
+    std::vector<int> tail;
+    while (t > 0 && best[2 * t + p] < INF) {
+        const int T = pick[2 * t + p];
+        tail.push_back(T);
+        t -= T;
+        p ^= 1;
+    }
+    std::sort(tail.begin(), tail.end(), [](int x, int y) { return x > y; });
+    plan.insert(plan.end(), tail.begin(), tail.end());
+}
+
+// The runtime loads a source file's kernels onto a device the first time
+// one of them runs (about a millisecond each).  A call's launches can use
+// the kernels of several sources (the 10- and 12-step kernels sit apart
+// from the others), so the first call on a device loads every march source
+// of both rules up front instead of in the middle of a run.
+static void preload_march_code()
+{
+    static std::mutex mu;
+    static bool done[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev])
+        return;
+    done[dev] = true;
+    for (int rule : {FRACTAL_RULE_CA, FRACTAL_RULE_HEAT}) {
+        const MarchFn fns[] = {pick_march(MAP_LAMBDA, rule, 4, 1, false, false),
+                               pick_march_mid(rule, 4, 10, false)};
+        for (MarchFn fn : fns) {
+            hipFuncAttributes attr;
+            if (fn)
+                (void)hipFuncGetAttributes(&attr, (const void *)fn); // loads its code object
+        }
+    }
+}
+
 int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s)
 {
+    preload_march_code();
     const int Tmax = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
     const bool alt = (t.flags & FRACTAL_FLAG_OCC_ALT) != 0;
-    int counts[kMaxListsPerItem];
-    march_split(steps, Tmax, counts);
     std::vector<int> plan;
-    for (int j = 0; j < kMaxListsPerItem; ++j)
-        for (int c = 0; c < counts[j]; ++c)
-            plan.push_back(Tmax >> j);
+    if (map == MAP_LAMBDA && Tmax == 16) {
+        std::vector<int> sizes{16};
+        for (int T : {12, 10})
+            if (pick_march_mid(rule, t.r, T, nt))
+                sizes.push_back(T);
+        for (int T : {8, 4, 2, 1})
+            sizes.push_back(T);
+        march_plan_cost(steps, sizes, plan);
+    } else {
+        int counts[kMaxListsPerItem];
+        march_split(steps, Tmax, counts);
+        for (int j = 0; j < kMaxListsPerItem; ++j)
+            for (int c = 0; c < counts[j]; ++c)
+                plan.push_back(Tmax >> j);
+    }
     const int rb = k - t.r;
     const uint64_t tiles = map == MAP_BB ? (uint64_t)1 << (2 * rb) : pow3_u64(rb);
     MarchArgs a;
@@ -94,7 +191,8 @@ int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     const int wpg = t.threads / 64;
     for (size_t i = 0; i < plan.size(); ++i) {
         const int T = plan[i];
-        MarchFn fn = pick_march(map, rule, t.r, T, nt, alt);
+        MarchFn fn = (T == 10 || T == 12) ? pick_march_mid(rule, t.r, T, nt)
+                                          : pick_march(map, rule, t.r, T, nt, alt);
         const int P = march_tiles_per_wave(rule, t.r, T);
         if (!fn || P < 1)
             return set_error(FRACTAL_E_INVAL, "no march kernel for rule %d r %d T %d", rule, t.r, T);

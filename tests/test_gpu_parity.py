@@ -239,6 +239,41 @@ def test_march_launches(rule, map_):
 
 
 @pytest.mark.parametrize("rule", RULES)
+def test_march_launch_plan_every_step_count(rule):
+    """Sixteen-step lambda tunings split a call into launches of 16, 12, 10,
+    8, 4, 2 and 1 steps by a cost model (20 -> 10 + 10, 30 -> 10 + 10 + 8 +
+    2), with a launch count of the parity of the step count.  Every step
+    count 1..40 at every tile size (the 10- and 12-step kernels exist for
+    sides 16..64; side 128 keeps powers of two), single tiles and stacks of
+    two, both store kinds, gives the same bits as one step per launch; level
+    9 also against the oracle."""
+    torch = torch_dev()
+    k = 9
+    init = fi.window_values(k, rule, 77)
+    cur, nxt = to_device(init), zeros_state(k, rule)
+    refs = {0: cur.view(torch.uint8).clone()}
+    for t in range(1, 41):
+        F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, cur, nxt, 1, 4, 64, 2, F.FLAG_SEGMENTS)
+        cur, nxt = nxt, cur
+        _sync()
+        refs[t] = cur.view(torch.uint8).clone()
+    for r in range(4, 8):
+        for extra in (0, F.FLAG_NT_STORE, F.FLAG_STACK2):
+            fl = F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16 | extra
+            for steps in range(1, 41):
+                a0, a1 = to_device(init), zeros_state(k, rule)
+                F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, a0, a1, steps, r, 256, 2, fl)
+                _sync()
+                fa = a0 if steps % 2 == 0 else a1
+                assert torch.equal(fa.view(torch.uint8), refs[steps]), (r, extra, steps)
+    ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 27)
+    a0, a1 = to_device(init), zeros_state(k, rule)
+    F.lambda_step(k, F.R_AUTO, rule, ALPHA, a0, a1, 27)
+    _sync()
+    assert_match(k, rule, a1.cpu().numpy(), ref, "even split, 27 steps")
+
+
+@pytest.mark.parametrize("rule", RULES)
 def test_march_stacks(rule):
     """Stacks of up to 2, 4 or 8 tiles (each class of equal column runs a
     smaller gasket of stacks under lambda) give the same bits as one step
