@@ -59,7 +59,8 @@ AUTOTUNE = False  # set by --autotune
 RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
               "device_march.hpp", "march_pick.hpp", "step_march.hip", "step_march_ca.hip",
-              "step_march_heat.hip"]
+              "step_march_heat.hip", "step_march_mid_ca.hip", "step_march_mid_heat.hip",
+              "block_heat.hip"]
 
 
 def kernel_hash() -> str:
@@ -157,7 +158,7 @@ def steps_per_launch(tuning):
 def kernel_name(tuning):
     """Name of the step kernel template a tuning launches."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    return "march_kernel" if fl & 32 else "step_kernel"
+    return "march_kernel" if fl & 32 else ("block_heat_kernel" if fl & 4096 else "step_kernel")
 
 
 def roofline(rule, cells, stats, tuning, traffic=None, kernel=""):
@@ -209,9 +210,14 @@ def bb_tuning(g, rule, r, lam=None):
     launch with whole segments."""
     t = lam or g.tunings[rule]
     fl = t[3]
+    if fl & g.F.FLAG_BLOCK and r != 6:
+        # the block engine takes 64 x 64 tiles only: the march at other sizes
+        fl = (fl & ~g.F.FLAG_BLOCK) | g.F.FLAG_MARCH
+    if fl & g.F.FLAG_FUSE16 and rule == 1 and r < 4:
+        fl = (fl & ~g.F.FLAG_FUSE16) | g.F.FLAG_FUSE8  # heat: 16 steps need 16-cell tiles
     if (1 << r) * (1 if rule == 0 else 4) < 16:
         fl = 3
-    return (r, 256 if (r >= 3 or fl & 32) else 64, g.F.ORDER_NATURAL, fl)
+    return (r, 256 if (r >= 3 or fl & 32 or fl & g.F.FLAG_BLOCK) else 64, g.F.ORDER_NATURAL, fl)
 
 
 def bb_leg(g, per_launch, nsteps):
@@ -224,7 +230,7 @@ def bb_leg(g, per_launch, nsteps):
             tb = bb_tuning(g, rule, r)
             g.run(rule, 2 * steps_per_launch(tb), F.MAP_BB, tb)
             res[r] = g.time(rule, nsteps, F.MAP_BB, tb)
-            if tb[3] & F.FLAG_MARCH:
+            if tb[3] & (F.FLAG_MARCH | F.FLAG_BLOCK):
                 # the LDS engine (one workgroup per block, empty blocks exit
                 # at once) may suit the bounding box better
                 tl = (r, 256 if r >= 3 else 64, F.ORDER_NATURAL, 19 if rule == 1 else 11)
@@ -466,7 +472,7 @@ def mfma_leg(g, steps):
     out = {}
     for rule in (0, 1):
         t = g.tunings[rule]
-        if t[3] & F.FLAG_MARCH:
+        if t[3] & (F.FLAG_MARCH | F.FLAG_BLOCK):
             t = (t[0], 256 if t[0] >= 3 else 64, t[2], 11 if rule == 0 else 17)
         g.run(rule, 8, F.MAP_MFMA, t)
         mf = g.time(rule, steps, F.MAP_MFMA, t)

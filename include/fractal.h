@@ -127,6 +127,17 @@ extern "C" {
                                      tile sizes, the BB map, batches and
                                      compact states ignore it.  Needs
                                      FRACTAL_FLAG_MARCH */
+#define FRACTAL_FLAG_BLOCK 4096 /* heat on 64 x 64 tiles (r = 6), lambda or BB
+                                   map: the block engine -- one wavefront per
+                                   tile, one lane per non-empty 8 x 8 block of
+                                   the tile and its 16-cell halo, neighbours
+                                   exchanged between lanes; each launch
+                                   advances up to the FUSE flag's step count
+                                   (at most 16), the steps of a call shared
+                                   out evenly over its launches.  Exclusive
+                                   with FRACTAL_FLAG_MARCH, STACK and OCC_ALT;
+                                   batches and compact states take the march
+                                   engine instead */
 
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */

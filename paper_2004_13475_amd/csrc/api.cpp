@@ -125,10 +125,10 @@ static int clamp_r(int k, int r)
 //   automaton  level >= 15: 64 x 64 tiles, non-temporal stores;
 //              level 14: 16 x 16 tiles on stacks of two (the 2T halo rows
 //              paid once per two tiles); below: 16 x 16 tiles;
-//   heat       level >= 16: 64 x 64 tiles, non-temporal stores; level 15:
-//              32 x 32 tiles on stacks of two, non-temporal stores; levels
-//              13 and 14: 32 x 32 tiles; below: 16 x 16 tiles (eight steps
-//              where the tile is narrower than 16 cells).
+//   heat       level >= 14: the block engine (one wavefront per 64 x 64
+//              tile, one lane per non-empty 8 x 8 block), curve order, plain
+//              stores; level 13: 32 x 32 tiles; below: 16 x 16 tiles (eight
+//              steps where the tile is narrower than 16 cells).
 // Non-temporal stores only from level 15: below it the state stays in the
 // last-level cache between launches.
 static fractal_tuning builtin_default(int k, int rule)
@@ -148,6 +148,14 @@ static fractal_tuning builtin_default(int k, int rule)
                   (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
         if (r == want_r && ((ca && k == 14) || (!ca && k == 15)))
             t.flags |= FRACTAL_FLAG_STACK2;
+    }
+    // heat from level 14: the block engine on 64 x 64 tiles, the curve order
+    // (neighbouring tiles share halo blocks in L2), plain stores
+    if (!ca && k >= 14) {
+        t.r = 6;
+        t.threads = 256;
+        t.order = FRACTAL_ORDER_CURVE;
+        t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE16;
     }
     return t;
 }
@@ -309,8 +317,23 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
     const bool march = (t->flags & FRACTAL_FLAG_MARCH) != 0;
     const int stack = t->flags & kStackFlags;
     if (t->flags & ~(FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH |
-                     kFuseFlags | kStackFlags | FRACTAL_FLAG_OCC_ALT))
+                     kFuseFlags | kStackFlags | FRACTAL_FLAG_OCC_ALT | FRACTAL_FLAG_BLOCK))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", t->flags);
+    if (t->flags & FRACTAL_FLAG_BLOCK) {
+        if (t->flags & (FRACTAL_FLAG_MARCH | kStackFlags | FRACTAL_FLAG_OCC_ALT))
+            return set_error(FRACTAL_E_INVAL,
+                             "FRACTAL_FLAG_BLOCK excludes MARCH, STACK and OCC_ALT");
+        if (rule != FRACTAL_RULE_HEAT || t->r != 6 || map == MAP_MFMA)
+            return set_error(FRACTAL_E_INVAL,
+                             "the block engine runs heat on 64 x 64 tiles (r = 6), lambda or BB map");
+        if (!(t->flags & FRACTAL_FLAG_SEGMENTS))
+            return set_error(FRACTAL_E_INVAL, "block launches need FRACTAL_FLAG_SEGMENTS");
+        if (fuse & (fuse - 1))
+            return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
+        if (t->threads != 256)
+            return set_error(FRACTAL_E_INVAL, "block launches take 256 threads");
+        return FRACTAL_OK;
+    }
     if (fuse & (fuse - 1))
         return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
     if (stack & (stack - 1))
@@ -555,6 +578,15 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                                         r, 256, FRACTAL_ORDER_CURVE_XCD,
                                         FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse |
                                             stack | occ});
+        // heat on 64 x 64 tiles: the block engine, 8 or 16 steps per launch,
+        // every order, with and without non-temporal stores
+        if (rule == FRACTAL_RULE_HEAT && r == 6)
+            for (int fuse : {(int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16})
+                for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
+                    for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE,
+                                      FRACTAL_ORDER_CURVE_XCD})
+                        cands.push_back(fractal_tuning{
+                            r, 256, order, FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | fuse | nt});
     }
     for (const fractal_tuning &t : cands) {
         // warm-up (even count keeps the state in buf0)

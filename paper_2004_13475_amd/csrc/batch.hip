@@ -56,6 +56,10 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         if (forced->flags & ~FRACTAL_FLAG_PERSISTENT)
             t.flags = forced->flags;
     }
+    // the block engine has no batch form: its launches become march launches
+    // of the same tile size and step count
+    if (t.flags & FRACTAL_FLAG_BLOCK)
+        t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
     t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags;
     if (t.flags & (FRACTAL_FLAG_MARCH | kFuseFlags))
         t.flags |= FRACTAL_FLAG_SEGMENTS; // fused and march launches move whole segments

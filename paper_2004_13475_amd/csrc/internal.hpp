@@ -108,6 +108,21 @@ int march_band_log(int rule, int r, int T, uint64_t tiles);
 int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 
+// The block engine (heat, 64 x 64 tiles): one wavefront per tile.
+struct BlockArgs {
+    const uint8_t *src;
+    uint8_t *dst;
+    int k;
+    float alpha;
+    int rb;         // tile level k - 6
+    int order;      // FRACTAL_ORDER_* (lambda map)
+    uint32_t total; // tiles in the map's id space
+    int steps;      // steps this launch advances, 1..16
+};
+typedef void (*BlockFn)(BlockArgs);
+int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
+                 const fractal_tuning &t, hipStream_t s);
+
 // Launch `steps` step kernels (validated arguments).
 int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
                  int steps, const fractal_tuning &t, hipStream_t s);

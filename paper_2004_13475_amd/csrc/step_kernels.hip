@@ -79,6 +79,8 @@ int launch_steps(int map, int k, int rule, float alpha, void *b0, void *b1,
     // buf[steps & 1]; the remaining 0..2T-1 steps run one step per launch.
     if (t.flags & FRACTAL_FLAG_MARCH)
         return launch_march(map, k, rule, alpha, b0, b1, steps, t, s);
+    if (t.flags & FRACTAL_FLAG_BLOCK)
+        return launch_block(map, k, rule, alpha, b0, b1, steps, t, s);
     const int T = launch_steps_of(t.flags);
     const bool fuse = T > 1;
     const int fused = fuse ? 2 * (steps / (2 * T)) : 0;

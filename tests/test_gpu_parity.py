@@ -273,6 +273,77 @@ def test_march_launch_plan_every_step_count(rule):
     assert_match(k, rule, a1.cpu().numpy(), ref, "even split, 27 steps")
 
 
+@pytest.mark.parametrize("map_", [F.MAP_LAMBDA, F.MAP_BB])
+def test_block_engine_heat_every_step_count(map_):
+    """The block engine (heat, 64 x 64 tiles: one wavefront per tile, one
+    lane per non-empty 8 x 8 block of the tile and its 16-cell halo) gives
+    the same bits as one step per launch of the LDS engine for every step
+    count 1..40, every launch cap (FUSE2 .. FUSE16, or none: one step per
+    launch), every dispatch order and both store kinds, at levels 6 (one
+    tile, the halo outside the array), 7, 9 and 12; level 9 also against the
+    oracle."""
+    torch = torch_dev()
+    rule = fi.RULE_HEAT
+    BLOCK = F.FLAG_BLOCK | F.FLAG_SEGMENTS
+    for k in (6, 7, 9, 12):
+        init = fi.window_values(k, rule, 60 + k)
+        cur, nxt = to_device(init), zeros_state(k, rule)
+        refs = {}
+        for t in range(1, 41):
+            F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, cur, nxt, 1, min(k, 4), 64, 2,
+                         F.FLAG_SEGMENTS)
+            cur, nxt = nxt, cur
+            _sync()
+            refs[t] = cur.view(torch.uint8).clone()
+        cases = [(F.FLAG_FUSE16, 2, 0), (F.FLAG_FUSE16, 0, F.FLAG_NT_STORE),
+                 (F.FLAG_FUSE16, 1, 0), (F.FLAG_FUSE8, 2, F.FLAG_NT_STORE),
+                 (F.FLAG_FUSE4, 2, 0), (F.FLAG_FUSE2, 0, 0), (0, 2, 0)]
+        for fuse, order, nt in cases:
+            step_list = range(1, 41) if (fuse == F.FLAG_FUSE16 and order == 2) else \
+                (1, 2, 3, 7, 16, 17, 33)
+            for steps in step_list:
+                a0, a1 = to_device(init), zeros_state(k, rule)
+                F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, 6, 256, order,
+                             BLOCK | fuse | nt)
+                _sync()
+                fa = a0 if steps % 2 == 0 else a1
+                assert torch.equal(fa.view(torch.uint8), refs[steps]), (k, fuse, order, nt, steps)
+        if k == 9:
+            ref = oracle_steps(k, rule, init.astype(np.float64), 27)
+            a0, a1 = to_device(init), zeros_state(k, rule)
+            F.step_tuned(map_, k, rule, ALPHA, a0, a1, 27, 6, 256, 2, BLOCK | F.FLAG_FUSE16)
+            _sync()
+            assert_match(k, rule, a1.cpu().numpy(), ref, "block engine, 27 steps")
+
+
+def test_block_engine_full_size_k16_equals_march():
+    """Level 16, the whole array: the block engine (lambda map) gives the
+    same bits as the register march on 64 x 64 tiles after 1, 16 and 37
+    steps, and its bounding-box form the same as its lambda form."""
+    torch = torch_dev()
+    k, rule = 16, fi.RULE_HEAT
+    n = 1 << k
+    for steps in (1, 16, 37):
+        outs = []
+        for map_, fl in ((F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16 |
+                          F.FLAG_NT_STORE),
+                         (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16),
+                         (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16)):
+            b0 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            b1 = torch.zeros_like(b0)
+            F.seed_fill(k, rule, 5, b0)
+            F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, 6, 256, 2, fl)
+            _sync()
+            res = b1 if steps % 2 else b0
+            if outs:
+                assert torch.equal(res.view(torch.int32), outs[0].view(torch.int32)), (steps, fl)
+            else:
+                outs.append(res)
+            del b0, b1
+        del outs
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("rule", RULES)
 def test_march_stacks(rule):
     """Stacks of up to 2, 4 or 8 tiles (each class of equal column runs a
@@ -312,8 +383,8 @@ def test_march_stacks(rule):
 
 @pytest.mark.parametrize("rule", RULES)
 def test_autotune_picks_a_valid_launch(rule):
-    """The autotuner times its candidates (both engines, fusion depths,
-    stacks) on the caller's buffers, caches the fastest for the level, and
+    """The autotuner times its candidates (the LDS, march and block engines,
+    fusion depths, stacks) on the caller's buffers, caches the fastest for the level, and
     lambda steps under that cached launch give the same bits as one step per
     launch; the built-in default comes back after set_tuning restores it."""
     torch = torch_dev()
@@ -326,7 +397,7 @@ def test_autotune_picks_a_valid_launch(rule):
     assert tuple(F.get_tuning(k, rule)) == tuple(t)
     r, th, order, fl = t
     assert 0 <= r <= 7 and th in (64, 256) and order in (0, 1, 2)
-    assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024 | 2048) == 0
+    assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024 | 2048 | 4096) == 0
     for steps in (5, 40):
         a0, a1 = to_device(init), zeros_state(k, rule)
         F.lambda_step(k, F.R_AUTO, rule, ALPHA, a0, a1, steps)

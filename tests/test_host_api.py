@@ -84,7 +84,10 @@ def test_tuning_defaults_and_validation():
             march = tuple(32 | 1 | nt | fuse | st | occ for nt in (0, 2)
                           for fuse in (0, 8, 16, 64, 128) for st in (0, 256, 512, 1024)
                           for occ in (0, 2048))
-            assert flags in lds + march, (k, rule, flags)
+            block = tuple(4096 | 1 | fuse | nt for nt in (0, 2) for fuse in (0, 8, 16, 64, 128))
+            assert flags in lds + march + block, (k, rule, flags)
+            if flags & 4096:  # the block engine: heat on 64 x 64 tiles
+                assert rule == 1 and r == 6 and th == 256
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
     with pytest.raises(F.FractalError):
@@ -226,6 +229,32 @@ def test_boundary_signatures():
         ["inst", "count", "tuning", "d_work", "work_bytes", "stream"]
     assert [a.split()[-1].lstrip("*") for a in _header_prototype("fractal_batch_workspace")] == \
         ["count", "bytes"]
+
+
+def test_block_engine_validation():
+    """The block engine takes heat on 64 x 64 tiles (r = 6) with whole
+    segments and 256 threads, the lambda or BB map, and no march, stack or
+    occupancy flags; anything else is refused before any device work."""
+    B = F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16
+    bad = [(0, 0, 12, 6, 256, B),                       # automaton
+           (0, 1, 12, 5, 256, B),                       # 32 x 32 tiles
+           (2, 1, 12, 6, 256, B),                       # matrix-core map
+           (0, 1, 12, 6, 256, B | F.FLAG_MARCH),
+           (0, 1, 12, 6, 256, B | F.FLAG_STACK2),
+           (0, 1, 12, 6, 256, B | F.FLAG_OCC_ALT),
+           (0, 1, 12, 6, 256, F.FLAG_BLOCK | F.FLAG_FUSE16),  # no whole segments
+           (0, 1, 12, 6, 64, B),
+           (0, 1, 12, 6, 256, B | F.FLAG_FUSE8)]        # two FUSE flags
+    for map_, rule, k, r, th, fl in bad:
+        with pytest.raises(F.FractalError) as e:
+            F.step_tuned(map_, k, rule, 0.2, FAKE0, FAKE1, 3, r, th, 2, fl, stream=0)
+        assert e.value.code == F.E_INVAL, (map_, rule, r, th, fl)
+    before = F.get_tuning(12, 1)
+    F.set_tuning(12, 1, 6, 256, 2, B)  # accepted as a tuning
+    try:
+        assert tuple(F.get_tuning(12, 1)) == (6, 256, 2, B)
+    finally:
+        F.set_tuning(12, 1, *before)
 
 
 def test_reduce_raw_workspace_needs_size():
