@@ -135,9 +135,10 @@ extern "C" {
                                    advances up to the FUSE flag's step count
                                    (at most 16), the steps of a call shared
                                    out evenly over its launches.  Exclusive
-                                   with FRACTAL_FLAG_MARCH, STACK and OCC_ALT;
-                                   batches and compact states take the march
-                                   engine instead */
+                                   with FRACTAL_FLAG_MARCH, STACK and OCC_ALT.
+                                   Batches run heat instances of levels >= 6
+                                   on it too (other instances on the march);
+                                   compact states take the march engine */
 
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */

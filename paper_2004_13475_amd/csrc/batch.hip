@@ -56,13 +56,16 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         if (forced->flags & ~FRACTAL_FLAG_PERSISTENT)
             t.flags = forced->flags;
     }
-    // the block engine has no batch form: its launches become march launches
-    // of the same tile size and step count
-    if (t.flags & FRACTAL_FLAG_BLOCK)
+    // the block engine takes heat on 64 x 64 tiles only; elsewhere its
+    // launches become march launches of the same tile size and step count
+    if ((t.flags & FRACTAL_FLAG_BLOCK) && (rule != FRACTAL_RULE_HEAT || t.r != 6 || k < 6))
         t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
-    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags;
-    if (t.flags & (FRACTAL_FLAG_MARCH | kFuseFlags))
-        t.flags |= FRACTAL_FLAG_SEGMENTS; // fused and march launches move whole segments
+    if (t.flags & FRACTAL_FLAG_BLOCK)
+        t.flags &= ~FRACTAL_FLAG_MARCH;
+    t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH |
+               FRACTAL_FLAG_BLOCK | kFuseFlags;
+    if (t.flags & (FRACTAL_FLAG_MARCH | FRACTAL_FLAG_BLOCK | kFuseFlags))
+        t.flags |= FRACTAL_FLAG_SEGMENTS; // fused, march and block launches move whole segments
     if (t.r > k)
         t.r = k;
     if (t.r > kMaxR)
@@ -71,11 +74,12 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         t.r = k - kMaxBlockLevel;
     if ((1 << t.r) * (int)cell_bytes(rule) < 16) // fused and march launches need 16-byte rows
         t.flags &= ~(kFuseFlags | FRACTAL_FLAG_MARCH);
-    if (!(t.flags & FRACTAL_FLAG_MARCH) && (t.flags & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)))
+    if (!(t.flags & (FRACTAL_FLAG_MARCH | FRACTAL_FLAG_BLOCK)) &&
+        (t.flags & (FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16)))
         t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE4; // LDS engine: 4 at most
     if ((t.flags & FRACTAL_FLAG_FUSE16) && rule != FRACTAL_RULE_CA && t.r < 4)
         t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE8; // narrow heat tiles: 8 at most
-    if (t.flags & FRACTAL_FLAG_MARCH)
+    if (t.flags & (FRACTAL_FLAG_MARCH | FRACTAL_FLAG_BLOCK))
         t.threads = 256;
     else if (t.threads == 256 && t.r < 3)
         t.threads = 64;
@@ -99,7 +103,8 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
         Class c;
         std::tie(c.rule, c.r, c.threads, c.flags) = g.first;
         const int T = launch_steps_of(c.flags);
-        const bool march = (c.flags & FRACTAL_FLAG_MARCH) != 0;
+        // march and block classes launch every power of two up to T
+        const bool march = (c.flags & (FRACTAL_FLAG_MARCH | FRACTAL_FLAG_BLOCK)) != 0;
         // launches per size: counts[j] of T >> j steps (LDS engine: T and 1 only)
         std::vector<std::array<int, kMaxListsPerItem>> counts(items.size());
         for (size_t i : g.second) {
@@ -180,7 +185,16 @@ int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hi
             continue;
         const uint64_t total = list.prefix[active];
         const BatchEntry *tab = d_table + list.first;
-        if (c.flags & FRACTAL_FLAG_MARCH) {
+        if (c.flags & FRACTAL_FLAG_BLOCK) {
+            // one wavefront per tile, four per workgroup
+            BatchBlockFn fn = pick_batch_block((c.flags & FRACTAL_FLAG_NT_STORE) != 0);
+            const uint64_t groups = (total + 3u) / 4u;
+            if (groups > 0xFFFFFFFFull)
+                return set_error(FRACTAL_E_INVAL, "batch list of %llu tiles is too long",
+                                 (unsigned long long)total);
+            hipLaunchKernelGGL(fn, dim3((unsigned)groups), dim3(256), 0, s, tab, (int)active,
+                               total, j, list.T);
+        } else if (c.flags & FRACTAL_FLAG_MARCH) {
             const bool nt = (c.flags & FRACTAL_FLAG_NT_STORE) != 0;
             BatchMarchFn fn = pick_batch_march(c.rule, c.r, list.T, nt);
             const int P = march_tiles_per_wave(c.rule, c.r, list.T);
@@ -304,7 +318,7 @@ extern "C" int fractal_batch_step(const fractal_instance *inst, int count,
         const int fuse = tuning->flags & kFuseFlags;
         if ((tuning->flags & ~(FRACTAL_FLAG_PERSISTENT | FRACTAL_FLAG_SEGMENTS |
                                FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH | kFuseFlags |
-                               kStackFlags | FRACTAL_FLAG_OCC_ALT)) ||
+                               kStackFlags | FRACTAL_FLAG_OCC_ALT | FRACTAL_FLAG_BLOCK)) ||
             (fuse & (fuse - 1)))
             return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", tuning->flags);
     }

@@ -120,6 +120,9 @@ struct BlockArgs {
     int steps;      // steps this launch advances, 1..16
 };
 typedef void (*BlockFn)(BlockArgs);
+// The block engine over a batch list (table, entries, tiles, slot, steps).
+typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
+BatchBlockFn pick_batch_block(bool nt);
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 

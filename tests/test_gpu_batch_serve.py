@@ -46,13 +46,17 @@ MARCH = F.FLAG_MARCH | F.FLAG_SEGMENTS
                                     (6, 0, 0, MARCH | F.FLAG_FUSE8 | F.FLAG_PERSISTENT),
                                     (5, 0, 2, MARCH | F.FLAG_FUSE16),
                                     (F.R_AUTO, 0, 0, F.FLAG_PERSISTENT),
-                                    (F.R_AUTO, 0, 0, MARCH | F.FLAG_FUSE16 | F.FLAG_PERSISTENT)])
+                                    (F.R_AUTO, 0, 0, MARCH | F.FLAG_FUSE16 | F.FLAG_PERSISTENT),
+                                    (6, 0, 0, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16),
+                                    (6, 0, 1, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE8 |
+                                     F.FLAG_NT_STORE)])
 def test_batch_alone_equals_in_mix(tuning):
     """Every instance of a mixed batch (levels 1..11, both rules, 0..37
     steps) gives the bits of its own plain lambda step call, for per-level
-    defaults, explicit tile sizes and flags, both engines and the persistent
-    march grid; small ones also match the oracle.  The workspace is a
-    torch-owned device buffer."""
+    defaults, explicit tile sizes and flags, the LDS, march and block
+    engines (the block engine takes heat instances of level >= 6, the others
+    fall back to the march) and the persistent march grid; small ones also
+    match the oracle.  The workspace is a torch-owned device buffer."""
     torch = torch_dev()
     specs = _mix(40, 3, 1, 11, 37)
     inst, inits = [], []
