@@ -60,7 +60,8 @@ RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
               "device_march.hpp", "march_pick.hpp", "step_march.hip", "step_march_ca.hip",
               "step_march_heat.hip", "step_march_mid_ca.hip", "step_march_mid_heat.hip",
-              "block_heat.hip"]
+              "block_engine.hpp", "block_heat.hpp", "block_heat.hip", "block_ca.hpp",
+              "block_ca.hip"]
 
 
 def kernel_hash() -> str:
@@ -155,10 +156,12 @@ def steps_per_launch(tuning):
     return 16 if fl & 128 else (8 if fl & 64 else (4 if fl & 16 else (2 if fl & 8 else 1)))
 
 
-def kernel_name(tuning):
+def kernel_name(tuning, rule):
     """Name of the step kernel template a tuning launches."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    return "march_kernel" if fl & 32 else ("block_heat_kernel" if fl & 4096 else "step_kernel")
+    if fl & 4096:
+        return "block_ca_kernel" if rule == 0 else "block_heat_kernel"
+    return "march_kernel" if fl & 32 else "step_kernel"
 
 
 def roofline(rule, cells, stats, tuning, traffic=None, kernel=""):
@@ -494,7 +497,7 @@ def level_leg(F, torch, k, steps, label):
         g.run(rule, 16)
         sec = g.time(rule, steps)
         rf = roofline(rule, g.cells, launch_stats(g, rule), g.tunings[rule],
-                      read_traffic(f"k{k}", RULE_NAME[rule]), kernel_name(g.tunings[rule]))
+                      read_traffic(f"k{k}", RULE_NAME[rule]), kernel_name(g.tunings[rule], rule))
         out[RULE_NAME[rule]] = {"tuning": list(g.tunings[rule]), "lambda_us": sec * 1e6,
                                 "cells_per_s": g.cells / sec, "roofline": rf}
     for rule in (0, 1):
@@ -781,7 +784,7 @@ def main() -> int:
     # the timed region
     dom = 1 if per_step[1] >= per_step[0] else 0
     rfs = {r: roofline(r, g.cells, stats[r], g.tunings[r],
-                       read_traffic(args.workload, RULE_NAME[r]), kernel_name(g.tunings[r]))
+                       read_traffic(args.workload, RULE_NAME[r]), kernel_name(g.tunings[r], r))
            for r in (0, 1)}
     rf = dict(rfs[dom], rule=RULE_NAME[dom])
 

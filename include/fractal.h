@@ -127,18 +127,20 @@ extern "C" {
                                      tile sizes, the BB map, batches and
                                      compact states ignore it.  Needs
                                      FRACTAL_FLAG_MARCH */
-#define FRACTAL_FLAG_BLOCK 4096 /* heat on 64 x 64 tiles (r = 6), lambda or BB
-                                   map: the block engine -- one wavefront per
+#define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6), lambda or BB map:
+                                   the block engine -- one wavefront per
                                    tile, one lane per non-empty 8 x 8 block of
-                                   the tile and its 16-cell halo, neighbours
-                                   exchanged between lanes; each launch
+                                   the tile and its 16-cell halo (float32
+                                   cells in registers; automaton cells as a
+                                   64-bit board), neighbours exchanged
+                                   between lanes; each launch
                                    advances up to the FUSE flag's step count
                                    (at most 16), the steps of a call shared
                                    out evenly over its launches.  Exclusive
                                    with FRACTAL_FLAG_MARCH, STACK and OCC_ALT.
-                                   Batches run heat instances of levels >= 6
-                                   on it too (other instances on the march);
-                                   compact states take the march engine */
+                                   Batches run instances of levels >= 6 on it
+                                   too (smaller ones on the march); compact
+                                   states take the march engine */
 
 typedef struct fractal_tuning {
     int r;       /* log2 of the tile side rho, 0..7 (rho <= 128)           */

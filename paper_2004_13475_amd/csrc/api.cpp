@@ -120,43 +120,34 @@ static int clamp_r(int k, int r)
 }
 
 // Used until the autotuner has run for (device, k, rule): the fastest lambda
-// launches measured on MI355X (whole launches, levels 12 to 16), all on the
-// register-march engine with sixteen steps per launch:
-//   automaton  level >= 15: 64 x 64 tiles, non-temporal stores;
-//              level 14: 16 x 16 tiles on stacks of two (the 2T halo rows
-//              paid once per two tiles); below: 16 x 16 tiles;
-//   heat       level >= 14: the block engine (one wavefront per 64 x 64
-//              tile, one lane per non-empty 8 x 8 block), curve order, plain
-//              stores; level 13: 32 x 32 tiles; below: 16 x 16 tiles (eight
-//              steps where the tile is narrower than 16 cells).
-// Non-temporal stores only from level 15: below it the state stays in the
-// last-level cache between launches.
+// launches measured on MI355X (whole launches, levels 12 to 16), sixteen
+// steps per launch:
+//   automaton  level >= 14: the block engine (one wavefront per 64 x 64
+//              tile, one lane per non-empty 8 x 8 block); below: the register
+//              march on 16 x 16 tiles;
+//   heat       level >= 13: the block engine; below: the march on 16 x 16
+//              tiles (eight steps where the tile is narrower than 16 cells).
+// The block engines use plain stores (non-temporal ones measured 1.3-3x
+// slower); march launches from level 15 non-temporal ones.
 static fractal_tuning builtin_default(int k, int rule)
 {
     const bool ca = rule == FRACTAL_RULE_CA;
-    int want_r = 4;
-    if (ca)
-        want_r = k >= 15 ? 6 : 4;
-    else
-        want_r = k >= 16 ? 6 : (k >= 13 ? 5 : 4);
-    const int r = clamp_r(k, want_r);
-    fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
-    if (t.flags & FRACTAL_FLAG_MARCH) {
-        const bool fuse16 = ca || r >= 4; // heat: 16 steps need tiles of side >= 16
-        t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |
-                  (fuse16 ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8) |
-                  (k >= 15 ? FRACTAL_FLAG_NT_STORE : 0);
-        if (r == want_r && ((ca && k == 14) || (!ca && k == 15)))
-            t.flags |= FRACTAL_FLAG_STACK2;
-    }
-    // heat from level 14: the block engine on 64 x 64 tiles, the curve order
-    // (neighbouring tiles share halo blocks in L2), plain stores
-    if (!ca && k >= 14) {
+    if (k >= (ca ? 14 : 13)) {
+        // the block engine, plain stores, in the curve order (neighbouring
+        // tiles share halo blocks in L2; for the automaton split over the
+        // dies)
+        fractal_tuning t;
         t.r = 6;
         t.threads = 256;
-        t.order = FRACTAL_ORDER_CURVE;
+        t.order = ca ? FRACTAL_ORDER_CURVE_XCD : FRACTAL_ORDER_CURVE;
         t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE16;
+        return t;
     }
+    const int r = clamp_r(k, 4);
+    fractal_tuning t = tuning_for_r(MAP_LAMBDA, k, rule, r);
+    if (t.flags & FRACTAL_FLAG_MARCH) // heat: 16 steps need tiles of side >= 16
+        t.flags = FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS |
+                  ((ca || r >= 4) ? FRACTAL_FLAG_FUSE16 : FRACTAL_FLAG_FUSE8);
     return t;
 }
 
@@ -323,9 +314,9 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         if (t->flags & (FRACTAL_FLAG_MARCH | kStackFlags | FRACTAL_FLAG_OCC_ALT))
             return set_error(FRACTAL_E_INVAL,
                              "FRACTAL_FLAG_BLOCK excludes MARCH, STACK and OCC_ALT");
-        if (rule != FRACTAL_RULE_HEAT || t->r != 6 || map == MAP_MFMA)
+        if (t->r != 6 || map == MAP_MFMA)
             return set_error(FRACTAL_E_INVAL,
-                             "the block engine runs heat on 64 x 64 tiles (r = 6), lambda or BB map");
+                             "the block engine runs on 64 x 64 tiles (r = 6), lambda or BB map");
         if (!(t->flags & FRACTAL_FLAG_SEGMENTS))
             return set_error(FRACTAL_E_INVAL, "block launches need FRACTAL_FLAG_SEGMENTS");
         if (fuse & (fuse - 1))
@@ -578,9 +569,9 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                                         r, 256, FRACTAL_ORDER_CURVE_XCD,
                                         FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse |
                                             stack | occ});
-        // heat on 64 x 64 tiles: the block engine, 8 or 16 steps per launch,
-        // every order, with and without non-temporal stores
-        if (rule == FRACTAL_RULE_HEAT && r == 6)
+        // 64 x 64 tiles: the block engine, 8 or 16 steps per launch, every
+        // order, with and without non-temporal stores
+        if (r == 6)
             for (int fuse : {(int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16})
                 for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
                     for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE,

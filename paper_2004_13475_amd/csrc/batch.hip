@@ -56,9 +56,9 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         if (forced->flags & ~FRACTAL_FLAG_PERSISTENT)
             t.flags = forced->flags;
     }
-    // the block engine takes heat on 64 x 64 tiles only; elsewhere its
-    // launches become march launches of the same tile size and step count
-    if ((t.flags & FRACTAL_FLAG_BLOCK) && (rule != FRACTAL_RULE_HEAT || t.r != 6 || k < 6))
+    // the block engines take 64 x 64 tiles only; elsewhere their launches
+    // become march launches of the same tile size and step count
+    if ((t.flags & FRACTAL_FLAG_BLOCK) && (t.r != 6 || k < 6))
         t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
     if (t.flags & FRACTAL_FLAG_BLOCK)
         t.flags &= ~FRACTAL_FLAG_MARCH;
@@ -187,7 +187,7 @@ int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hi
         const BatchEntry *tab = d_table + list.first;
         if (c.flags & FRACTAL_FLAG_BLOCK) {
             // one wavefront per tile, four per workgroup
-            BatchBlockFn fn = pick_batch_block((c.flags & FRACTAL_FLAG_NT_STORE) != 0);
+            BatchBlockFn fn = pick_batch_block(c.rule, (c.flags & FRACTAL_FLAG_NT_STORE) != 0);
             const uint64_t groups = (total + 3u) / 4u;
             if (groups > 0xFFFFFFFFull)
                 return set_error(FRACTAL_E_INVAL, "batch list of %llu tiles is too long",

@@ -1,8 +1,9 @@
-// batch_block_heat.hip -- the block engine over a batch work list: heat
-// instances on 64 x 64 tiles, one wavefront per tile of the list.
+// batch_block.hip -- the block engines over a batch work list: instances
+// on 64 x 64 tiles, one wavefront per tile of the list.
 #include <hip/hip_runtime.h>
 
 #include "batch_kernels.hpp"
+#include "block_ca.hpp"
 #include "block_heat.hpp"
 #include "internal.hpp"
 
@@ -27,8 +28,24 @@ __global__ __launch_bounds__(256) void batch_block_heat_kernel(const BatchEntry 
     block_tile<FL>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, e.alpha, t, steps);
 }
 
-BatchBlockFn pick_batch_block(bool nt)
+template <int FL>
+__global__ __launch_bounds__(256) void batch_block_ca_kernel(const BatchEntry *__restrict__ table,
+                                                             int count, uint64_t total, int slot,
+                                                             int steps)
 {
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= total)
+        return; // wavefront-uniform
+    const BatchEntry e = table[find_instance(table, count, w)];
+    const TileXY t = lambda_wave_curve((uint32_t)(w - e.tile_begin), e.k - blk::kTileLog);
+    const bool odd = ((e.phase + e.flip0 + slot) & 1) != 0;
+    block_ca_tile<FL>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, t, steps);
+}
+
+BatchBlockFn pick_batch_block(int rule, bool nt)
+{
+    if (rule == FRACTAL_RULE_CA)
+        return nt ? batch_block_ca_kernel<TILE_NT_STORE> : batch_block_ca_kernel<0>;
     return nt ? batch_block_heat_kernel<TILE_NT_STORE> : batch_block_heat_kernel<0>;
 }
 

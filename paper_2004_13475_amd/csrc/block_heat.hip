@@ -1,5 +1,6 @@
 // block_heat.hip -- the block engine of the float32 heat step on one
-// gasket (lambda and bounding-box maps) and its launcher.
+// gasket (lambda and bounding-box maps), and the launcher of both block
+// engines (the automaton's kernels are in block_ca.hip).
 #include <hip/hip_runtime.h>
 
 #include "block_heat.hpp"
@@ -48,10 +49,11 @@ static BlockFn pick_block(int map, bool nt)
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s)
 {
-    if (rule != FRACTAL_RULE_HEAT || t.r != blk::kTileLog || k < blk::kTileLog)
-        return set_error(FRACTAL_E_INVAL, "the block engine runs heat on 64 x 64 tiles (r = 6)");
+    if (t.r != blk::kTileLog || k < blk::kTileLog)
+        return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 tiles (r = 6)");
     const int cap = launch_steps_of(t.flags);
-    BlockFn fn = pick_block(map, (t.flags & FRACTAL_FLAG_NT_STORE) != 0);
+    const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
+    BlockFn fn = rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt) : pick_block(map, nt);
     if (!fn || cap < 1 || cap > 16)
         return set_error(FRACTAL_E_INVAL, "no block kernel for map %d, %d steps per launch", map,
                          cap);

@@ -1,74 +1,23 @@
-// block_heat.hpp -- the block engine of the float32 heat step: one
-// wavefront per 64 x 64 tile, one lane per non-empty 8 x 8 block.
-//
-// A tile of a level-k gasket is a level-3 gasket of 8 x 8 blocks, and its
-// halo of 16 cells (two blocks on each side) holds more non-empty blocks of
-// the neighbouring tiles: at most 54 in the 12 x 12 blocks of the region,
-// so one block per lane fits one wavefront.  Lanes take the region's
-// non-empty blocks in row-major order, keep the 27 member cells of their
-// block in registers for the whole launch, and exchange across block edges
-// by ds_bpermute: in a gasket only the corner cells of two side-by-side
-// blocks touch (the cell at (0,0) of a block and the one at (0,7) of the
-// block above it, (7,0) of the block to its left), so a step needs four
-// values from other lanes.  No LDS, no barrier.  Blocks near the region's
-// edge see zeros for what lies outside it; the damage moves one cell per
-// step and the tile is 16 cells in, so a launch of up to 16 steps leaves the
-// tile exact.  The arithmetic per cell is the march and LDS engines'
+// block_heat.hpp -- the block engine of the float32 heat step (one
+// wavefront per 64 x 64 tile, one lane per non-empty 8 x 8 block; the
+// shared setup is in block_engine.hpp).  Each lane keeps the 27 member
+// cells of its block in registers for the whole launch; a step needs four
+// values from other lanes: in a gasket the cell at (0,0) of a block touches
+// only the cell at (0,7) of the block above it and (7,0) of the block to
+// its left.  The arithmetic per cell is the march and LDS engines'
 // (fma(a, (N + S) + (W + E), (1 - 4a) u), neighbours that cannot be members
 // left out), so all engines agree bit for bit on non-negative states.  Work
 // goes only to non-empty blocks: where the march walks every 16-byte chunk
 // of a tile's bounding box (a third of them hold a member in a 64 x 64
 // float32 tile), here 27 of the 64 cells of each active lane's block are
-// members and 16 of 64 lanes idle at most.
+// members.
 #pragma once
 
-#include <hip/hip_runtime.h>
-
-#include "device_map.hpp"
-#include "device_march.hpp"
-#include "internal.hpp"
+#include "block_engine.hpp"
 
 namespace fractal {
 
 namespace blk {
-
-constexpr int kTileLog = 6;   // tiles of 64 x 64 cells
-constexpr int kBlk = 8;       // blocks of 8 x 8 cells
-constexpr int kTileBlk = 8;   // blocks per tile side
-constexpr int kHaloBlk = 2;   // halo blocks per side (16 cells: up to 16 steps)
-constexpr int kReg = kTileBlk + 2 * kHaloBlk; // region side in blocks
-constexpr int kPos = kReg * kReg;             // 144 block positions
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// Cell (i, j) of a block (column i, row j) is a member iff (i & j) == 0:
-// the block's own bits and the block coordinates' bits do not overlap.
-constexpr bool mem(int i, int j)
-{
-    return i >= 0 && j >= 0 && i < kBlk && j < kBlk && (i & j) == 0;
-}
-
-// Index of the r-th set bit (0-based) of v.
-__device__ __forceinline__ uint32_t select_bit(uint64_t v, uint32_t r)
-{
-    uint32_t pos = 0u;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const uint64_t low = v & ((1ull << s) - 1ull);
-        const uint32_t c = (uint32_t)__builtin_popcountll(low);
-        if (r >= c) {
-            r -= c;
-            v >>= s;
-            pos += (uint32_t)s;
-        }
-    }
-    return pos;
-}
-
-__device__ __forceinline__ float pull(uint32_t lane, float v)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute((int)(lane << 2), __float_as_int(v)));
-}
 
 // a + b over the terms present (at least one is)
 template <bool A, bool B>
@@ -136,56 +85,16 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
                                            float alpha_in, TileXY t, int steps)
 {
     using namespace blk;
-    const uint32_t lane = lane_id();
-    // the region's non-empty blocks, in row-major order of the 12 x 12
-    // positions (three ballots of 64 positions)
-    const int nbl = 1 << (k - 3); // blocks per array side
-    const int bx0 = (int)(t.x << (kTileLog - 3)) - kHaloBlk;
-    const int by0 = (int)(t.y << (kTileLog - 3)) - kHaloBlk;
-    uint64_t m[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int p = (int)lane + 64 * q;
-        const int gx = bx0 + p % kReg, gy = by0 + p / kReg;
-        const bool ne = p < kPos && gx >= 0 && gy >= 0 && gx < nbl && gy < nbl && (gx & gy) == 0;
-        m[q] = __builtin_amdgcn_ballot_w64(ne);
-    }
-    const uint32_t c0 = (uint32_t)__builtin_popcountll(m[0]);
-    const uint32_t c1n = (uint32_t)__builtin_popcountll(m[1]);
-    const uint32_t nblocks = c0 + c1n + (uint32_t)__builtin_popcountll(m[2]);
-    const bool active = lane < nblocks;
-    // this lane's block: the lane-th non-empty position
-    uint32_t pos = 0u;
-    {
-        const uint32_t q = lane < c0 ? 0u : (lane < c0 + c1n ? 1u : 2u);
-        const uint32_t r = lane - (q == 0u ? 0u : (q == 1u ? c0 : c0 + c1n));
-        const uint64_t bits = q == 0u ? m[0] : (q == 1u ? m[1] : m[2]);
-        pos = active ? 64u * q + select_bit(bits, r) : 0u;
-    }
-    const int px = (int)pos % kReg, py = (int)pos / kReg;
-    // lane holding block position p (valid where p is a non-empty position)
-    auto lane_of = [&](int p, bool &ok) -> uint32_t {
-        const int q = p >> 6, b = p & 63;
-        const uint64_t mq = q == 0 ? m[0] : (q == 1 ? m[1] : m[2]);
-        ok = ok && ((mq >> b) & 1ull) != 0ull;
-        const uint32_t before = (uint32_t)__builtin_popcountll(mq & ((1ull << b) - 1ull));
-        return before + (q >= 1 ? c0 : 0u) + (q >= 2 ? c1n : 0u);
-    };
-    bool okN = active && py > 0, okS = active && py < kReg - 1;
-    bool okW = active && px > 0, okE = active && px < kReg - 1;
-    uint32_t lN = lane_of(okN ? (int)pos - kReg : 0, okN);
-    uint32_t lS = lane_of(okS ? (int)pos + kReg : 0, okS);
-    uint32_t lW = lane_of(okW ? (int)pos - 1 : 0, okW);
-    uint32_t lE = lane_of(okE ? (int)pos + 1 : 0, okE);
-    lN = okN ? lN : lane;
-    lS = okS ? lS : lane;
-    lW = okW ? lW : lane;
-    lE = okE ? lE : lane;
+    const Region g = block_region(k, t);
+    const bool active = g.active;
+    const int px = g.px, py = g.py;
+    const bool okN = g.ok[DN], okS = g.ok[DS], okW = g.ok[DW], okE = g.ok[DE];
+    const uint32_t lN = g.lane[DN], lS = g.lane[DS], lW = g.lane[DW], lE = g.lane[DE];
 
     // load the block's member chunks (rows 4..7 hold members in their
     // first four cells only)
     const int n = 1 << k;
-    const int gx = bx0 + px, gy = by0 + py;
+    const int gx = g.gx, gy = g.gy;
     const int64_t base = ((int64_t)(gy * kBlk) * n + (int64_t)gx * kBlk) * 4;
     Cells c;
     {

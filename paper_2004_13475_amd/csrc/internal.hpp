@@ -108,7 +108,7 @@ int march_band_log(int rule, int r, int T, uint64_t tiles);
 int launch_march(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 
-// The block engine (heat, 64 x 64 tiles): one wavefront per tile.
+// The block engines (64 x 64 tiles): one wavefront per tile.
 struct BlockArgs {
     const uint8_t *src;
     uint8_t *dst;
@@ -120,9 +120,10 @@ struct BlockArgs {
     int steps;      // steps this launch advances, 1..16
 };
 typedef void (*BlockFn)(BlockArgs);
+BlockFn pick_block_ca(int map, bool nt);
 // The block engine over a batch list (table, entries, tiles, slot, steps).
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
-BatchBlockFn pick_batch_block(bool nt);
+BatchBlockFn pick_batch_block(int rule, bool nt);
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 

@@ -274,16 +274,16 @@ def test_march_launch_plan_every_step_count(rule):
 
 
 @pytest.mark.parametrize("map_", [F.MAP_LAMBDA, F.MAP_BB])
-def test_block_engine_heat_every_step_count(map_):
-    """The block engine (heat, 64 x 64 tiles: one wavefront per tile, one
-    lane per non-empty 8 x 8 block of the tile and its 16-cell halo) gives
-    the same bits as one step per launch of the LDS engine for every step
-    count 1..40, every launch cap (FUSE2 .. FUSE16, or none: one step per
-    launch), every dispatch order and both store kinds, at levels 6 (one
-    tile, the halo outside the array), 7, 9 and 12; level 9 also against the
-    oracle."""
+@pytest.mark.parametrize("rule", RULES)
+def test_block_engine_every_step_count(rule, map_):
+    """The block engine (64 x 64 tiles: one wavefront per tile, one lane per
+    non-empty 8 x 8 block of the tile and its 16-cell halo; heat cells in
+    registers, automaton cells as a 64-bit board) gives the same bits as one
+    step per launch of the LDS engine for every step count 1..40, every
+    launch cap (FUSE2 .. FUSE16, or none: one step per launch), every
+    dispatch order and both store kinds, at levels 6 (one tile, the halo
+    outside the array), 7, 9 and 12; level 9 also against the oracle."""
     torch = torch_dev()
-    rule = fi.RULE_HEAT
     BLOCK = F.FLAG_BLOCK | F.FLAG_SEGMENTS
     for k in (6, 7, 9, 12):
         init = fi.window_values(k, rule, 60 + k)
@@ -309,34 +309,36 @@ def test_block_engine_heat_every_step_count(map_):
                 fa = a0 if steps % 2 == 0 else a1
                 assert torch.equal(fa.view(torch.uint8), refs[steps]), (k, fuse, order, nt, steps)
         if k == 9:
-            ref = oracle_steps(k, rule, init.astype(np.float64), 27)
+            ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 27)
             a0, a1 = to_device(init), zeros_state(k, rule)
             F.step_tuned(map_, k, rule, ALPHA, a0, a1, 27, 6, 256, 2, BLOCK | F.FLAG_FUSE16)
             _sync()
             assert_match(k, rule, a1.cpu().numpy(), ref, "block engine, 27 steps")
 
 
-def test_block_engine_full_size_k16_equals_march():
+@pytest.mark.parametrize("rule", RULES)
+def test_block_engine_full_size_k16_equals_march(rule):
     """Level 16, the whole array: the block engine (lambda map) gives the
     same bits as the register march on 64 x 64 tiles after 1, 16 and 37
     steps, and its bounding-box form the same as its lambda form."""
     torch = torch_dev()
-    k, rule = 16, fi.RULE_HEAT
+    k = 16
     n = 1 << k
+    dt = torch.uint8 if rule == fi.RULE_CA else torch.float32
     for steps in (1, 16, 37):
         outs = []
         for map_, fl in ((F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16 |
                           F.FLAG_NT_STORE),
                          (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16),
                          (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16)):
-            b0 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            b0 = torch.empty((n, n), dtype=dt, device="cuda")
             b1 = torch.zeros_like(b0)
             F.seed_fill(k, rule, 5, b0)
             F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, 6, 256, 2, fl)
             _sync()
             res = b1 if steps % 2 else b0
             if outs:
-                assert torch.equal(res.view(torch.int32), outs[0].view(torch.int32)), (steps, fl)
+                assert torch.equal(res.view(torch.uint8), outs[0].view(torch.uint8)), (steps, fl)
             else:
                 outs.append(res)
             del b0, b1

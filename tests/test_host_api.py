@@ -86,8 +86,8 @@ def test_tuning_defaults_and_validation():
                           for occ in (0, 2048))
             block = tuple(4096 | 1 | fuse | nt for nt in (0, 2) for fuse in (0, 8, 16, 64, 128))
             assert flags in lds + march + block, (k, rule, flags)
-            if flags & 4096:  # the block engine: heat on 64 x 64 tiles
-                assert rule == 1 and r == 6 and th == 256
+            if flags & 4096:  # the block engine: 64 x 64 tiles
+                assert r == 6 and th == 256
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
     with pytest.raises(F.FractalError):
@@ -232,11 +232,11 @@ def test_boundary_signatures():
 
 
 def test_block_engine_validation():
-    """The block engine takes heat on 64 x 64 tiles (r = 6) with whole
-    segments and 256 threads, the lambda or BB map, and no march, stack or
-    occupancy flags; anything else is refused before any device work."""
+    """The block engine takes 64 x 64 tiles (r = 6) with whole segments and
+    256 threads, the lambda or BB map, and no march, stack or occupancy
+    flags; anything else is refused before any device work."""
     B = F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16
-    bad = [(0, 0, 12, 6, 256, B),                       # automaton
+    bad = [(0, 0, 12, 5, 256, B),                       # automaton, 32 x 32 tiles
            (0, 1, 12, 5, 256, B),                       # 32 x 32 tiles
            (2, 1, 12, 6, 256, B),                       # matrix-core map
            (0, 1, 12, 6, 256, B | F.FLAG_MARCH),
