@@ -60,8 +60,8 @@ RULE_NAME = {0: "ca", 1: "heat"}
 KERNEL_SRC = ["device_tile.hpp", "device_map.hpp", "step_kernel.hpp", "step_kernels.hip",
               "device_march.hpp", "march_pick.hpp", "step_march.hip", "step_march_ca.hip",
               "step_march_heat.hip", "step_march_mid_ca.hip", "step_march_mid_heat.hip",
-              "block_engine.hpp", "block_heat.hpp", "block_heat.hip", "block_ca.hpp",
-              "block_ca.hip"]
+              "block_engine.hpp", "block_slots.inc", "block_heat.hpp", "block_heat.hip",
+              "block_ca.hpp", "block_ca.hip"]
 
 
 def kernel_hash() -> str:
@@ -151,9 +151,13 @@ class Gasket:
 
 
 def steps_per_launch(tuning):
-    """Steps one launch advances: 16, 8, 4 or 2 for fused launches, else 1."""
+    """Steps one launch advances: 32, 24 (block engine), 16, 8, 4 or 2 for
+    fused launches, else 1."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    return 16 if fl & 128 else (8 if fl & 64 else (4 if fl & 16 else (2 if fl & 8 else 1)))
+    for flag, T in ((16384, 32), (8192, 24), (128, 16), (64, 8), (16, 4), (8, 2)):
+        if fl & flag:
+            return T
+    return 1
 
 
 def kernel_name(tuning, rule):
@@ -215,7 +219,10 @@ def bb_tuning(g, rule, r, lam=None):
     fl = t[3]
     if fl & g.F.FLAG_BLOCK and r != 6:
         # the block engine takes 64 x 64 tiles only: the march at other sizes
+        # (16 steps per launch at most)
         fl = (fl & ~g.F.FLAG_BLOCK) | g.F.FLAG_MARCH
+        if fl & (g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32):
+            fl = (fl & ~(g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32)) | g.F.FLAG_FUSE16
     if fl & g.F.FLAG_FUSE16 and rule == 1 and r < 4:
         fl = (fl & ~g.F.FLAG_FUSE16) | g.F.FLAG_FUSE8  # heat: 16 steps need 16-cell tiles
     if (1 << r) * (1 if rule == 0 else 4) < 16:

@@ -13,7 +13,8 @@ namespace fractal {
 // per-instance tile prefix, its tile from that instance's lambda in the
 // curve order (per wavefront).  `slot` is the index of this launch within
 // the item's launches of this list's size (every launch flips the buffers);
-// every launch of the list advances `steps` steps.
+// every launch of the list advances `steps` steps (at most 16: batches take
+// the 16-cell halo).
 template <int FL>
 __global__ __launch_bounds__(256) void batch_block_heat_kernel(const BatchEntry *__restrict__ table,
                                                                int count, uint64_t total,
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(256) void batch_block_heat_kernel(const BatchEntry 
     const BatchEntry e = table[find_instance(table, count, w)];
     const TileXY t = lambda_wave_curve((uint32_t)(w - e.tile_begin), e.k - blk::kTileLog);
     const bool odd = ((e.phase + e.flip0 + slot) & 1) != 0;
-    block_tile<FL>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, e.alpha, t, steps);
+    block_tile<FL, 16>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, e.alpha, t, steps);
 }
 
 template <int FL>
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void batch_block_ca_kernel(const BatchEntry *_
     const BatchEntry e = table[find_instance(table, count, w)];
     const TileXY t = lambda_wave_curve((uint32_t)(w - e.tile_begin), e.k - blk::kTileLog);
     const bool odd = ((e.phase + e.flip0 + slot) & 1) != 0;
-    block_ca_tile<FL>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, t, steps);
+    block_ca_tile<FL, 16>(odd ? e.buf1 : e.buf0, odd ? e.buf0 : e.buf1, e.k, t, steps);
 }
 
 BatchBlockFn pick_batch_block(int rule, bool nt)

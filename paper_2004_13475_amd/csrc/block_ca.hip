@@ -9,7 +9,7 @@ namespace fractal {
 
 // One wavefront per tile: tile id `tile` of the map (lambda: the curve or
 // natural order; BB: row-major over all (n/64)^2 tiles, empty ones idle).
-template <int MAP, int FL>
+template <int MAP, int FL, int D>
 __global__ __launch_bounds__(256) void block_ca_kernel(BlockArgs a)
 {
     uint32_t wg = blockIdx.x;
@@ -30,16 +30,28 @@ __global__ __launch_bounds__(256) void block_ca_kernel(BlockArgs a)
     } else {
         t = lambda_wave_curve(tile, a.rb);
     }
-    block_ca_tile<FL>(a.src, a.dst, a.k, t, a.steps);
+    block_ca_tile<FL, D>(a.src, a.dst, a.k, t, a.steps);
 }
 
-BlockFn pick_block_ca(int map, bool nt)
+template <int MAP, int D>
+static BlockFn pick_block_ca_d(bool nt)
 {
-    if (map == MAP_BB)
-        return nt ? block_ca_kernel<MAP_BB, TILE_NT_STORE> : block_ca_kernel<MAP_BB, 0>;
-    if (map == MAP_LAMBDA)
-        return nt ? block_ca_kernel<MAP_LAMBDA, TILE_NT_STORE> : block_ca_kernel<MAP_LAMBDA, 0>;
-    return nullptr;
+    return nt ? block_ca_kernel<MAP, TILE_NT_STORE, D> : block_ca_kernel<MAP, 0, D>;
+}
+
+BlockFn pick_block_ca(int map, bool nt, int depth)
+{
+    if (map != MAP_BB && map != MAP_LAMBDA)
+        return nullptr;
+    const bool bb = map == MAP_BB;
+    switch (depth) {
+    case 16:
+        return bb ? pick_block_ca_d<MAP_BB, 16>(nt) : pick_block_ca_d<MAP_LAMBDA, 16>(nt);
+    case 24:
+        return bb ? pick_block_ca_d<MAP_BB, 24>(nt) : pick_block_ca_d<MAP_LAMBDA, 24>(nt);
+    default:
+        return nullptr; // no automaton table beyond 24 steps
+    }
 }
 
 } // namespace fractal

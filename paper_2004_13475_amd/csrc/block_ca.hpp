@@ -1,16 +1,17 @@
 // block_ca.hpp -- the block engine of the uint8 B3/S23 automaton (one
-// wavefront per 64 x 64 tile, one lane per non-empty 8 x 8 block; the
-// shared setup is in block_engine.hpp).  A lane keeps its block as a 64-bit
-// board (bit 8j + i holds cell (i, j)) and advances it with bitwise
-// operations: the eight neighbour boards are the board shifted, with the
-// cells of the neighbouring blocks that touch it shifted in, and a
-// bit-sliced adder counts them.  In a gasket only these cells of other
-// blocks touch a block's members: the cell (0,7) of the block above and of
-// the block above right, (7,0) of the block to the left and of the block
-// below left, (0,0) and (0,1) of the block to the right, (0,0) and (1,0) of
-// the block below; a step reads the words that hold them from six lanes.
-// The finished tile is assembled in LDS (4 KB per wavefront) and written a
-// whole 64-byte row per lane.
+// wavefront per 64 x 64 tile, one lane per 8 x 8 block; the shared setup is
+// in block_engine.hpp).  A lane keeps its block as a 64-bit board (bit
+// 8j + i holds cell (i, j); the low word holds rows 0..3, the high word rows
+// 4..7) and advances it with bitwise operations.  A step first sums each
+// cell's row neighbours, (i-1, j) + (i+1, j), and the same with the cell
+// itself; the rows above and below contribute their three-cell sums, taken
+// from this board or, for row 0 and row 7, from the lanes of the blocks
+// above and below, whose sums already hold the diagonal blocks' cells.  In
+// a gasket only these cells of other blocks touch a block's members: (7,0)
+// of the block to the left, column 0 of the block to the right, (0,7) of
+// the blocks above and above right, and row 0 of the block below with
+// (7,0) of the block below left.  The finished tile is assembled in LDS (4 KB
+// per wavefront) and written four lanes to a 64-byte row.
 #pragma once
 
 #include "block_engine.hpp"
@@ -30,8 +31,6 @@ constexpr uint64_t member_board()
     return m;
 }
 constexpr uint64_t kMembers = member_board();
-constexpr uint64_t kCol0 = 0x0101010101010101ull;
-constexpr uint64_t kCol7 = 0x8080808080808080ull;
 
 // The low bits of bytes 0..3 of v gathered into bits 0..3 (the products of
 // the four terms land on distinct bits, so nothing carries into 28..31).
@@ -42,65 +41,95 @@ __device__ __forceinline__ uint32_t unpack4(uint32_t x)
     return ((x & 0xFu) * 0x00204081u) & 0x01010101u;
 }
 
-// Three-input xor and majority of 64-bit boards, one v_bitop3 per 32-bit
-// half (both functions are symmetric in their inputs).
-__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c)
+constexpr uint32_t kMembersLo = (uint32_t)kMembers, kMembersHi = (uint32_t)(kMembers >> 32);
+
+// Three-input xor and majority (one v_bitop3 each; both are symmetric in
+// their inputs).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
-    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
-    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32),
-                                                    (uint32_t)(c >> 32), 0x96);
-    return ((uint64_t)hi << 32) | lo;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
-__device__ __forceinline__ uint64_t maj3(uint64_t a, uint64_t b, uint64_t c)
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
 {
-    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0xE8);
-    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32),
-                                                    (uint32_t)(c >> 32), 0xE8);
-    return ((uint64_t)hi << 32) | lo;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+// The bits of a where m is set, of b elsewhere.
+__device__ __forceinline__ uint32_t merge(uint32_t m, uint32_t a, uint32_t b)
+{
+    return (a & m) | (b & ~m);
+}
+// The low word of (hi:lo) >> s.
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
+{
+    return __builtin_amdgcn_alignbit(hi, lo, s);
 }
 
-// One B3/S23 step of board b.  nrow: row 7 of the block above (bits 0..7);
-// srow: row 0 of the block below (bits 0..7); wcol: column 7 of the block to
-// the left in column 0 (rows 0..3); ecol: column 0 of the block to the right
-// in column 7 (rows 0..3); ne: cell (0,7) of the block above right; sw: cell
-// (7,0) of the block below left.  Cells outside these are not members or
-// touch no member of this block.
-__device__ __forceinline__ uint64_t life_step(uint64_t b, uint64_t nrow, uint64_t srow,
-                                              uint64_t wcol, uint64_t ecol, uint64_t ne,
-                                              uint64_t sw)
+struct Board {
+    uint32_t lo, hi; // rows 0..3, rows 4..7
+};
+
+// One B3/S23 step of board b.  nb: the lanes of the blocks in each
+// direction (the zero lane where there is none; for the diagonals, also
+// where the block above or below that relays the corner cell is held).
+// Every lane of the wavefront calls it.
+__device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
 {
-    const uint64_t nb = (b << 8) | nrow;         // cell (i, j-1)
-    const uint64_t sb = (b >> 8) | (srow << 56); // cell (i, j+1)
-    const uint64_t n1 = nb;
-    const uint64_t n2 = sb;
-    const uint64_t n3 = ((b << 1) & ~kCol0) | wcol;                       // (i-1, j)
-    const uint64_t n4 = ((b >> 1) & ~kCol7) | ecol;                       // (i+1, j)
-    const uint64_t n5 = ((nb << 1) & ~kCol0) | (wcol << 8);               // (i-1, j-1)
-    const uint64_t n6 = ((nb >> 1) & ~kCol7) | (ecol << 8) | (ne << 7);   // (i+1, j-1)
-    const uint64_t n7 = ((sb << 1) & ~kCol0) | (wcol >> 8) | (sw << 56);  // (i-1, j+1)
-    const uint64_t n8 = ((sb >> 1) & ~kCol7) | (ecol >> 8);               // (i+1, j+1)
-    // bit-sliced sum of the eight boards (full adders: sum = xor3, carry =
-    // majority): count = s0 + 2 s1 + 4 (f0 + f1)
-    const uint64_t a1 = xor3(n1, n2, n3), c1 = maj3(n1, n2, n3);
-    const uint64_t a2 = xor3(n4, n5, n6), c2 = maj3(n4, n5, n6);
-    const uint64_t a3 = n7 ^ n8, c3 = n7 & n8;
-    const uint64_t s0 = xor3(a1, a2, a3), c4 = maj3(a1, a2, a3);
-    const uint64_t t = xor3(c1, c2, c3), f0 = maj3(c1, c2, c3);
-    const uint64_t s1 = t ^ c4, f1 = t & c4;
-    // B3/S23: alive next iff count == 3, or count == 2 and alive now
-    return kMembers & s1 & ~(f0 | f1) & (s0 | b);
+    // the cells (i-1, j) and (i+1, j): the board shifted along its rows,
+    // with column 7 of the block to the left (a member in row 0 only) and
+    // column 0 of the block to the right shifted in; rows 4..7 hold no
+    // member beyond column 3, so their left shift spills nothing
+    const uint32_t w = pull_u32(nb[DW], b.lo);
+    const uint32_t elo = pull_u32(nb[DE], b.lo), ehi = pull_u32(nb[DE], b.hi);
+    const uint32_t llo = merge(0xFEFEFEFEu, b.lo << 1, w >> 7), lhi = b.hi << 1;
+    const uint32_t rlo = merge(0x7F7F7F7Fu, b.lo >> 1, elo << 7);
+    const uint32_t rhi = merge(0x7F7F7F7Fu, b.hi >> 1, ehi << 7);
+    // per cell, two-bit sums of (i-1, j) + (i, j) + (i+1, j) (x) and of
+    // (i-1, j) + (i+1, j) (c)
+    const uint32_t x0lo = xor3(llo, b.lo, rlo), x1lo = maj3(llo, b.lo, rlo);
+    const uint32_t x0hi = xor3(lhi, b.hi, rhi), x1hi = maj3(lhi, b.hi, rhi);
+    const uint32_t c0lo = llo ^ rlo, c1lo = llo & rlo;
+    const uint32_t c0hi = lhi ^ rhi, c1hi = lhi & rhi;
+    // the sums of the rows above (u) and below (d): row 7 of the block above
+    // and row 0 of the block below come from their lanes.  Their sums hold
+    // the corner cells (0,7) of the block above right and (7,0) of the block
+    // below left; where the block above (below) is missing, that cell is
+    // read directly and lands in a sum that is otherwise zero.
+    const uint32_t ne = pull_u32(nb[DNE], b.hi), sw = pull_u32(nb[DSW], b.lo);
+    const uint32_t n0 = pull_u32(nb[DN], x0hi) | ((ne << 7) & 0x80000000u);
+    const uint32_t n1 = pull_u32(nb[DN], x1hi);
+    const uint32_t s0 = pull_u32(nb[DS], x0lo) | ((sw >> 7) & 1u);
+    const uint32_t s1 = pull_u32(nb[DS], x1lo);
+    const uint32_t u0lo = funnel(x0lo, n0, 24), u0hi = funnel(x0hi, x0lo, 24);
+    const uint32_t u1lo = funnel(x1lo, n1, 24), u1hi = funnel(x1hi, x1lo, 24);
+    const uint32_t d0lo = funnel(x0hi, x0lo, 8), d0hi = funnel(s0, x0hi, 8);
+    const uint32_t d1lo = funnel(x1hi, x1lo, 8), d1hi = funnel(s1, x1hi, 8);
+    // neighbours = u + d + c (at most 3 + 3 + 2): bit 0 is the xor t of the
+    // low planes; with their carry k and the high planes' sum p and carry q,
+    // the count is 2 or 3 iff k + p + 2q == 1, i.e. (k ^ p) & ~q.  Alive next
+    // iff the count is 3, or 2 and alive now; non-members stay zero.
+    auto rule = [](uint32_t u0, uint32_t d0, uint32_t c0, uint32_t u1, uint32_t d1, uint32_t c1,
+                   uint32_t self, uint32_t members) {
+        const uint32_t t = xor3(u0, d0, c0), k = maj3(u0, d0, c0);
+        const uint32_t p = xor3(u1, d1, c1), q = maj3(u1, d1, c1);
+        return (k ^ p) & ~q & ((t | self) & members);
+    };
+    Board nx;
+    nx.lo = rule(u0lo, d0lo, c0lo, u1lo, d1lo, c1lo, b.lo, kMembersLo);
+    nx.hi = rule(u0hi, d0hi, c0hi, u1hi, d1hi, c1hi, b.hi, kMembersHi);
+    return nx;
 }
 
 } // namespace blk
 
 // One wavefront advances the tile t of a level-k automaton state `steps`
-// steps (1..16), src -> dst; all 64 lanes call it.
-template <int FL>
+// steps (1..D), src -> dst; all 64 lanes call it.
+template <int FL, int D>
 __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
                                               TileXY t, int steps)
 {
     using namespace blk;
-    const Region g = block_region(k, t);
+    constexpr int H = halo_blocks(D);
+    const Region g = block_region<true, D>(k, t);
     const int n = 1 << k;
     const int64_t base = (int64_t)(g.gy * kBlk) * n + (int64_t)g.gx * kBlk;
     // load: 8 bytes a row (rows 4..7 hold members in their first four)
@@ -117,28 +146,24 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
         });
         b = g.active ? (b & kMembers) : 0ull;
     }
-    auto step = [&](uint64_t cur) -> uint64_t {
-        const uint32_t lo = (uint32_t)cur, hi = (uint32_t)(cur >> 32);
-        // every lane takes part in every exchange (a lane with no such
-        // neighbour reads itself and drops the value)
-        uint32_t vn = pull_u32(g.lane[DN], hi), vs = pull_u32(g.lane[DS], lo);
-        uint32_t vw = pull_u32(g.lane[DW], lo), ve = pull_u32(g.lane[DE], lo);
-        uint32_t vne = pull_u32(g.lane[DNE], hi), vsw = pull_u32(g.lane[DSW], lo);
-        vn = g.ok[DN] ? vn : 0u;
-        vs = g.ok[DS] ? vs : 0u;
-        vw = g.ok[DW] ? vw : 0u;
-        ve = g.ok[DE] ? ve : 0u;
-        vne = g.ok[DNE] ? vne : 0u;
-        vsw = g.ok[DSW] ? vsw : 0u;
-        return life_step(cur, (vn >> 24) & 0xFFu, vs & 0xFFu, (vw >> 7) & 0x01010101u,
-                         (uint64_t)(ve & 0x01010101u) << 7, (vne >> 24) & 1u, (vsw >> 7) & 1u);
-    };
+    // the diagonal lanes only where the block relaying their corner cell is
+    // not held
+    uint32_t nb[kDirs];
+#pragma unroll
+    for (int d = 0; d < kDirs; ++d)
+        nb[d] = g.lane[d];
+    const uint32_t have_n = pull_u32(g.lane[DN], g.active ? 1u : 0u);
+    const uint32_t have_s = pull_u32(g.lane[DS], g.active ? 1u : 0u);
+    nb[DNE] = have_n ? kZeroLane : g.lane[DNE];
+    nb[DSW] = have_s ? kZeroLane : g.lane[DSW];
+    Board cur = {(uint32_t)b, (uint32_t)(b >> 32)};
     for (int s = 0; s < steps; ++s)
-        b = step(b);
+        cur = life_step(cur, nb);
+    b = ((uint64_t)cur.hi << 32) | cur.lo;
 
     // Store: a 64-byte segment is a whole tile row (eight blocks), so the
     // wavefront assembles its tile in LDS (zeros where blocks are empty)
-    // and each lane writes one tile row with four 16-byte stores.
+    // and writes it in 16-byte pieces, whole rows per instruction.
     __shared__ uint32_t rows[4][64 * 16]; // per wavefront: 64 rows of 64 bytes
     uint32_t *my = rows[threadIdx.x >> 6];
     const uint32_t lane = lane_id();
@@ -149,10 +174,10 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const bool inner = g.active && g.px >= kHaloBlk && g.px < kHaloBlk + kTileBlk &&
-                       g.py >= kHaloBlk && g.py < kHaloBlk + kTileBlk;
+    const bool inner = g.active && g.px >= H && g.px < H + kTileBlk && g.py >= H &&
+                       g.py < H + kTileBlk;
     if (inner) {
-        const int w0 = ((g.py - kHaloBlk) * kBlk) * 16 + (g.px - kHaloBlk) * 2;
+        const int w0 = ((g.py - H) * kBlk) * 16 + (g.px - H) * 2;
         static_for<0, kBlk>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             const uint32_t row = (uint32_t)(b >> (8 * j)) & 0xFFu;
@@ -164,16 +189,19 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {
-        // lane r: tile row r (every row of a non-empty tile holds members)
-        const int64_t y = ((int64_t)t.y << kTileLog) + lane;
-        u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + y * n + ((int64_t)t.x << kTileLog));
+        // four lanes per tile row, so that each store instruction writes 16
+        // whole 64-byte rows (every row of a non-empty tile holds members)
+        const uint32_t quarter = lane & 3u, r0 = lane >> 2;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const u32x4v v = *reinterpret_cast<const u32x4v *>(my + lane * 16 + 4 * q);
+            const uint32_t r = 16u * q + r0;
+            const int64_t y = ((int64_t)t.y << kTileLog) + r;
+            u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + y * n + ((int64_t)t.x << kTileLog)) + quarter;
+            const u32x4v v = *reinterpret_cast<const u32x4v *>(my + r * 16 + 4 * quarter);
             if constexpr (FL & TILE_NT_STORE)
-                __builtin_nontemporal_store(v, p + q);
+                __builtin_nontemporal_store(v, p);
             else
-                p[q] = v;
+                *p = v;
         }
     }
 }

@@ -10,7 +10,7 @@ namespace fractal {
 
 // One wavefront per tile: tile id `wave` of the map (lambda: the curve or
 // natural order; BB: row-major over all (n/64)^2 tiles, empty ones idle).
-template <int MAP, int FL>
+template <int MAP, int FL, int D>
 __global__ __launch_bounds__(256) void block_heat_kernel(BlockArgs a)
 {
     uint32_t wg = blockIdx.x;
@@ -31,16 +31,31 @@ __global__ __launch_bounds__(256) void block_heat_kernel(BlockArgs a)
     } else {
         t = lambda_wave_curve(tile, a.rb);
     }
-    block_tile<FL>(a.src, a.dst, a.k, a.alpha, t, a.steps);
+    block_tile<FL, D>(a.src, a.dst, a.k, a.alpha, t, a.steps);
 }
 
-static BlockFn pick_block(int map, bool nt)
+template <int MAP, int D>
+static BlockFn pick_block_d(bool nt)
 {
-    if (map == MAP_BB)
-        return nt ? block_heat_kernel<MAP_BB, TILE_NT_STORE> : block_heat_kernel<MAP_BB, 0>;
-    if (map == MAP_LAMBDA)
-        return nt ? block_heat_kernel<MAP_LAMBDA, TILE_NT_STORE> : block_heat_kernel<MAP_LAMBDA, 0>;
-    return nullptr;
+    return nt ? block_heat_kernel<MAP, TILE_NT_STORE, D> : block_heat_kernel<MAP, 0, D>;
+}
+
+// The heat kernel for launches of up to `depth` steps (16, 24 or 32).
+static BlockFn pick_block(int map, bool nt, int depth)
+{
+    if (map != MAP_BB && map != MAP_LAMBDA)
+        return nullptr;
+    const bool bb = map == MAP_BB;
+    switch (depth) {
+    case 16:
+        return bb ? pick_block_d<MAP_BB, 16>(nt) : pick_block_d<MAP_LAMBDA, 16>(nt);
+    case 24:
+        return bb ? pick_block_d<MAP_BB, 24>(nt) : pick_block_d<MAP_LAMBDA, 24>(nt);
+    case 32:
+        return bb ? pick_block_d<MAP_BB, 32>(nt) : pick_block_d<MAP_LAMBDA, 32>(nt);
+    default:
+        return nullptr;
+    }
 }
 
 // Launches: the fewest whose count has the parity of `steps` (the result
@@ -53,10 +68,13 @@ int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int 
         return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 tiles (r = 6)");
     const int cap = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
-    BlockFn fn = rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt) : pick_block(map, nt);
-    if (!fn || cap < 1 || cap > 16)
-        return set_error(FRACTAL_E_INVAL, "no block kernel for map %d, %d steps per launch", map,
-                         cap);
+    // the kernel whose halo covers `cap` steps: 16 cells up to 16 steps,
+    // then 24 and 32
+    const int depth = cap <= 16 ? 16 : (cap <= 24 ? 24 : 32);
+    BlockFn fn = rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt, depth) : pick_block(map, nt, depth);
+    if (!fn || cap < 1)
+        return set_error(FRACTAL_E_INVAL, "no block kernel for map %d, rule %d, %d steps per launch",
+                         map, rule, cap);
     if (steps <= 0)
         return FRACTAL_OK;
     int L = (steps + cap - 1) / cap;

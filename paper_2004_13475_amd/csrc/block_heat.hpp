@@ -79,16 +79,16 @@ __device__ __forceinline__ void block_step(const Cells &in, Cells &out, float nN
 } // namespace blk
 
 // One wavefront advances the tile t of a level-k state `steps` steps
-// (1..16), src -> dst; all 64 lanes call it.
-template <int FL>
+// (1..D), src -> dst; all 64 lanes call it.
+template <int FL, int D>
 __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
                                            float alpha_in, TileXY t, int steps)
 {
     using namespace blk;
-    const Region g = block_region(k, t);
+    constexpr int H = halo_blocks(D);
+    const Region g = block_region<false, D>(k, t);
     const bool active = g.active;
     const int px = g.px, py = g.py;
-    const bool okN = g.ok[DN], okS = g.ok[DS], okW = g.ok[DW], okE = g.ok[DE];
     const uint32_t lN = g.lane[DN], lS = g.lane[DS], lW = g.lane[DW], lE = g.lane[DE];
 
     // load the block's member chunks (rows 4..7 hold members in their
@@ -120,14 +120,11 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
     const float c1 = 1.0f - 4.0f * alpha;
     Cells d;
     auto exchange_step = [&](const Cells &in, Cells &out) {
-        float nN = pull(lN, in.v[kBlk - 1][0]);
-        float nS = pull(lS, in.v[0][0]);
-        float nW = pull(lW, in.v[0][kBlk - 1]);
-        float nE = pull(lE, in.v[0][0]);
-        nN = okN ? nN : 0.0f;
-        nS = okS ? nS : 0.0f;
-        nW = okW ? nW : 0.0f;
-        nE = okE ? nE : 0.0f;
+        // (zero from the zero lane where there is no such block)
+        const float nN = pull(lN, in.v[kBlk - 1][0]);
+        const float nS = pull(lS, in.v[0][0]);
+        const float nW = pull(lW, in.v[0][kBlk - 1]);
+        const float nE = pull(lE, in.v[0][0]);
         block_step(in, out, nN, nS, nW, nE, alpha, c1);
     };
     int s = 0;
@@ -143,8 +140,7 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
     // the tile's own blocks write their rows; a 64-byte segment spans two
     // blocks, so an even block whose right-hand partner is empty writes the
     // partner's half as zeros (whole segments are written)
-    const bool inner = active && px >= kHaloBlk && px < kHaloBlk + kTileBlk && py >= kHaloBlk &&
-                       py < kHaloBlk + kTileBlk;
+    const bool inner = active && px >= H && px < H + kTileBlk && py >= H && py < H + kTileBlk;
     if (inner) {
         uint8_t *dst = dst_state + base;
         const bool zero_partner = (gx & 1) == 0 && ((gx + 1) & gy) != 0;

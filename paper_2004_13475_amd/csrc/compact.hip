@@ -213,7 +213,7 @@ int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0, void *
     const int fuse = flags & kFuseFlags;
     if ((flags & ~(FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_MARCH |
                    kFuseFlags)) ||
-        (fuse & (fuse - 1)))
+        (fuse & (fuse - 1)) || (fuse & kDeepFlags))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", flags);
     int Tmax;
     bool nt;

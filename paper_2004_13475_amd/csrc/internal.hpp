@@ -61,17 +61,21 @@ StepFn pick_step_lambda(int rule, int r, int threads, int flags);
 StepFn pick_step_bb(int rule, int r, int threads, int flags);
 StepFn pick_step_mfma(int rule, int r, int threads, int flags);
 
-// Steps one launch advances under these flags (1, 2, 4, 8 or 16).
+// Steps one launch advances under these flags (1, 2, 4, 8, 16, or for the
+// block engine 24 or 32).
 inline int launch_steps_of(int flags)
 {
-    return (flags & FRACTAL_FLAG_FUSE16)  ? 16
-           : (flags & FRACTAL_FLAG_FUSE8) ? 8
-           : (flags & FRACTAL_FLAG_FUSE4) ? 4
-           : (flags & FRACTAL_FLAG_FUSE2) ? 2
-                                          : 1;
+    return (flags & FRACTAL_FLAG_FUSE32)   ? 32
+           : (flags & FRACTAL_FLAG_FUSE24) ? 24
+           : (flags & FRACTAL_FLAG_FUSE16) ? 16
+           : (flags & FRACTAL_FLAG_FUSE8)  ? 8
+           : (flags & FRACTAL_FLAG_FUSE4)  ? 4
+           : (flags & FRACTAL_FLAG_FUSE2)  ? 2
+                                           : 1;
 }
-constexpr int kFuseFlags =
-    FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8 | FRACTAL_FLAG_FUSE16;
+constexpr int kDeepFlags = FRACTAL_FLAG_FUSE24 | FRACTAL_FLAG_FUSE32; // block engine only
+constexpr int kFuseFlags = FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8 |
+                           FRACTAL_FLAG_FUSE16 | kDeepFlags;
 constexpr int kStackFlags = FRACTAL_FLAG_STACK2 | FRACTAL_FLAG_STACK4 | FRACTAL_FLAG_STACK8;
 // log2 of the highest stack under these flags (0: one tile per walk).
 inline int stack_log_of(int flags)
@@ -120,7 +124,8 @@ struct BlockArgs {
     int steps;      // steps this launch advances, 1..16
 };
 typedef void (*BlockFn)(BlockArgs);
-BlockFn pick_block_ca(int map, bool nt);
+// The automaton's block kernel for launches of up to `depth` steps (16 or 24).
+BlockFn pick_block_ca(int map, bool nt, int depth);
 // The block engine over a batch list (table, entries, tiles, slot, steps).
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
 BatchBlockFn pick_batch_block(int rule, bool nt);
