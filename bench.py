@@ -151,10 +151,10 @@ class Gasket:
 
 
 def steps_per_launch(tuning):
-    """Steps one launch advances: 32, 24 (block engine), 16, 8, 4 or 2 for
-    fused launches, else 1."""
+    """Steps one launch advances: 36, 32, 24 (block engine), 16, 8, 4 or 2
+    for fused launches, else 1."""
     fl = tuning[3] if len(tuning) > 3 else 0
-    for flag, T in ((16384, 32), (8192, 24), (128, 16), (64, 8), (16, 4), (8, 2)):
+    for flag, T in ((32768, 36), (16384, 32), (8192, 24), (128, 16), (64, 8), (16, 4), (8, 2)):
         if fl & flag:
             return T
     return 1
@@ -221,8 +221,9 @@ def bb_tuning(g, rule, r, lam=None):
         # the block engine takes 64 x 64 tiles only: the march at other sizes
         # (16 steps per launch at most)
         fl = (fl & ~g.F.FLAG_BLOCK) | g.F.FLAG_MARCH
-        if fl & (g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32):
-            fl = (fl & ~(g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32)) | g.F.FLAG_FUSE16
+        deep = g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32 | g.F.FLAG_FUSE36
+        if fl & deep:
+            fl = (fl & ~deep) | g.F.FLAG_FUSE16
     if fl & g.F.FLAG_FUSE16 and rule == 1 and r < 4:
         fl = (fl & ~g.F.FLAG_FUSE16) | g.F.FLAG_FUSE8  # heat: 16 steps need 16-cell tiles
     if (1 << r) * (1 if rule == 0 else 4) < 16:

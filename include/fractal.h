@@ -130,22 +130,21 @@ extern "C" {
 #define FRACTAL_FLAG_FUSE24 8192 /* 24 steps per launch (with
                                     FRACTAL_FLAG_BLOCK only: the halo grows
                                     to 24 cells) */
-#define FRACTAL_FLAG_FUSE32 16384 /* 32 steps per launch (with
-                                     FRACTAL_FLAG_BLOCK, heat only: a
-                                     32-cell halo) */
+#define FRACTAL_FLAG_FUSE32 16384 /* as FUSE24, 32 steps per launch */
+#define FRACTAL_FLAG_FUSE36 32768 /* as FUSE24, 36 steps per launch */
 #define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6), lambda or BB map:
                                    the block engine -- one wavefront per
                                    tile, one lane per non-empty 8 x 8 block of
                                    the tile and of the part of its halo
-                                   (16, 24 or 32 cells deep) that can reach
-                                   it within a launch (float32 cells in
+                                   (16 to 36 cells deep) that can reach it
+                                   within a launch (float32 cells in
                                    registers; automaton cells as a 64-bit
                                    board), neighbours exchanged between
                                    lanes; each launch advances up to the
-                                   FUSE flag's step count (at most 16, or 24
-                                   with FUSE24, or for heat 32 with FUSE32),
-                                   the steps of a call shared out evenly over
-                                   its launches.  Exclusive with
+                                   FUSE flag's step count (at most 16, or 24,
+                                   32, 36 with FUSE24 / 32 / 36), the steps of
+                                   a call shared out evenly over its
+                                   launches.  Exclusive with
                                    FRACTAL_FLAG_MARCH, STACK and OCC_ALT.
                                    Batches run instances of levels >= 6 on it
                                    too, with at most 16 steps per launch
@@ -439,8 +438,8 @@ int fractal_batch_workspace(int count, size_t *bytes);
  * FRACTAL_R_AUTO keeps the per-level tile size, tuning->threads 0 keeps the
  * default thread count, and tuning->flags, where any flag besides
  * FRACTAL_FLAG_PERSISTENT is set, applies to every instance (FUSE flags fall
- * back to what narrow tiles allow, FUSE24 and FUSE32 to FUSE16; STACK flags
- * are ignored).  With
+ * back to what narrow tiles allow, FUSE24 / 32 / 36 to FUSE16; STACK
+ * flags are ignored).  With
  * FRACTAL_FLAG_PERSISTENT the register-march launches run a persistent grid
  * (as many workgroups as the chip holds at once, the workgroups of each die
  * striding through that die's contiguous share of the list); LDS-engine

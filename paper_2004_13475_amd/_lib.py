@@ -23,7 +23,7 @@ FLAG_MARCH, FLAG_FUSE8, FLAG_FUSE16 = 32, 64, 128
 FLAG_STACK2, FLAG_STACK4, FLAG_STACK8 = 256, 512, 1024
 FLAG_OCC_ALT = 2048
 FLAG_BLOCK = 4096
-FLAG_FUSE24, FLAG_FUSE32 = 8192, 16384
+FLAG_FUSE24, FLAG_FUSE32, FLAG_FUSE36 = 8192, 16384, 32768
 MAP_LAMBDA, MAP_BB, MAP_MFMA = 0, 1, 2
 R_AUTO = -1
 

@@ -135,15 +135,14 @@ static fractal_tuning builtin_default(int k, int rule)
     if (k >= (ca ? 14 : 13)) {
         // the block engine, plain stores, in the curve order (neighbouring
         // tiles share halo blocks in L2; for the automaton split over the
-        // dies), with the deepest halo of the rule: a launch costs about
-        // the same at 16, 24 or 32 steps (its time goes to moving the tile),
-        // so the longest launch is the cheapest per step
+        // dies), with the deepest halo: a launch costs about the same at 16
+        // or 36 steps (its time goes to moving the tile), so the longest
+        // launch is the cheapest per step
         fractal_tuning t;
         t.r = 6;
         t.threads = 256;
         t.order = ca ? FRACTAL_ORDER_CURVE_XCD : FRACTAL_ORDER_CURVE;
-        t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS |
-                  (ca ? FRACTAL_FLAG_FUSE24 : FRACTAL_FLAG_FUSE32);
+        t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE36;
         return t;
     }
     const int r = clamp_r(k, 4);
@@ -324,15 +323,12 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
             return set_error(FRACTAL_E_INVAL, "block launches need FRACTAL_FLAG_SEGMENTS");
         if (fuse & (fuse - 1))
             return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
-        if ((fuse & FRACTAL_FLAG_FUSE32) && rule == FRACTAL_RULE_CA)
-            return set_error(FRACTAL_E_INVAL,
-                             "automaton block launches take at most 24 steps (FUSE24)");
         if (t->threads != 256)
             return set_error(FRACTAL_E_INVAL, "block launches take 256 threads");
         return FRACTAL_OK;
     }
     if (fuse & kDeepFlags)
-        return set_error(FRACTAL_E_INVAL, "FUSE24 and FUSE32 need FRACTAL_FLAG_BLOCK");
+        return set_error(FRACTAL_E_INVAL, "FUSE24, FUSE32 and FUSE36 need FRACTAL_FLAG_BLOCK");
     if (fuse & (fuse - 1))
         return set_error(FRACTAL_E_INVAL, "the FUSE flags are exclusive");
     if (stack & (stack - 1))
@@ -577,12 +573,12 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                                         r, 256, FRACTAL_ORDER_CURVE_XCD,
                                         FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse |
                                             stack | occ});
-        // 64 x 64 tiles: the block engine, 8 to 24 (heat: 32) steps per
-        // launch, every order, with and without non-temporal stores
+        // 64 x 64 tiles: the block engine, 8 to 36 steps per launch, every
+        // order, with and without non-temporal stores
         if (r == 6)
             for (int fuse : {(int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16,
-                             (int)FRACTAL_FLAG_FUSE24, (int)FRACTAL_FLAG_FUSE32})
-                if (fuse != FRACTAL_FLAG_FUSE32 || rule != FRACTAL_RULE_CA)
+                             (int)FRACTAL_FLAG_FUSE24, (int)FRACTAL_FLAG_FUSE32,
+                             (int)FRACTAL_FLAG_FUSE36})
                 for (int nt : {0, (int)FRACTAL_FLAG_NT_STORE})
                     for (int order : {FRACTAL_ORDER_NATURAL, FRACTAL_ORDER_CURVE,
                                       FRACTAL_ORDER_CURVE_XCD})

@@ -60,8 +60,8 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
     // become march launches of the same tile size and step count
     if ((t.flags & FRACTAL_FLAG_BLOCK) && (t.r != 6 || k < 6))
         t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
-    // batch launches advance at most 16 steps (the block engine's 16-cell
-    // halo; the march's longest launch)
+    // batch launches advance at most 16 steps (the batch block kernels take
+    // the 16-cell halo; the march's longest launch)
     if (t.flags & kDeepFlags)
         t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE16;
     if (t.flags & FRACTAL_FLAG_BLOCK)

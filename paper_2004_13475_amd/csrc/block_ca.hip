@@ -49,8 +49,12 @@ BlockFn pick_block_ca(int map, bool nt, int depth)
         return bb ? pick_block_ca_d<MAP_BB, 16>(nt) : pick_block_ca_d<MAP_LAMBDA, 16>(nt);
     case 24:
         return bb ? pick_block_ca_d<MAP_BB, 24>(nt) : pick_block_ca_d<MAP_LAMBDA, 24>(nt);
+    case 32:
+        return bb ? pick_block_ca_d<MAP_BB, 32>(nt) : pick_block_ca_d<MAP_LAMBDA, 32>(nt);
+    case 36:
+        return bb ? pick_block_ca_d<MAP_BB, 36>(nt) : pick_block_ca_d<MAP_LAMBDA, 36>(nt);
     default:
-        return nullptr; // no automaton table beyond 24 steps
+        return nullptr;
     }
 }
 

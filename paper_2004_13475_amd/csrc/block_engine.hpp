@@ -6,14 +6,15 @@
 // the 64 are non-empty), and it touches the neighbouring tiles only at
 // corner cells.  Within D steps a walk along the gasket from the tile gets
 // only a few blocks deep into the tiles to its left, above, to its right,
-// below and, for the automaton, above right and below left; the blocks it
-// can reach are listed per rule and D in block_slots.inc (generated by a
-// breadth-first search over every pattern of neighbouring tiles): 10, 18
-// or 28 blocks for heat at D = 16, 24, 32, 20 or 36 for the automaton at
-// D = 16, 24.  Each listed block has a fixed lane (a constant table per rule
-// and D), so a lane's block and the lanes of the blocks around it come
-// from one table entry; a halo lane takes part only when its tile exists.
-// The steps exchange the few cells where blocks touch by ds_bpermute (two
+// below, above right and below left, and which blocks it reaches depends
+// only on which of those six tiles exist (ten patterns occur, one of them
+// the lone tile of level 6).
+// block_slots.inc lists the blocks per pattern, rule and D (a breadth-first
+// search, gen_block_slots.py): at most 8 / 14 / 23 / 28 for heat at D = 16 /
+// 24 / 32 / 36, 11 / 21 / 29 / 33 for the automaton.  Each listed block has
+// a fixed lane (a constant table per rule, D and pattern), so a lane's block
+// and the lanes of the blocks around it come from one table entry.  The
+// steps exchange the few cells where blocks touch by ds_bpermute (two
 // neighbouring blocks of a gasket touch only at corner cells); lane 63
 // holds no block and stays zero, and stands for every neighbour the launch
 // does not hold.  Cells near the edge of what is held see zeros for what
@@ -65,100 +66,77 @@ __device__ __forceinline__ float pull(uint32_t lane, float v)
 // Directions of the neighbouring blocks a step reads from.
 enum Dir { DN = 0, DS, DW, DE, DNE, DSW, kDirs };
 
-// The tiles a lane's block can belong to: the tile itself and its
-// neighbours (kNone: no block).
-enum TileClass { kOwn = 0, kLeft, kAbove, kRight, kBelow, kAboveRight, kBelowLeft, kNone };
-
 constexpr uint32_t kZeroLane = 63; // holds no block: every value it gives is zero
 
-// The tile a block at (rx, ry), in blocks relative to the tile's first,
-// belongs to (kNone: the tiles above left and below right, which no walk of
-// these depths reaches).
-constexpr int tile_class(int rx, int ry)
-{
-    const bool l = rx < 0, r = rx >= kTileBlk, a = ry < 0, b = ry >= kTileBlk;
-    if (!l && !r && !a && !b)
-        return kOwn;
-    if (l && !a && !b)
-        return kLeft;
-    if (a && !l && !r)
-        return kAbove;
-    if (r && !a && !b)
-        return kRight;
-    if (b && !l && !r)
-        return kBelow;
-    if (r && a)
-        return kAboveRight;
-    if (l && b)
-        return kBelowLeft;
-    return kNone;
-}
-
-// One entry per lane: bits 0-3 and 4-7 the block's position in the region
-// (the tile's first block at (H, H), H = halo_blocks(D)), bits 8-10 its
-// TileClass, bits 16 + 8d.. the lane of the block in direction d (kZeroLane
-// where the table holds none).  Lanes 0..26 hold the tile's own blocks in
-// row-major order, then the halo blocks in the listed order.
+// One entry per lane: bits 0-4 and 5-9 the block's position in the region
+// (the tile's first block at (H, H), H = halo_blocks(D)), bit 10 set where
+// the lane holds a block, bits 16 + 8d.. the lane of the block in direction
+// d (kZeroLane where the list holds none).  Lanes 0..26 hold the tile's own
+// blocks in row-major order, then the pattern's halo blocks in the listed
+// order.
 struct SlotTable {
-    uint64_t e[64];
-    int count;
+    uint64_t e[kMaskCount][64];
+    int most; // the most lanes any pattern uses
 };
 
 template <int N>
-constexpr SlotTable make_slots(const int (&halo)[N][2], int H)
+constexpr SlotTable make_slots(const int (&halo)[kMaskCount][N][2], const int (&count)[kMaskCount],
+                               int H)
 {
     SlotTable s{};
-    int rx[64] = {}, ry[64] = {};
-    int n = 0;
-    for (int y = 0; y < kTileBlk; ++y)
-        for (int x = 0; x < kTileBlk; ++x)
-            if ((x & y) == 0) {
-                rx[n] = x;
-                ry[n] = y;
-                ++n;
-            }
-    for (int i = 0; i < N && n < 64; ++i) {
-        rx[n] = halo[i][0];
-        ry[n] = halo[i][1];
-        ++n;
-    }
-    s.count = 27 + N;
+    s.most = 0;
     const int dx[kDirs] = {0, 0, -1, 1, 1, -1}, dy[kDirs] = {-1, 1, 0, 0, -1, 1};
-    for (int i = 0; i < 64; ++i) {
-        uint64_t e = (uint64_t)kNone << 8;
-        for (int d = 0; d < kDirs; ++d)
-            e |= (uint64_t)kZeroLane << (16 + 8 * d);
-        if (i < n) {
-            e = (uint64_t)(rx[i] + H) | (uint64_t)(ry[i] + H) << 4 |
-                (uint64_t)tile_class(rx[i], ry[i]) << 8;
-            for (int d = 0; d < kDirs; ++d) {
-                uint64_t l = kZeroLane;
-                for (int j = 0; j < n; ++j)
-                    if (rx[j] == rx[i] + dx[d] && ry[j] == ry[i] + dy[d])
-                        l = (uint64_t)j;
-                e |= l << (16 + 8 * d);
-            }
+    for (int m = 0; m < kMaskCount; ++m) {
+        int rx[64] = {}, ry[64] = {};
+        int n = 0;
+        for (int y = 0; y < kTileBlk; ++y)
+            for (int x = 0; x < kTileBlk; ++x)
+                if ((x & y) == 0) {
+                    rx[n] = x;
+                    ry[n] = y;
+                    ++n;
+                }
+        for (int i = 0; i < count[m] && n < 64; ++i) {
+            rx[n] = halo[m][i][0];
+            ry[n] = halo[m][i][1];
+            ++n;
         }
-        s.e[i] = e;
+        s.most = n > s.most ? n : s.most;
+        for (int i = 0; i < 64; ++i) {
+            uint64_t e = 0;
+            for (int d = 0; d < kDirs; ++d)
+                e |= (uint64_t)kZeroLane << (16 + 8 * d);
+            if (i < n) {
+                e = (uint64_t)(rx[i] + H) | (uint64_t)(ry[i] + H) << 5 | 1ull << 10;
+                for (int d = 0; d < kDirs; ++d) {
+                    uint64_t l = kZeroLane;
+                    for (int j = 0; j < n; ++j)
+                        if (rx[j] == rx[i] + dx[d] && ry[j] == ry[i] + dy[d])
+                            l = (uint64_t)j;
+                    e |= l << (16 + 8 * d);
+                }
+            }
+            s.e[m][i] = e;
+        }
     }
     return s;
 }
 
-static __constant__ SlotTable kSlotsHeat16 = make_slots(kHalo_heat_16, halo_blocks(16));
-static __constant__ SlotTable kSlotsHeat24 = make_slots(kHalo_heat_24, halo_blocks(24));
-static __constant__ SlotTable kSlotsHeat32 = make_slots(kHalo_heat_32, halo_blocks(32));
-static __constant__ SlotTable kSlotsMoore16 = make_slots(kHalo_moore_16, halo_blocks(16));
-static __constant__ SlotTable kSlotsMoore24 = make_slots(kHalo_moore_24, halo_blocks(24));
-static_assert(make_slots(kHalo_heat_32, 4).count <= (int)kZeroLane &&
-                  make_slots(kHalo_moore_24, 3).count <= (int)kZeroLane,
+static __constant__ SlotTable kSlotsHeat16 = make_slots(kHalo_heat_16, kHaloCount_heat_16, 2);
+static __constant__ SlotTable kSlotsHeat24 = make_slots(kHalo_heat_24, kHaloCount_heat_24, 3);
+static __constant__ SlotTable kSlotsHeat32 = make_slots(kHalo_heat_32, kHaloCount_heat_32, 4);
+static __constant__ SlotTable kSlotsHeat36 = make_slots(kHalo_heat_36, kHaloCount_heat_36, 5);
+static __constant__ SlotTable kSlotsMoore16 = make_slots(kHalo_moore_16, kHaloCount_moore_16, 2);
+static __constant__ SlotTable kSlotsMoore24 = make_slots(kHalo_moore_24, kHaloCount_moore_24, 3);
+static __constant__ SlotTable kSlotsMoore32 = make_slots(kHalo_moore_32, kHaloCount_moore_32, 4);
+static __constant__ SlotTable kSlotsMoore36 = make_slots(kHalo_moore_36, kHaloCount_moore_36, 5);
+static_assert(make_slots(kHalo_heat_36, kHaloCount_heat_36, 5).most <= (int)kZeroLane &&
+                  make_slots(kHalo_moore_36, kHaloCount_moore_36, 5).most <= (int)kZeroLane,
               "every table leaves the zero lane free");
-
-// The largest step count of a launch that has a table for this rule.
-template <bool MOORE>
-constexpr int max_block_steps()
-{
-    return MOORE ? 24 : 32;
-}
+static_assert(halo_blocks(36) * 2 + kTileBlk <= 32, "region positions fit five bits");
+static_assert(kMaskIndex[0] >= 0 && kHaloCount_heat_36[kMaskIndex[0]] == 0 &&
+                  kHaloCount_moore_36[kMaskIndex[0]] == 0,
+              "a tile with no neighbours (level 6) has a pattern with no halo");
 
 // This lane's block of the region of tile t and the lanes holding the
 // blocks around it (kZeroLane where there is none, and for every direction
@@ -171,40 +149,50 @@ struct Region {
 };
 
 // MOORE: the automaton's eight-cell neighbourhood (otherwise the four-cell
-// one of heat); D: the most steps a launch takes (16, 24 or, for heat, 32).
-// All 64 lanes call it.
+// one of heat); D: the most steps a launch takes (16, 24, 32 or 36).  All 64
+// lanes call it.
 template <bool MOORE, int D>
 __device__ __forceinline__ Region block_region(int k, TileXY t)
 {
-    static_assert(D == 16 || D == 24 || (D == 32 && !MOORE), "no table for these steps");
+    static_assert(D == 16 || D == 24 || D == 32 || D == 36, "no table for these steps");
     constexpr int H = halo_blocks(D);
     const uint32_t lane = lane_id();
-    uint64_t e;
-    if constexpr (MOORE)
-        e = D == 16 ? kSlotsMoore16.e[lane] : kSlotsMoore24.e[lane];
-    else
-        e = D == 16 ? kSlotsHeat16.e[lane] : (D == 24 ? kSlotsHeat24.e[lane] : kSlotsHeat32.e[lane]);
     // which of the neighbouring tiles exist (are inside the array and
     // non-empty); the same for the whole wavefront
     const uint32_t nt = 1u << (k - kTileLog);
     const uint32_t tx = t.x, ty = t.y;
     const bool l = tx > 0u, r = tx + 1u < nt, a = ty > 0u, b = ty + 1u < nt;
-    uint32_t have = 1u << kOwn;
-    have |= (l && ((tx - 1u) & ty) == 0u) ? 1u << kLeft : 0u;
-    have |= (a && (tx & (ty - 1u)) == 0u) ? 1u << kAbove : 0u;
-    have |= (r && ((tx + 1u) & ty) == 0u) ? 1u << kRight : 0u;
-    have |= (b && (tx & (ty + 1u)) == 0u) ? 1u << kBelow : 0u;
-    have |= (r && a && ((tx + 1u) & (ty - 1u)) == 0u) ? 1u << kAboveRight : 0u;
-    have |= (l && b && ((tx - 1u) & (ty + 1u)) == 0u) ? 1u << kBelowLeft : 0u;
+    uint32_t mask = 0u;
+    mask |= (l && ((tx - 1u) & ty) == 0u) ? 1u : 0u;
+    mask |= (a && (tx & (ty - 1u)) == 0u) ? 2u : 0u;
+    mask |= (r && ((tx + 1u) & ty) == 0u) ? 4u : 0u;
+    mask |= (b && (tx & (ty + 1u)) == 0u) ? 8u : 0u;
+    mask |= (r && a && ((tx + 1u) & (ty - 1u)) == 0u) ? 16u : 0u;
+    mask |= (l && b && ((tx - 1u) & (ty + 1u)) == 0u) ? 32u : 0u;
+    // every mask a gasket's tile can have is listed; one that were not
+    // would take the lone tile's pattern (no halo, so nothing outside the
+    // array is read)
+    const int m = kMaskIndex[mask] < 0 ? kMaskIndex[0] : kMaskIndex[mask];
+    uint64_t e;
+    if constexpr (MOORE)
+        e = D == 16   ? kSlotsMoore16.e[m][lane]
+            : D == 24 ? kSlotsMoore24.e[m][lane]
+            : D == 32 ? kSlotsMoore32.e[m][lane]
+                      : kSlotsMoore36.e[m][lane];
+    else
+        e = D == 16   ? kSlotsHeat16.e[m][lane]
+            : D == 24 ? kSlotsHeat24.e[m][lane]
+            : D == 32 ? kSlotsHeat32.e[m][lane]
+                      : kSlotsHeat36.e[m][lane];
     Region g;
-    g.active = ((have >> ((uint32_t)(e >> 8) & 7u)) & 1u) != 0u;
-    g.px = (int)(e & 15u);
-    g.py = (int)((e >> 4) & 15u);
+    g.active = ((e >> 10) & 1u) != 0u;
+    g.px = (int)(e & 31u);
+    g.py = (int)((e >> 5) & 31u);
     g.gx = (int)(tx << (kTileLog - 3)) - H + g.px;
     g.gy = (int)(ty << (kTileLog - 3)) - H + g.py;
 #pragma unroll
     for (int d = 0; d < kDirs; ++d)
-        g.lane[d] = g.active ? (uint32_t)(e >> (16 + 8 * d)) & 63u : kZeroLane;
+        g.lane[d] = (uint32_t)(e >> (16 + 8 * d)) & 63u;
     return g;
 }
 

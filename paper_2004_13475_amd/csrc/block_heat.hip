@@ -40,7 +40,7 @@ static BlockFn pick_block_d(bool nt)
     return nt ? block_heat_kernel<MAP, TILE_NT_STORE, D> : block_heat_kernel<MAP, 0, D>;
 }
 
-// The heat kernel for launches of up to `depth` steps (16, 24 or 32).
+// The heat kernel for launches of up to `depth` steps (16, 24, 32 or 36).
 static BlockFn pick_block(int map, bool nt, int depth)
 {
     if (map != MAP_BB && map != MAP_LAMBDA)
@@ -53,6 +53,8 @@ static BlockFn pick_block(int map, bool nt, int depth)
         return bb ? pick_block_d<MAP_BB, 24>(nt) : pick_block_d<MAP_LAMBDA, 24>(nt);
     case 32:
         return bb ? pick_block_d<MAP_BB, 32>(nt) : pick_block_d<MAP_LAMBDA, 32>(nt);
+    case 36:
+        return bb ? pick_block_d<MAP_BB, 36>(nt) : pick_block_d<MAP_LAMBDA, 36>(nt);
     default:
         return nullptr;
     }
@@ -69,8 +71,8 @@ int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     const int cap = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
     // the kernel whose halo covers `cap` steps: 16 cells up to 16 steps,
-    // then 24 and 32
-    const int depth = cap <= 16 ? 16 : (cap <= 24 ? 24 : 32);
+    // then 24, 32 and 36
+    const int depth = cap <= 16 ? 16 : (cap <= 24 ? 24 : (cap <= 32 ? 32 : 36));
     BlockFn fn = rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt, depth) : pick_block(map, nt, depth);
     if (!fn || cap < 1)
         return set_error(FRACTAL_E_INVAL, "no block kernel for map %d, rule %d, %d steps per launch",

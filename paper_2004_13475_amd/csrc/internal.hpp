@@ -62,10 +62,11 @@ StepFn pick_step_bb(int rule, int r, int threads, int flags);
 StepFn pick_step_mfma(int rule, int r, int threads, int flags);
 
 // Steps one launch advances under these flags (1, 2, 4, 8, 16, or for the
-// block engine 24 or 32).
+// block engine 24, 32 or 36).
 inline int launch_steps_of(int flags)
 {
-    return (flags & FRACTAL_FLAG_FUSE32)   ? 32
+    return (flags & FRACTAL_FLAG_FUSE36)   ? 36
+           : (flags & FRACTAL_FLAG_FUSE32) ? 32
            : (flags & FRACTAL_FLAG_FUSE24) ? 24
            : (flags & FRACTAL_FLAG_FUSE16) ? 16
            : (flags & FRACTAL_FLAG_FUSE8)  ? 8
@@ -73,7 +74,7 @@ inline int launch_steps_of(int flags)
            : (flags & FRACTAL_FLAG_FUSE2)  ? 2
                                            : 1;
 }
-constexpr int kDeepFlags = FRACTAL_FLAG_FUSE24 | FRACTAL_FLAG_FUSE32; // block engine only
+constexpr int kDeepFlags = FRACTAL_FLAG_FUSE24 | FRACTAL_FLAG_FUSE32 | FRACTAL_FLAG_FUSE36; // block engine only
 constexpr int kFuseFlags = FRACTAL_FLAG_FUSE2 | FRACTAL_FLAG_FUSE4 | FRACTAL_FLAG_FUSE8 |
                            FRACTAL_FLAG_FUSE16 | kDeepFlags;
 constexpr int kStackFlags = FRACTAL_FLAG_STACK2 | FRACTAL_FLAG_STACK4 | FRACTAL_FLAG_STACK8;
@@ -124,7 +125,8 @@ struct BlockArgs {
     int steps;      // steps this launch advances, 1..16
 };
 typedef void (*BlockFn)(BlockArgs);
-// The automaton's block kernel for launches of up to `depth` steps (16 or 24).
+// The automaton's block kernel for launches of up to `depth` steps (16, 24,
+// 32 or 36).
 BlockFn pick_block_ca(int map, bool nt, int depth);
 // The block engine over a batch list (table, entries, tiles, slot, steps).
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);

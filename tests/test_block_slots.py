@@ -1,8 +1,11 @@
 """The halo blocks of the block engines (paper_2004_13475_amd/csrc/
-block_slots.inc): the committed file is what its generator writes, and every
-8 x 8 block that holds a member within D steps of some 64 x 64 tile of a real
-gasket is listed (found here by a different method: repeated dilation of
-each tile's members over the whole array, four or eight neighbours)."""
+block_slots.inc): the committed file is what its generator writes; the masks
+of non-empty neighbouring tiles it lists are all that occur in gasket tile
+arrays of 1 to 4096 tiles a side; and, tile by tile over a real gasket, the
+list of the tile's mask holds every 8 x 8 block with a member within D steps
+of the tile and nothing else (found here by a different method than the
+generator's breadth-first search over masks: repeated dilation of each
+tile's members over the whole array, four or eight neighbours)."""
 import os
 import re
 import subprocess
@@ -12,14 +15,42 @@ import numpy as np
 import pytest
 
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_2004_13475_amd", "csrc")
+VARIANTS = [("heat", False, d) for d in (16, 24, 32, 36)] + [("moore", True, d) for d in (16, 24, 32, 36)]
 
 
-def halo_lists():
+def parse():
     text = open(os.path.join(CSRC, "block_slots.inc")).read()
-    out = {}
-    for name, depth, body in re.findall(r"kHalo_(\w+?)_(\d+)\[\]\[2\] = \{(.*)\};", text):
-        out[(name, int(depth))] = {(int(a), int(b)) for a, b in re.findall(r"\{(-?\d+), (-?\d+)\}", body)}
-    return out
+    index = [int(v) for v in re.search(r"kMaskIndex\[64\] = \{([^}]*)\}", text).group(1).split(",")]
+    lists = {}
+    for name, depth, body in re.findall(r"kHalo_(\w+?)_(\d+)\[\d+\]\[\d+\]\[2\] = \{(.*?)\};", text, re.S):
+        counts = [int(v) for v in re.search(rf"kHaloCount_{name}_{depth}\[\d+\] = \{{([^}}]*)\}}",
+                                            text).group(1).split(",")]
+        rows = re.findall(r"\{((?:\{-?\d+, -?\d+\}(?:, )?)+)\}", body)
+        assert len(rows) == len(counts)
+        per = []
+        for row, c in zip(rows, counts):
+            pts = [(int(a), int(b)) for a, b in re.findall(r"\{(-?\d+), (-?\d+)\}", row)]
+            per.append(set(pts[:c]))
+            assert len(set(pts[:c])) == c
+        lists[(name, int(depth))] = per
+    return index, lists
+
+
+def tile_masks(nt):
+    """Mask of non-empty neighbouring tiles (bit 0 left, 1 above, 2 right, 3
+    below, 4 above right, 5 below left) of every tile of an nt x nt array;
+    -1 for empty tiles."""
+    t = np.arange(nt, dtype=np.int64)
+    tx, ty = t[None, :], t[:, None]
+
+    def present(dx, dy):
+        x, y = tx + dx, ty + dy
+        return (x >= 0) & (x < nt) & (y >= 0) & (y < nt) & ((x & y) == 0)
+
+    m = np.zeros((nt, nt), dtype=np.int64)
+    for bit, (dx, dy) in enumerate(((-1, 0), (0, -1), (1, 0), (0, 1), (1, -1), (-1, 1))):
+        m |= present(dx, dy).astype(np.int64) << bit
+    return np.where((tx & ty) == 0, m, -1)
 
 
 def test_generator_matches_committed_file():
@@ -28,26 +59,36 @@ def test_generator_matches_committed_file():
     assert r.returncode == 0, r.stdout + r.stderr
 
 
+def test_every_occurring_mask_is_listed():
+    index, _ = parse()
+    listed = {m for m in range(64) if index[m] >= 0}
+    every = set()
+    for j in range(13):
+        seen = set(np.unique(tile_masks(1 << j)).tolist()) - {-1}
+        assert seen <= listed, (1 << j, sorted(seen - listed))
+        every |= seen
+    assert every == listed
+    assert index[0] >= 0  # the lone tile of a level-6 array
+
+
 def reached_blocks(k, moore, depth):
-    """Blocks (relative to each tile's first block) holding a member within
-    `depth` steps of the tile, over all non-empty tiles of the level-k gasket."""
+    """Per non-empty tile (tx, ty) of the level-k gasket: the blocks outside
+    it (relative to its first block) holding a member within `depth` steps."""
     n = 1 << k
     x = np.arange(n)
     mem = (x[None, :] & x[:, None]) == 0  # [y, x]
-    out = set()
+    out = {}
     pad = depth + 1
     for ty in range(n >> 6):
         for tx in range(n >> 6):
             if tx & ty:
                 continue
-            # a window of the tile and `pad` cells around it (the array's
-            # edge closes it: cells beyond are not members)
             y0, y1 = max(0, ty * 64 - pad), min(n, ty * 64 + 64 + pad)
             x0, x1 = max(0, tx * 64 - pad), min(n, tx * 64 + 64 + pad)
             m = mem[y0:y1, x0:x1]
             cur = np.zeros_like(m)
-            cur[ty * 64 - y0:ty * 64 + 64 - y0, tx * 64 - x0:tx * 64 + 64 - x0] = \
-                m[ty * 64 - y0:ty * 64 + 64 - y0, tx * 64 - x0:tx * 64 + 64 - x0]
+            sy, sx = slice(ty * 64 - y0, ty * 64 + 64 - y0), slice(tx * 64 - x0, tx * 64 + 64 - x0)
+            cur[sy, sx] = m[sy, sx]
             for _ in range(depth):
                 g = cur.copy()
                 g[1:, :] |= cur[:-1, :]
@@ -63,20 +104,25 @@ def reached_blocks(k, moore, depth):
             ys, xs = np.nonzero(cur)
             bx = (xs + x0) // 8 - tx * 8
             by = (ys + y0) // 8 - ty * 8
-            out |= set(zip(bx.tolist(), by.tolist()))
-    return {b for b in out if not (0 <= b[0] < 8 and 0 <= b[1] < 8)}
+            out[(tx, ty)] = {b for b in zip(bx.tolist(), by.tolist())
+                             if not (0 <= b[0] < 8 and 0 <= b[1] < 8)}
+    return out
 
 
-@pytest.mark.parametrize("name,moore,depth", [("heat", False, 16), ("heat", False, 24),
-                                              ("heat", False, 32), ("moore", True, 16),
-                                              ("moore", True, 24)])
-def test_halo_lists_hold_every_reachable_block(name, moore, depth):
-    lists = halo_lists()
-    listed = lists[(name, depth)]
-    assert len(listed) <= 63 - 27, "27 tile blocks, the halo and a free zero lane fit 64 lanes"
-    for b in listed:  # listed blocks are non-empty within their tile
-        assert ((b[0] % 8) & (b[1] % 8)) == 0, b
-    found = reached_blocks(10, moore, depth)
-    assert found <= listed, sorted(found - listed)
-    # nothing listed is unreachable at level 10 (the list is the union, not a box)
-    assert listed == found, sorted(listed - found)
+@pytest.mark.parametrize("name,moore,depth", VARIANTS)
+def test_halo_lists_are_exactly_the_reachable_blocks(name, moore, depth):
+    index, lists = parse()
+    per_mask = lists[(name, depth)]
+    k = 10
+    masks = tile_masks(1 << (k - 6))
+    union = [set() for _ in per_mask]
+    for (tx, ty), found in reached_blocks(k, moore, depth).items():
+        i = index[int(masks[ty, tx])]
+        assert i >= 0
+        assert found <= per_mask[i], ((tx, ty), sorted(found - per_mask[i]))
+        union[i] |= found
+    for i, listed in enumerate(per_mask):
+        assert len(listed) <= 63 - 27, "27 tile blocks, the halo and a free zero lane fit 64 lanes"
+        for b in listed:  # listed blocks are non-empty within their tile
+            assert ((b[0] % 8) & (b[1] % 8)) == 0, b
+        assert union[i] == listed, (i, sorted(listed - union[i]))

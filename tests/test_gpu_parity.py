@@ -280,13 +280,13 @@ def test_block_engine_every_step_count(rule, map_):
     non-empty 8 x 8 block of the tile and of the part of its halo that can
     reach it; heat cells in registers, automaton cells as a 64-bit board)
     gives the same bits as one step per launch of the LDS engine for every
-    step count 1..40 (1..72 for the 24- and 32-step launches), every launch
-    cap (FUSE2 .. FUSE32, or none: one step per launch), every dispatch order
-    and both store kinds, at levels 6 (one tile, the halo outside the array),
-    7, 9 and 12; level 9 also against the oracle."""
+    step count 1..40 (1..72 for the 24-, 32- and 36-step launches), every
+    launch cap (FUSE2 .. FUSE36, or none: one step per launch), every
+    dispatch order and both store kinds, at levels 6 (one tile, the halo
+    outside the array), 7, 9 and 12; level 9 also against the oracle."""
     torch = torch_dev()
     BLOCK = F.FLAG_BLOCK | F.FLAG_SEGMENTS
-    deep = [F.FLAG_FUSE24] + ([F.FLAG_FUSE32] if rule == fi.RULE_HEAT else [])
+    deep = [F.FLAG_FUSE24, F.FLAG_FUSE32, F.FLAG_FUSE36]
     for k in (6, 7, 9, 12):
         init = fi.window_values(k, rule, 60 + k)
         cur, nxt = to_device(init), zeros_state(k, rule)
@@ -303,7 +303,7 @@ def test_block_engine_every_step_count(rule, map_):
         cases += [(d, 2, 0) for d in deep] + [(d, 1, F.FLAG_NT_STORE) for d in deep]
         for fuse, order, nt in cases:
             if fuse in deep:
-                step_list = range(1, 73) if (order == 2 and nt == 0) else (1, 23, 24, 25, 33, 47, 65)
+                step_list = range(1, 73) if (order == 2 and nt == 0) else (1, 23, 24, 25, 33, 36, 47, 65)
             elif fuse == F.FLAG_FUSE16 and order == 2:
                 step_list = range(1, 41)
             else:
@@ -331,20 +331,22 @@ def test_block_engine_every_step_count(rule, map_):
 
 @pytest.mark.parametrize("rule", RULES)
 def test_block_engine_full_size_k16_equals_march(rule):
-    """Level 16, the whole array: the block engine (lambda map; 16-step
-    launches and the deepest launches of the rule, 24 or 32 steps) gives the
-    same bits as the register march on 64 x 64 tiles after 1, 16, 37 and 64
-    steps, and its bounding-box form the same as its lambda form."""
+    """Level 16, the whole array: the block engine (lambda map; 16-, 24- and
+    36-step launches) gives the same bits as the register march on 64 x 64
+    tiles after 1, 16, 37 and 64 steps, and its bounding-box form the same
+    as its lambda form."""
     torch = torch_dev()
     k = 16
     n = 1 << k
     dt = torch.uint8 if rule == fi.RULE_CA else torch.float32
-    deep = F.FLAG_FUSE24 if rule == fi.RULE_CA else F.FLAG_FUSE32
+    deep = F.FLAG_FUSE36
     for steps in (1, 16, 37, 64):
         outs = []
         for map_, fl in ((F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16 |
                           F.FLAG_NT_STORE),
                          (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep),
+                         (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE24 |
+                          F.FLAG_NT_STORE),
                          (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep),
                          (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16)):
             b0 = torch.empty((n, n), dtype=dt, device="cuda")
@@ -416,7 +418,7 @@ def test_autotune_picks_a_valid_launch(rule):
     r, th, order, fl = t
     assert 0 <= r <= 7 and th in (64, 256) and order in (0, 1, 2)
     assert fl & ~(1 | 2 | 8 | 16 | 32 | 64 | 128 | 256 | 512 | 1024 | 2048 | 4096 | 8192 |
-                  16384) == 0
+                  16384 | 32768) == 0
     for steps in (5, 40):
         a0, a1 = to_device(init), zeros_state(k, rule)
         F.lambda_step(k, F.R_AUTO, rule, ALPHA, a0, a1, steps)

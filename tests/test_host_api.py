@@ -85,12 +85,10 @@ def test_tuning_defaults_and_validation():
                           for fuse in (0, 8, 16, 64, 128) for st in (0, 256, 512, 1024)
                           for occ in (0, 2048))
             block = tuple(4096 | 1 | fuse | nt for nt in (0, 2)
-                          for fuse in (0, 8, 16, 64, 128, 8192, 16384))
+                          for fuse in (0, 8, 16, 64, 128, 8192, 16384, 32768))
             assert flags in lds + march + block, (k, rule, flags)
             if flags & 4096:  # the block engine: 64 x 64 tiles
                 assert r == 6 and th == 256
-            if flags & 16384:  # 32 steps per launch: heat only
-                assert rule == 1
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
     with pytest.raises(F.FractalError):
@@ -237,9 +235,8 @@ def test_boundary_signatures():
 def test_block_engine_validation():
     """The block engine takes 64 x 64 tiles (r = 6) with whole segments and
     256 threads, the lambda or BB map, and no march, stack or occupancy
-    flags; 24 steps per launch for both rules, 32 for heat only, and those
-    only on the block engine; anything else is refused before any device
-    work."""
+    flags; 24, 32 and 36 steps per launch only on the block engine; anything
+    else is refused before any device work."""
     B = F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16
     bad = [(0, 0, 12, 5, 256, B),                       # automaton, 32 x 32 tiles
            (0, 1, 12, 5, 256, B),                       # 32 x 32 tiles
@@ -250,8 +247,9 @@ def test_block_engine_validation():
            (0, 1, 12, 6, 256, F.FLAG_BLOCK | F.FLAG_FUSE16),  # no whole segments
            (0, 1, 12, 6, 64, B),
            (0, 1, 12, 6, 256, B | F.FLAG_FUSE8),        # two FUSE flags
-           (0, 0, 12, 6, 256, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE32),  # automaton: 24 at most
+           (0, 1, 12, 6, 256, B & ~F.FLAG_FUSE16 | F.FLAG_FUSE24 | F.FLAG_FUSE36),
            (0, 1, 12, 4, 256, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE24),  # deep: block only
+           (0, 0, 12, 4, 256, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE36),
            (0, 1, 12, 4, 256, F.FLAG_SEGMENTS | F.FLAG_FUSE32)]
     for map_, rule, k, r, th, fl in bad:
         with pytest.raises(F.FractalError) as e:
@@ -333,8 +331,8 @@ def test_compact_sizes_and_validation():
         F.compact_bytes(21, 7, 0)
     # zero steps is a no-op that touches no device memory
     F.compact_step(10, 4, 0, 0.2, FAKE0, FAKE1, 0, 0, stream=0)
-    # compact states take the march engine: no 24- or 32-step launches
-    for fl in (F.FLAG_FUSE24, F.FLAG_FUSE32):
+    # compact states take the march engine: no 24-, 32- or 36-step launches
+    for fl in (F.FLAG_FUSE24, F.FLAG_FUSE32, F.FLAG_FUSE36):
         with pytest.raises(F.FractalError) as e:
             F.compact_step(10, 4, 0, 0.2, FAKE0, FAKE1, 0, fl, stream=0)
         assert e.value.code == F.E_INVAL
