@@ -600,7 +600,7 @@ def serve_leg(F, torch, seconds, rate=200.0, seed=2004, arena_gb=200.0):
 
     def run(paced):
         tickets = []
-        with F.Server(arena, nbytes, max_slots=256, steps_per_iter=16) as srv:
+        with F.Server(arena, nbytes, max_slots=256, steps_per_iter=32) as srv:
             t0 = F.now()
             for i in range(nreq):
                 target = t0 + (float(arrivals[i]) if paced else 0.0)

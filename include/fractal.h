@@ -147,7 +147,7 @@ extern "C" {
                                    launches.  Exclusive with
                                    FRACTAL_FLAG_MARCH, STACK and OCC_ALT.
                                    Batches run instances of levels >= 6 on it
-                                   too, with at most 16 steps per launch
+                                   too, with 16 or 32 steps per launch
                                    (smaller levels on the march); compact
                                    states take the march engine */
 
@@ -438,8 +438,8 @@ int fractal_batch_workspace(int count, size_t *bytes);
  * FRACTAL_R_AUTO keeps the per-level tile size, tuning->threads 0 keeps the
  * default thread count, and tuning->flags, where any flag besides
  * FRACTAL_FLAG_PERSISTENT is set, applies to every instance (FUSE flags fall
- * back to what narrow tiles allow, FUSE24 / 32 / 36 to FUSE16; STACK
- * flags are ignored).  With
+ * back to what narrow tiles allow; the block engine takes 16 or 32 steps per
+ * launch here, FUSE24 / 36 becoming FUSE32; STACK flags are ignored).  With
  * FRACTAL_FLAG_PERSISTENT the register-march launches run a persistent grid
  * (as many workgroups as the chip holds at once, the workgroups of each die
  * striding through that die's contiguous share of the list); LDS-engine
@@ -491,7 +491,7 @@ double fractal_now(void);
  * caller, 256-byte aligned; a small header of it holds the server's device
  * tables, the rest request states) with at most max_slots concurrently
  * admitted requests (1..4096), working on `stream`.  Each admitted request
- * advances 16 steps per scheduling iteration until
+ * advances 32 steps per scheduling iteration until
  * fractal_serve_set_steps_per_iter changes it.  Host threads are started;
  * the library allocates no device memory.  E_NOMEM if the arena cannot hold
  * the header. */
@@ -499,9 +499,10 @@ int fractal_serve_create(void *d_arena, size_t arena_bytes, int max_slots,
                          void *stream, void **server);
 
 /* Steps each admitted request advances per scheduling iteration (1..2^20),
- * from the next iteration on.  They are fused into launches of up to 16
- * (automaton) or 8 (heat) steps, so multiples of 16 let every launch take
- * its longest form; smaller values admit arriving requests sooner. */
+ * from the next iteration on.  They are fused into launches of up to 32
+ * steps (block engine, levels from 13 / 14) or 16 (march), so multiples of
+ * 32 let every launch take its longest form; smaller values admit arriving
+ * requests sooner. */
 int fractal_serve_set_steps_per_iter(void *server, int steps_per_iter);
 
 /* Queue a request; never waits for the GPU.  A request whose footprint

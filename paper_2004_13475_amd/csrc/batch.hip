@@ -60,10 +60,12 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
     // become march launches of the same tile size and step count
     if ((t.flags & FRACTAL_FLAG_BLOCK) && (t.r != 6 || k < 6))
         t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
-    // batch launches advance at most 16 steps (the batch block kernels take
-    // the 16-cell halo; the march's longest launch)
+    // a class's launches split into halvings of its largest, so batch block
+    // launches take 16 or 32 steps (24 and 36 become 32); the march's
+    // longest launch is 16 steps
     if (t.flags & kDeepFlags)
-        t.flags = (t.flags & ~kFuseFlags) | FRACTAL_FLAG_FUSE16;
+        t.flags = (t.flags & ~kFuseFlags) |
+                  ((t.flags & FRACTAL_FLAG_BLOCK) ? FRACTAL_FLAG_FUSE32 : FRACTAL_FLAG_FUSE16);
     if (t.flags & FRACTAL_FLAG_BLOCK)
         t.flags &= ~FRACTAL_FLAG_MARCH;
     t.flags &= FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_MARCH |
@@ -112,7 +114,7 @@ void BatchPlan::build(const std::vector<BatchItem> &items, BatchEntry *host)
         // launches per size: counts[j] of T >> j steps (LDS engine: T and 1 only)
         std::vector<std::array<int, kMaxListsPerItem>> counts(items.size());
         for (size_t i : g.second) {
-            int cnt[kMaxListsPerItem] = {0, 0, 0, 0};
+            int cnt[kMaxListsPerItem] = {};
             const int steps = items[i].steps;
             if (march) {
                 march_split(steps, T, cnt, !items[i].any_parity);
@@ -191,7 +193,10 @@ int BatchPlan::launch_slot(const BatchEntry *d_table, int t, bool persistent, hi
         const BatchEntry *tab = d_table + list.first;
         if (c.flags & FRACTAL_FLAG_BLOCK) {
             // one wavefront per tile, four per workgroup
-            BatchBlockFn fn = pick_batch_block(c.rule, (c.flags & FRACTAL_FLAG_NT_STORE) != 0);
+            BatchBlockFn fn = pick_batch_block(c.rule, (c.flags & FRACTAL_FLAG_NT_STORE) != 0,
+                                               launch_steps_of(c.flags) > 16 ? 32 : 16);
+            if (!fn)
+                return set_error(FRACTAL_E_INVAL, "no batch block kernel for flags 0x%x", c.flags);
             const uint64_t groups = (total + 3u) / 4u;
             if (groups > 0xFFFFFFFFull)
                 return set_error(FRACTAL_E_INVAL, "batch list of %llu tiles is too long",

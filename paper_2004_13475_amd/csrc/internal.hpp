@@ -130,7 +130,8 @@ typedef void (*BlockFn)(BlockArgs);
 BlockFn pick_block_ca(int map, bool nt, int depth);
 // The block engine over a batch list (table, entries, tiles, slot, steps).
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
-BatchBlockFn pick_batch_block(int rule, bool nt);
+// depth: the most steps of one launch of the list's class (16 or 32).
+BatchBlockFn pick_batch_block(int rule, bool nt, int depth);
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 
@@ -164,7 +165,7 @@ struct BatchEntry {
 };
 static_assert(sizeof(BatchEntry) == 48, "BatchEntry layout");
 // An instance sits in at most one list per launch size (16, 8, 4, 2, 1 steps).
-constexpr int kMaxListsPerItem = 5;
+constexpr int kMaxListsPerItem = 6; // launch sizes T, T/2, ..., T/32
 
 // One gasket advanced by a batched launch sequence.
 struct BatchItem {

@@ -25,9 +25,9 @@
 namespace fractal {
 
 // Steps each admitted request advances per scheduling iteration until
-// fractal_serve_set_steps_per_iter changes it: the automaton's longest
-// launch (16 steps) then always fits.
-constexpr int kDefaultStepsPerIter = 16;
+// fractal_serve_set_steps_per_iter changes it: the longest batch launch of
+// the block engines (32 steps; the march's are 16).
+constexpr int kDefaultStepsPerIter = 32;
 
 static double now_s()
 {

@@ -49,6 +49,9 @@ MARCH = F.FLAG_MARCH | F.FLAG_SEGMENTS
                                     (F.R_AUTO, 0, 0, MARCH | F.FLAG_FUSE16 | F.FLAG_PERSISTENT),
                                     (6, 0, 0, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16),
                                     (6, 0, 1, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE8 |
+                                     F.FLAG_NT_STORE),
+                                    (6, 0, 0, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE32),
+                                    (6, 0, 2, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE36 |
                                      F.FLAG_NT_STORE)])
 def test_batch_alone_equals_in_mix(tuning):
     """Every instance of a mixed batch (levels 1..11, both rules, 0..37
@@ -100,13 +103,13 @@ def test_batch_level8_to_13_many_steps(persistent):
 
 
 def test_batch_workspace_size_and_short_workspace():
-    """The workspace holds the per-instance offset table (5 entries of 48
+    """The workspace holds the per-instance offset table (6 entries of 48
     bytes per instance, rounded to 256 bytes); a short one is refused before
     anything is enqueued."""
     torch = torch_dev()
     assert F.batch_workspace(0) == 0
-    assert F.batch_workspace(1) == 256
-    assert F.batch_workspace(40) == (40 * 5 * 48 + 255) // 256 * 256
+    assert F.batch_workspace(1) == 512
+    assert F.batch_workspace(40) == (40 * 6 * 48 + 255) // 256 * 256
     k, rule = 6, fi.RULE_CA
     init = fi.window_values(k, rule, 2)
     b0, b1 = to_device(init), zeros_state(k, rule)

@@ -203,8 +203,9 @@ def test_batch_validation():
     F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], tuning=(4, 256, 2, 33 | 64 | 256), **w)
     F.batch_step([], **w)
     F.batch_step([(10, 0, 0, 0.2, FAKE0, FAKE1)], **w)  # no steps: no-op
-    assert F.batch_workspace(0) == 0 and F.batch_workspace(1) == 256
-    assert F.batch_workspace(65536) == 65536 * 5 * 48
+    # one 48-byte table entry per launch-size list (at most 6) per instance
+    assert F.batch_workspace(0) == 0 and F.batch_workspace(1) == 512
+    assert F.batch_workspace(65536) == 65536 * 6 * 48
     with pytest.raises(F.FractalError):
         F.batch_workspace(65537)
 
