@@ -91,6 +91,21 @@ def read_traffic(workload: str, rule_name: str):
     return float(m_bytes.group(1))
 
 
+def read_valu_issue(kernel: str):
+    """Fraction of the VALU issue ceiling a full-depth launch of `kernel`
+    reached (SQ counters), from the committed summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "block_k16_sq_counters.md")
+    if not kernel or not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    m = re.search(rf"valu_issue_frac {re.escape(kernel)}:\s*([0-9.]+)", txt)
+    if not m_hash or not m or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m.group(1))
+
+
 class Gasket:
     """A pair of state buffers per rule for one level, plus timing helpers."""
 
@@ -189,7 +204,10 @@ def roofline(rule, cells, stats, tuning, traffic=None, kernel=""):
             "avg_launch_us_stderr": stats["stderr_s"] * 1e6,
             "timing": f"{stats['reps']} sub-averages of {stats['launches']} back-to-back "
                       f"{spl}-step launches (HIP events on the launch stream)",
-            "per_step_equivalent_GBs": alg * spl / sec_per_launch / 1e9}
+            "per_step_equivalent_GBs": alg * spl / sec_per_launch / 1e9,
+            # the other limit of a deep launch: the share of the VALU issue
+            # ceiling its steps use (committed SQ counters)
+            "valu_issue_frac": read_valu_issue(kernel)}
 
 
 def launch_stats(g, rule, map_=None, tuning=None, reps=10, pairs=2):
