@@ -337,12 +337,17 @@ def sw_rd_leg(F, torch, k, reps=20):
 
 def compact_leg(F, torch, steps=64):
     """Compact storage (tiles kept in lambda order): per-step time and cell
-    rate at levels 16, 18 and 20 with the default compact launch, and the
-    state bytes against the n x n array's."""
+    rate at levels 16, 18 and 20 with the default compact launch (the block
+    engine on 64 x 64 tiles), and the state bytes against the n x n array's;
+    beside it the register march on compact states (the automaton on the
+    same tiles, heat on 32 x 32 tiles)."""
     stream = torch.cuda.current_stream()
     alpha = float(__import__("numpy").float32(ALPHA))
     out = {}
-    for rule, r in ((0, 6), (1, 5)):
+    march = F.FLAG_MARCH | F.FLAG_SEGMENTS
+    for name, rule, r, flags in (("ca", 0, 6, 0), ("heat", 1, 6, 0),
+                                 ("ca_march", 0, 6, march | F.FLAG_FUSE16 | F.FLAG_NT_STORE),
+                                 ("heat_march_r5", 1, 5, 0)):
         row = {}
         for k in (16, 18, 20):
             nbytes = F.compact_bytes(k, r, rule)
@@ -353,11 +358,11 @@ def compact_leg(F, torch, steps=64):
             c0 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             c1 = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
             F.compact_seed_fill(k, r, rule, 1, c0)
-            F.compact_step(k, r, rule, alpha, c0, c1, 32)
+            F.compact_step(k, r, rule, alpha, c0, c1, 32, flags)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            F.compact_step(k, r, rule, alpha, c0, c1, steps)
+            F.compact_step(k, r, rule, alpha, c0, c1, steps, flags)
             e1.record(stream)
             torch.cuda.synchronize()
             sec = e0.elapsed_time(e1) * 1e-3 / steps
@@ -366,7 +371,7 @@ def compact_leg(F, torch, steps=64):
                             "array_state_GB": (1 << (2 * k)) * (1 if rule == 0 else 4) / 1e9}
             del c0, c1
             torch.cuda.empty_cache()
-        out[RULE_NAME[rule]] = row
+        out[name] = row
     return out
 
 

@@ -347,14 +347,19 @@ int fractal_compact_seed_fill(int k, int r, int rule, uint32_t stream_id,
                               void *d_compact, void *stream);
 
 /* `steps` steps of `rule` on a compact state, ping-ponging between d_c0 and
- * d_c1 (result in buf[steps & 1]) with the register-march engine; each lane
- * finds the tiles around its own through lambda^-1.  Results equal
- * pack(fractal_lambda_step(unpack(state))) bit for bit.  flags: 0 for the
- * default (the longest launch the tile allows up to 16 steps for the
- * automaton from level 15, else 8; non-temporal stores from level 15), or
- * FRACTAL_FLAG_FUSE2/4/8/16 and FRACTAL_FLAG_NT_STORE (MARCH and SEGMENTS
- * are implied and accepted); steps per launch and halo must fit in one
- * tile (T <= rho).  k <= 20; buffers of fractal_compact_bytes each. */
+ * d_c1 (result in buf[steps & 1]).  States of 64 x 64 tiles (r = 6) take
+ * the block engine (one wavefront per tile in curve order, the neighbouring
+ * tiles found by lambda^-1); other tile sizes the register-march engine,
+ * each lane finding the tiles around its own through lambda^-1.  Results
+ * equal pack(fractal_lambda_step(unpack(state))) bit for bit.  flags: 0 for
+ * the default (r = 6: the block engine, up to 36 steps per launch; else the
+ * longest march launch the tile allows, up to 16 steps for the automaton
+ * from level 15, else 8, non-temporal stores from level 15), or
+ * FRACTAL_FLAG_FUSE2/4/8/16 and FRACTAL_FLAG_NT_STORE for the march (MARCH
+ * and SEGMENTS are implied and accepted; steps per launch and halo must fit
+ * in one tile, T <= rho), or FRACTAL_FLAG_BLOCK (r = 6) with a FUSE flag up
+ * to FUSE36 and FRACTAL_FLAG_NT_STORE.  k <= 20; buffers of
+ * fractal_compact_bytes each; cells off the gasket must be zero in both. */
 int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0,
                          void *d_c1, int steps, int flags, void *stream);
 

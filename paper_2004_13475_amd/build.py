@@ -31,7 +31,7 @@ SOURCES = ["api.cpp", "step_kernels.hip", "step_lambda.hip", "step_bb.hip", "ste
            "step_march.hip", "step_march_ca.hip", "step_march_heat.hip",
            "step_march_mid_ca.hip", "step_march_mid_heat.hip", "block_heat.hip", "block_ca.hip", "batch_block.hip",
            "seed.hip", "batch.hip", "batch_ca.hip", "batch_heat.hip", "batch_march_ca.hip", "batch_march_heat.hip",
-           "sw_rd.hip", "compact.hip", "compact_ca.hip", "compact_heat.hip", "nbb.hip",
+           "sw_rd.hip", "compact.hip", "compact_ca.hip", "compact_heat.hip", "compact_block.hip", "nbb.hip",
            "serve.cpp"]
 
 

@@ -122,16 +122,17 @@ __device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
 } // namespace blk
 
 // One wavefront advances the tile t of a level-k automaton state `steps`
-// steps (1..D), src -> dst; all 64 lanes call it.
-template <int FL, int D>
+// steps (1..D), src -> dst, the cells where `lay` puts them; all 64 lanes
+// call it.
+template <int FL, int D, class Layout>
 __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
-                                              TileXY t, int steps)
+                                              TileXY t, int steps, const Layout &lay)
 {
     using namespace blk;
     constexpr int H = halo_blocks(D);
     const Region g = block_region<true, D>(k, t);
-    const int n = 1 << k;
-    const int64_t base = (int64_t)(g.gy * kBlk) * n + (int64_t)g.gx * kBlk;
+    const int64_t base = lay.block_off(g.gx, g.gy);
+    const int64_t P = lay.pitch(); // bytes between a block's rows
     // load: 8 bytes a row (rows 4..7 hold members in their first four)
     uint64_t b = 0;
     {
@@ -140,7 +141,7 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
         const uint8_t *src = src_state + (g.active ? base : 0);
         static_for<0, kBlk>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const u32x2 v = *(gu2 *)(src + (int64_t)j * n);
+            const u32x2 v = *(gu2 *)(src + j * P);
             const uint64_t row = pack4(v[0]) | (pack4(v[1]) << 4);
             b |= row << (8 * j);
         });
@@ -195,8 +196,7 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t r = 16u * q + r0;
-            const int64_t y = ((int64_t)t.y << kTileLog) + r;
-            u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + y * n + ((int64_t)t.x << kTileLog)) + quarter;
+            u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + lay.tile_row((int)r)) + quarter;
             const u32x4v v = *reinterpret_cast<const u32x4v *>(my + r * 16 + 4 * quarter);
             if constexpr (FL & TILE_NT_STORE)
                 __builtin_nontemporal_store(v, p);
@@ -204,6 +204,14 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
                 *p = v;
         }
     }
+}
+
+// The n x n array form.
+template <int FL, int D>
+__device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
+                                              TileXY t, int steps)
+{
+    block_ca_tile<FL, D>(src_state, dst_state, k, t, steps, blk::ArrayLayout{(int64_t)1 << k, 1, t});
 }
 
 } // namespace fractal

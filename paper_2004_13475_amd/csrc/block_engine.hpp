@@ -196,6 +196,94 @@ __device__ __forceinline__ Region block_region(int k, TileXY t)
     return g;
 }
 
+// Where a state's cells live.  ArrayLayout: the n x n array, row-major.
+struct ArrayLayout {
+    int64_t row_bytes; // bytes per array row
+    int S;             // bytes per cell
+    TileXY t;          // the tile the wavefront advances
+    __device__ __forceinline__ int64_t block_off(int gx, int gy) const
+    {
+        return (int64_t)(gy * kBlk) * row_bytes + (int64_t)gx * kBlk * S;
+    }
+    __device__ __forceinline__ int64_t pitch() const { return row_bytes; }
+    __device__ __forceinline__ int64_t tile_row(int r) const
+    {
+        return (((int64_t)t.y << kTileLog) + r) * row_bytes + ((int64_t)t.x << kTileLog) * S;
+    }
+};
+
+// The base-3 reading of a byte's bits: sum of 3^i over its set bits i.
+struct Base3Bytes {
+    uint32_t v[256];
+};
+constexpr Base3Bytes make_base3_bytes()
+{
+    Base3Bytes b{};
+    for (int x = 0; x < 256; ++x) {
+        uint32_t s = 0, p = 1;
+        for (int i = 0; i < 8; ++i, p *= 3)
+            s += ((x >> i) & 1) ? p : 0u;
+        b.v[x] = s;
+    }
+    return b;
+}
+static __constant__ Base3Bytes kBase3Bytes = make_base3_bytes();
+
+// lambda^-1 of tile (x, y) of a level-rb tile space (rb <= 16): its curve
+// index, whose base-3 digit mu is 2 where bit mu of x is set, 0 where that
+// of y is, 1 elsewhere, i.e. (3^rb - 1) / 2 + B(x) - B(y) with B the base-3
+// reading of a bit pattern.  Wave-uniform arguments keep it in scalar
+// registers.  Coordinates outside the space give some index (unused).
+__device__ __forceinline__ uint32_t curve_index(uint32_t x, uint32_t y, int rb)
+{
+    auto b3 = [](uint32_t v) {
+        return kBase3Bytes.v[v & 255u] + 6561u * kBase3Bytes.v[(v >> 8) & 255u];
+    };
+    return (pow3_u32((uint32_t)rb) - 1u) / 2u + b3(x) - b3(y);
+}
+
+// Compact storage: the non-empty 64 x 64 tiles in curve order, each
+// row-major; a launch reads blocks of the tile and of its left, above,
+// right, below, above-right and below-left neighbours, found by their curve
+// indices.
+struct CompactLayout {
+    int S; // bytes per cell
+    TileXY t;
+    uint32_t own, left, above, right, below, aright, bleft;
+    __device__ __forceinline__ int64_t block_off(int gx, int gy) const
+    {
+        const int dx = (gx >> 3) - (int)t.x, dy = (gy >> 3) - (int)t.y;
+        uint32_t i = own;
+        i = dx < 0 ? (dy > 0 ? bleft : left) : i;
+        i = dx > 0 ? (dy < 0 ? aright : right) : i;
+        i = dx == 0 ? (dy < 0 ? above : (dy > 0 ? below : own)) : i;
+        return ((((int64_t)i << (2 * kTileLog)) + ((int64_t)((gy & 7) * kBlk) << kTileLog) +
+                 (gx & 7) * kBlk) *
+                S);
+    }
+    __device__ __forceinline__ int64_t pitch() const { return (int64_t)S << kTileLog; }
+    __device__ __forceinline__ int64_t tile_row(int r) const
+    {
+        return (((int64_t)own << (2 * kTileLog)) + ((int64_t)r << kTileLog)) * S;
+    }
+};
+
+// The compact layout of tile t, curve index L, of a level-rb tile space.
+__device__ __forceinline__ CompactLayout compact_layout(TileXY t, uint32_t L, int rb, int S)
+{
+    CompactLayout c;
+    c.S = S;
+    c.t = t;
+    c.own = L;
+    c.left = curve_index(t.x - 1u, t.y, rb);
+    c.above = curve_index(t.x, t.y - 1u, rb);
+    c.right = curve_index(t.x + 1u, t.y, rb);
+    c.below = curve_index(t.x, t.y + 1u, rb);
+    c.aright = curve_index(t.x + 1u, t.y - 1u, rb);
+    c.bleft = curve_index(t.x - 1u, t.y + 1u, rb);
+    return c;
+}
+
 } // namespace blk
 
 } // namespace fractal

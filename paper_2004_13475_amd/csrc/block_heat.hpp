@@ -79,10 +79,10 @@ __device__ __forceinline__ void block_step(const Cells &in, Cells &out, float nN
 } // namespace blk
 
 // One wavefront advances the tile t of a level-k state `steps` steps
-// (1..D), src -> dst; all 64 lanes call it.
-template <int FL, int D>
+// (1..D), src -> dst, the cells where `lay` puts them; all 64 lanes call it.
+template <int FL, int D, class Layout>
 __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
-                                           float alpha_in, TileXY t, int steps)
+                                           float alpha_in, TileXY t, int steps, const Layout &lay)
 {
     using namespace blk;
     constexpr int H = halo_blocks(D);
@@ -93,17 +93,17 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
 
     // load the block's member chunks (rows 4..7 hold members in their
     // first four cells only)
-    const int n = 1 << k;
     const int gx = g.gx, gy = g.gy;
-    const int64_t base = ((int64_t)(gy * kBlk) * n + (int64_t)gx * kBlk) * 4;
+    const int64_t base = lay.block_off(gx, gy);
+    const int64_t P = lay.pitch(); // bytes between a block's rows
     Cells c;
     {
         using gf4 = const __attribute__((address_space(1))) f32x4;
         const uint8_t *src = src_state + (active ? base : 0);
         static_for<0, kBlk>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const f32x4 v0 = *(gf4 *)(src + (int64_t)j * n * 4);
-            const f32x4 v1 = (j & 4) == 0 ? *(gf4 *)(src + (int64_t)j * n * 4 + 16) : f32x4{0, 0, 0, 0};
+            const f32x4 v0 = *(gf4 *)(src + j * P);
+            const f32x4 v1 = (j & 4) == 0 ? *(gf4 *)(src + j * P + 16) : f32x4{0, 0, 0, 0};
             static_for<0, 4>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 c.v[j][i] = mem(i, j) ? v0[i] : 0.0f;
@@ -152,7 +152,7 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
                 v0[i] = mem(i, j) ? c.v[j][i] : 0.0f;
                 v1[i] = mem(i + 4, j) ? c.v[j][i + 4] : 0.0f;
             });
-            f32x4 *p = reinterpret_cast<f32x4 *>(dst + (int64_t)j * n * 4);
+            f32x4 *p = reinterpret_cast<f32x4 *>(dst + j * P);
             const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
             if constexpr (FL & TILE_NT_STORE) {
                 __builtin_nontemporal_store(v0, p);
@@ -171,6 +171,15 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
             }
         });
     }
+}
+
+// The n x n array form.
+template <int FL, int D>
+__device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
+                                           float alpha_in, TileXY t, int steps)
+{
+    block_tile<FL, D>(src_state, dst_state, k, alpha_in, t, steps,
+                      blk::ArrayLayout{(int64_t)4 << k, 4, t});
 }
 
 } // namespace fractal

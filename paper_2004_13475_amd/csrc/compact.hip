@@ -211,10 +211,21 @@ int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0, void *
     if (p0 < p1 + bytes && p1 < p0 + bytes)
         return set_error(FRACTAL_E_INVAL, "the two compact buffers overlap");
     const int fuse = flags & kFuseFlags;
+    const bool block = (flags & FRACTAL_FLAG_BLOCK) != 0;
     if ((flags & ~(FRACTAL_FLAG_NT_STORE | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_MARCH |
-                   kFuseFlags)) ||
-        (fuse & (fuse - 1)) || (fuse & kDeepFlags))
+                   FRACTAL_FLAG_BLOCK | kFuseFlags)) ||
+        (fuse & (fuse - 1)) || ((fuse & kDeepFlags) && !block) ||
+        (block && (flags & FRACTAL_FLAG_MARCH)))
         return set_error(FRACTAL_E_INVAL, "unknown flags 0x%x", flags);
+    if (block && r != 6)
+        return set_error(FRACTAL_E_INVAL, "the block engine takes compact states of 64 x 64 tiles (r = 6)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // 64 x 64 tiles: the block engine (by default with 36 steps per launch)
+    if (block || (flags == 0 && r == 6)) {
+        const int cap = block ? launch_steps_of(flags) : 36;
+        return launch_compact_block(k, rule, alpha, d_c0, d_c1, steps, cap,
+                                    (flags & FRACTAL_FLAG_NT_STORE) != 0, s);
+    }
     int Tmax;
     bool nt;
     if (flags == 0) {
@@ -244,7 +255,6 @@ int fractal_compact_step(int k, int r, int rule, float alpha, void *d_c0, void *
     a.rb = rb;
     a.total = (uint32_t)pow3_u64(rb);
     uint8_t *bufs[2] = {static_cast<uint8_t *>(d_c0), static_cast<uint8_t *>(d_c1)};
-    hipStream_t s = static_cast<hipStream_t>(stream);
     int launch = 0;
     for (int j = 0; j < kMaxListsPerItem; ++j) {
         const int T = Tmax >> j;

@@ -132,6 +132,9 @@ BlockFn pick_block_ca(int map, bool nt, int depth);
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
 // depth: the most steps of one launch of the list's class (16 or 32).
 BatchBlockFn pick_batch_block(int rule, bool nt, int depth);
+// The block engine over compact storage of 64 x 64 tiles (compact_block.hip).
+int launch_compact_block(int k, int rule, float alpha, void *c0, void *c1, int steps, int cap,
+                         bool nt, hipStream_t s);
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s);
 

@@ -64,15 +64,21 @@ def _valid(rule, r, T):
     return T <= 16 and T <= rho and hl_cells <= rho
 
 
+BLOCK = F.FLAG_BLOCK | F.FLAG_SEGMENTS
+
+
 @pytest.mark.parametrize("rule", RULES)
 def test_compact_step_equals_array_step(rule):
-    """Compact steps (every tile size, 1..16 steps per launch, both store
-    kinds, step counts that exercise the power-of-two tail and the parity
-    split) give exactly the packed result of the same steps over the n x n
-    array; small levels also against the oracle."""
+    """Compact steps (every tile size, 1..16 march steps per launch, the
+    block engine on 64 x 64 tiles with 16 to 36 steps per launch -- the
+    default there -- both store kinds, step counts that exercise the
+    power-of-two tail and the parity split) give exactly the packed result
+    of the same steps over the n x n array; small levels also against the
+    oracle."""
     torch = torch_dev()
     fl_list = [0, F.FLAG_NT_STORE, F.FLAG_FUSE2, F.FLAG_FUSE4 | F.FLAG_NT_STORE, F.FLAG_FUSE8,
-               F.FLAG_FUSE16]
+               F.FLAG_FUSE16, BLOCK | F.FLAG_FUSE16, BLOCK | F.FLAG_FUSE24 | F.FLAG_NT_STORE,
+               BLOCK | F.FLAG_FUSE36]
     for k in (4, 6, 8, 11):
         init = fi.window_values(k, rule, 80 + k)
         for r in _rs(rule):
@@ -90,13 +96,22 @@ def test_compact_step_equals_array_step(rule):
             for fl in fl_list:
                 T = 16 if fl & F.FLAG_FUSE16 else 8 if fl & F.FLAG_FUSE8 else \
                     4 if fl & F.FLAG_FUSE4 else 2 if fl & F.FLAG_FUSE2 else 1
-                if fl != 0 and not _valid(rule, r, T):
+                ok = (r == 6) if fl & F.FLAG_BLOCK else (fl == 0 or _valid(rule, r, T))
+                if not ok:
                     with pytest.raises(F.FractalError) as e:
                         F.compact_step(k, r, rule, ALPHA, _cbuf(k, r, rule), _cbuf(k, r, rule),
                                        4, fl)
                     assert e.value.code == F.E_INVAL
                     continue
-                for steps in STEPS:
+                for steps in STEPS + ((72, 73) if fl & F.FLAG_BLOCK or r == 6 else ()):
+                    if steps not in refs:
+                        a0, a1 = to_device(init), zeros_state(k, rule)
+                        F.step_tuned(F.MAP_LAMBDA, k, rule, ALPHA, a0, a1, steps, r, 64, 2,
+                                     F.FLAG_SEGMENTS)
+                        c = _cbuf(k, r, rule)
+                        F.pack(k, r, rule, a0 if steps % 2 == 0 else a1, c)
+                        _sync()
+                        refs[steps] = c.view(torch.uint8).clone()
                     c0, c1 = _cbuf(k, r, rule), _cbuf(k, r, rule)
                     F.pack(k, r, rule, to_device(init), c0)
                     F.compact_step(k, r, rule, ALPHA, c0, c1, steps, fl)
@@ -118,10 +133,17 @@ def test_compact_level18_sampled(rule, k):
     """Level 18 (387,420,489 cells; the n x n array would take 69 GB per
     float32 buffer) and, for the automaton, level 20 (3.5e9 cells, 19.6 GB
     per compact state, byte offsets past 2^34): 64 compact steps from the
-    compact seeded fill, sampled in light-cone windows against the oracle."""
+    compact seeded fill (the block engine on 64 x 64 tiles; heat at level 18
+    also on 32 x 32 tiles with the march), sampled in light-cone windows
+    against the oracle."""
+    torch = torch_dev()
+    for r in ((6,) if rule == fi.RULE_CA else (6, 5)):
+        _sampled(rule, k, r)
+
+
+def _sampled(rule, k, r):
     torch = torch_dev()
     steps = 64
-    r = 6 if rule == fi.RULE_CA else 5
     n = 1 << k
     c0, c1 = _cbuf(k, r, rule), _cbuf(k, r, rule)
     F.compact_seed_fill(k, r, rule, 7, c0)
@@ -158,6 +180,9 @@ def test_compact_rejects_bad_arguments():
         lambda: F.compact_step(8, 1, fi.RULE_HEAT, ALPHA, a, b, 2),        # 8-byte rows
         lambda: F.compact_step(8, 2, fi.RULE_HEAT, ALPHA, a, b, 2, F.FLAG_FUSE8),  # T > rho
         lambda: F.pack(17, 4, fi.RULE_CA, a, b),                           # array level > 16
+        lambda: F.compact_step(8, 4, fi.RULE_CA, ALPHA, a, b, 2, BLOCK | F.FLAG_FUSE16),  # r != 6
+        lambda: F.compact_step(8, 6, fi.RULE_CA, ALPHA, a, b, 2,
+                               BLOCK | F.FLAG_MARCH | F.FLAG_FUSE16),       # two engines
     ]
     for f in bad:
         with pytest.raises(F.FractalError) as e:
