@@ -179,6 +179,8 @@ def kernel_name(tuning, rule):
     """Name of the step kernel template a tuning launches."""
     fl = tuning[3] if len(tuning) > 3 else 0
     if fl & 4096:
+        if tuning[0] == 7:
+            return "block2_heat_kernel"
         return "block_ca_kernel" if rule == 0 else "block_heat_kernel"
     return "march_kernel" if fl & 32 else "step_kernel"
 
@@ -235,9 +237,9 @@ def bb_tuning(g, rule, r, lam=None):
     launch with whole segments."""
     t = lam or g.tunings[rule]
     fl = t[3]
-    if fl & g.F.FLAG_BLOCK and r != 6:
-        # the block engine takes 64 x 64 tiles only: the march at other sizes
-        # (16 steps per launch at most)
+    if fl & g.F.FLAG_BLOCK and r != 6 and not (r == 7 and rule == 1):
+        # the block engine takes 64 x 64 tiles (heat also 128 x 128): the
+        # march at other sizes (16 steps per launch at most)
         fl = (fl & ~g.F.FLAG_BLOCK) | g.F.FLAG_MARCH
         deep = g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32 | g.F.FLAG_FUSE36
         if fl & deep:

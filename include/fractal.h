@@ -132,12 +132,13 @@ extern "C" {
                                     to 24 cells) */
 #define FRACTAL_FLAG_FUSE32 16384 /* as FUSE24, 32 steps per launch */
 #define FRACTAL_FLAG_FUSE36 32768 /* as FUSE24, 36 steps per launch */
-#define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6), lambda or BB map:
-                                   the block engine -- one wavefront per
-                                   tile, one lane per non-empty 8 x 8 block of
-                                   the tile and of the part of its halo
-                                   (16 to 36 cells deep) that can reach it
-                                   within a launch (float32 cells in
+#define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6; heat also 128 x
+                                   128, r = 7, two blocks per lane), lambda
+                                   or BB map: the block engine -- one
+                                   wavefront per tile, one lane per non-empty
+                                   8 x 8 block of the tile and of the part of
+                                   its halo (16 to 36 cells deep) that can
+                                   reach it within a launch (float32 cells in
                                    registers; automaton cells as a 64-bit
                                    board), neighbours exchanged between
                                    lanes; each launch advances up to the

@@ -56,8 +56,11 @@ fractal_tuning batch_item_tuning(int k, int rule, const fractal_tuning *forced)
         if (forced->flags & ~FRACTAL_FLAG_PERSISTENT)
             t.flags = forced->flags;
     }
-    // the block engines take 64 x 64 tiles only; elsewhere their launches
-    // become march launches of the same tile size and step count
+    // the batch block kernels take 64 x 64 tiles (heat's 128 x 128 form
+    // steps down to them); elsewhere block launches become march launches
+    // of the same tile size and step count
+    if ((t.flags & FRACTAL_FLAG_BLOCK) && t.r == 7)
+        t.r = 6;
     if ((t.flags & FRACTAL_FLAG_BLOCK) && (t.r != 6 || k < 6))
         t.flags = (t.flags & ~FRACTAL_FLAG_BLOCK) | FRACTAL_FLAG_MARCH;
     // a class's launches split into halvings of its largest, so batch block

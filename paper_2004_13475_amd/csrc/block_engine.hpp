@@ -196,6 +196,109 @@ __device__ __forceinline__ Region block_region(int k, TileXY t)
     return g;
 }
 
+// The two-slot form on 128 x 128 tiles: 81 tile blocks and the halo of up
+// to 36 steps (at most 109 blocks) over 64 lanes, two blocks per lane.
+// Block q of the list (the tile's blocks row-major, then the halo) sits in
+// slot q >> 6 of lane q & 63; entry q: bits 0-4 and 5-9 the block's position
+// in the region (the tile from (H, H)), bit 10 set where the slot holds a
+// block, bits 16 + 8d.. the list index of the block in direction d (127,
+// slot 1 of lane 63, which never holds a block, where there is none).
+constexpr int kTile2Log = 7;                  // tiles of 128 x 128 cells
+constexpr int kTile2Blk = 1 << (kTile2Log - 3); // 16 blocks per tile side
+constexpr uint32_t kZeroSlot = 127;
+
+struct SlotTable2 {
+    uint64_t e[kMaskCount][128];
+    int most;
+};
+
+template <int N>
+constexpr SlotTable2 make_slots2(const int (&halo)[kMaskCount][N][2], const int (&count)[kMaskCount],
+                                 int H)
+{
+    SlotTable2 s{};
+    s.most = 0;
+    const int dx[kDirs] = {0, 0, -1, 1, 1, -1}, dy[kDirs] = {-1, 1, 0, 0, -1, 1};
+    for (int m = 0; m < kMaskCount; ++m) {
+        int rx[128] = {}, ry[128] = {};
+        int n = 0;
+        for (int y = 0; y < kTile2Blk; ++y)
+            for (int x = 0; x < kTile2Blk; ++x)
+                if ((x & y) == 0) {
+                    rx[n] = x;
+                    ry[n] = y;
+                    ++n;
+                }
+        for (int i = 0; i < count[m] && n < 128; ++i) {
+            rx[n] = halo[m][i][0];
+            ry[n] = halo[m][i][1];
+            ++n;
+        }
+        s.most = n > s.most ? n : s.most;
+        for (int q = 0; q < 128; ++q) {
+            uint64_t e = 0;
+            for (int d = 0; d < kDirs; ++d)
+                e |= (uint64_t)kZeroSlot << (16 + 8 * d);
+            if (q < n) {
+                e = (uint64_t)(rx[q] + H) | (uint64_t)(ry[q] + H) << 5 | 1ull << 10;
+                for (int d = 0; d < kDirs; ++d) {
+                    uint64_t l = kZeroSlot;
+                    for (int j = 0; j < n; ++j)
+                        if (rx[j] == rx[q] + dx[d] && ry[j] == ry[q] + dy[d])
+                            l = (uint64_t)j;
+                    e |= l << (16 + 8 * d);
+                }
+            }
+            s.e[m][q] = e;
+        }
+    }
+    return s;
+}
+
+static __constant__ SlotTable2 kSlots2Heat36 =
+    make_slots2(kHalo_heat_36_t128, kHaloCount_heat_36_t128, halo_blocks(36));
+static_assert(make_slots2(kHalo_heat_36_t128, kHaloCount_heat_36_t128, 5).most <= (int)kZeroSlot,
+              "the zero slot stays free");
+static_assert(halo_blocks(36) * 2 + kTile2Blk <= 32, "region positions fit five bits");
+
+// One slot of a lane in the two-slot form.
+struct Slot2 {
+    bool active;
+    int px, py, gx, gy;
+    uint32_t nb[kDirs]; // list indices of the neighbouring blocks
+};
+
+// The two slots of this lane for tile t (128 x 128) of a level-k state,
+// heat's table of up to 36 steps.  All 64 lanes call it.
+__device__ __forceinline__ void block_region2(int k, TileXY t, Slot2 (&sl)[2])
+{
+    constexpr int H = halo_blocks(36);
+    const uint32_t lane = lane_id();
+    const uint32_t nt = 1u << (k - kTile2Log);
+    const uint32_t tx = t.x, ty = t.y;
+    const bool l = tx > 0u, r = tx + 1u < nt, a = ty > 0u, b = ty + 1u < nt;
+    uint32_t mask = 0u;
+    mask |= (l && ((tx - 1u) & ty) == 0u) ? 1u : 0u;
+    mask |= (a && (tx & (ty - 1u)) == 0u) ? 2u : 0u;
+    mask |= (r && ((tx + 1u) & ty) == 0u) ? 4u : 0u;
+    mask |= (b && (tx & (ty + 1u)) == 0u) ? 8u : 0u;
+    mask |= (r && a && ((tx + 1u) & (ty - 1u)) == 0u) ? 16u : 0u;
+    mask |= (l && b && ((tx - 1u) & (ty + 1u)) == 0u) ? 32u : 0u;
+    const int m = kMaskIndex[mask] < 0 ? kMaskIndex[0] : kMaskIndex[mask];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const uint64_t e = kSlots2Heat36.e[m][s * 64 + lane];
+        sl[s].active = ((e >> 10) & 1u) != 0u;
+        sl[s].px = (int)(e & 31u);
+        sl[s].py = (int)((e >> 5) & 31u);
+        sl[s].gx = (int)(tx << (kTile2Log - 3)) - H + sl[s].px;
+        sl[s].gy = (int)(ty << (kTile2Log - 3)) - H + sl[s].py;
+#pragma unroll
+        for (int d = 0; d < kDirs; ++d)
+            sl[s].nb[d] = (uint32_t)(e >> (16 + 8 * d)) & 127u;
+    }
+}
+
 // Where a state's cells live.  ArrayLayout: the n x n array, row-major.
 struct ArrayLayout {
     int64_t row_bytes; // bytes per array row

@@ -34,6 +34,40 @@ __global__ __launch_bounds__(256) void block_heat_kernel(BlockArgs a)
     block_tile<FL, D>(a.src, a.dst, a.k, a.alpha, t, a.steps);
 }
 
+// The two-slot form: one wavefront per 128 x 128 tile, up to 36 steps.
+template <int MAP, int FL>
+__global__ __launch_bounds__(256) void block2_heat_kernel(BlockArgs a)
+{
+    uint32_t wg = blockIdx.x;
+    if (a.order == FRACTAL_ORDER_CURVE_XCD)
+        wg = xcd_chunk(wg, gridDim.x);
+    const uint32_t tile = wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (tile >= a.total)
+        return; // wavefront-uniform
+    TileXY t;
+    if constexpr (MAP == MAP_BB) {
+        t.x = tile & ((1u << a.rb) - 1u);
+        t.y = tile >> a.rb;
+        if (t.x & t.y)
+            return; // empty tile: the whole wavefront leaves
+    } else if (a.order == FRACTAL_ORDER_NATURAL) {
+        const uint32_t gx = pow3_u32((uint32_t)(a.rb + 1) / 2u);
+        t = lambda_wave(tile % gx, tile / gx, a.rb);
+    } else {
+        t = lambda_wave_curve(tile, a.rb);
+    }
+    block2_tile<FL>(a.src, a.dst, a.k, a.alpha, t, a.steps, blk::ArrayLayout{(int64_t)4 << a.k, 4, t});
+}
+
+static BlockFn pick_block2(int map, bool nt)
+{
+    if (map == MAP_BB)
+        return nt ? block2_heat_kernel<MAP_BB, TILE_NT_STORE> : block2_heat_kernel<MAP_BB, 0>;
+    if (map == MAP_LAMBDA)
+        return nt ? block2_heat_kernel<MAP_LAMBDA, TILE_NT_STORE> : block2_heat_kernel<MAP_LAMBDA, 0>;
+    return nullptr;
+}
+
 template <int MAP, int D>
 static BlockFn pick_block_d(bool nt)
 {
@@ -66,15 +100,20 @@ static BlockFn pick_block(int map, bool nt, int depth)
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s)
 {
-    if (t.r != blk::kTileLog || k < blk::kTileLog)
-        return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 tiles (r = 6)");
+    // 64 x 64 tiles (one block per lane), or for heat 128 x 128 tiles (two)
+    const bool two = t.r == blk::kTile2Log;
+    if ((t.r != blk::kTileLog && !two) || k < t.r || (two && rule == FRACTAL_RULE_CA))
+        return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 tiles (r = 6), "
+                                          "or for heat on 128 x 128 tiles (r = 7)");
     const int cap = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
     // the kernel whose halo covers `cap` steps: 16 cells up to 16 steps,
-    // then 24, 32 and 36
+    // then 24, 32 and 36 (the two-slot form: 36)
     const int depth = cap <= 16 ? 16 : (cap <= 24 ? 24 : (cap <= 32 ? 32 : 36));
-    BlockFn fn = rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt, depth) : pick_block(map, nt, depth);
-    if (!fn || cap < 1)
+    BlockFn fn = two ? pick_block2(map, nt)
+                 : rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt, depth)
+                                           : pick_block(map, nt, depth);
+    if (!fn || cap < 1 || cap > 36)
         return set_error(FRACTAL_E_INVAL, "no block kernel for map %d, rule %d, %d steps per launch",
                          map, rule, cap);
     if (steps <= 0)
@@ -82,7 +121,7 @@ int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int 
     int L = (steps + cap - 1) / cap;
     if ((L & 1) != (steps & 1))
         ++L;
-    const int rb = k - blk::kTileLog;
+    const int rb = k - t.r;
     BlockArgs a;
     a.k = k;
     a.alpha = alpha;

@@ -76,6 +76,61 @@ __device__ __forceinline__ void block_step(const Cells &in, Cells &out, float nN
     });
 }
 
+// The member cells of the block whose first cell is at src (rows P bytes
+// apart; rows 4..7 hold members in their first four cells only); zeros
+// where the lane holds no block.
+__device__ __forceinline__ Cells load_block(const uint8_t *src, int64_t P, bool active)
+{
+    Cells c;
+    using gf4 = const __attribute__((address_space(1))) f32x4;
+    static_for<0, kBlk>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const f32x4 v0 = *(gf4 *)(src + j * P);
+        const f32x4 v1 = (j & 4) == 0 ? *(gf4 *)(src + j * P + 16) : f32x4{0, 0, 0, 0};
+        static_for<0, 4>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            c.v[j][i] = (active && mem(i, j)) ? v0[i] : 0.0f;
+            c.v[j][i + 4] = (active && mem(i + 4, j)) ? v1[i] : 0.0f;
+        });
+    });
+    return c;
+}
+
+// Writes block (gx, gy)'s rows at dst; a 64-byte segment spans two blocks,
+// so an even block whose right-hand partner is empty writes the partner's
+// half as zeros (whole segments are written).
+template <int FL>
+__device__ __forceinline__ void store_block(uint8_t *dst, int64_t P, int gx, int gy, const Cells &c)
+{
+    const bool zero_partner = (gx & 1) == 0 && ((gx + 1) & gy) != 0;
+    static_for<0, kBlk>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        f32x4 v0, v1;
+        static_for<0, 4>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            v0[i] = mem(i, j) ? c.v[j][i] : 0.0f;
+            v1[i] = mem(i + 4, j) ? c.v[j][i + 4] : 0.0f;
+        });
+        f32x4 *p = reinterpret_cast<f32x4 *>(dst + j * P);
+        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (FL & TILE_NT_STORE) {
+            __builtin_nontemporal_store(v0, p);
+            __builtin_nontemporal_store(v1, p + 1);
+            if (zero_partner) {
+                __builtin_nontemporal_store(z, p + 2);
+                __builtin_nontemporal_store(z, p + 3);
+            }
+        } else {
+            p[0] = v0;
+            p[1] = v1;
+            if (zero_partner) {
+                p[2] = z;
+                p[3] = z;
+            }
+        }
+    });
+}
+
 } // namespace blk
 
 // One wavefront advances the tile t of a level-k state `steps` steps
@@ -96,25 +151,7 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
     const int gx = g.gx, gy = g.gy;
     const int64_t base = lay.block_off(gx, gy);
     const int64_t P = lay.pitch(); // bytes between a block's rows
-    Cells c;
-    {
-        using gf4 = const __attribute__((address_space(1))) f32x4;
-        const uint8_t *src = src_state + (active ? base : 0);
-        static_for<0, kBlk>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            const f32x4 v0 = *(gf4 *)(src + j * P);
-            const f32x4 v1 = (j & 4) == 0 ? *(gf4 *)(src + j * P + 16) : f32x4{0, 0, 0, 0};
-            static_for<0, 4>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                c.v[j][i] = mem(i, j) ? v0[i] : 0.0f;
-                c.v[j][i + 4] = mem(i + 4, j) ? v1[i] : 0.0f;
-            });
-        });
-        if (!active)
-            static_for<0, kBlk>([&](auto jc) {
-                static_for<0, kBlk>([&](auto ic) { c.v[decltype(jc)::value][decltype(ic)::value] = 0.0f; });
-            });
-    }
+    Cells c = load_block(src_state + (active ? base : 0), P, active);
 
     const float alpha = alpha_in;
     const float c1 = 1.0f - 4.0f * alpha;
@@ -137,39 +174,64 @@ __device__ __forceinline__ void block_tile(const uint8_t *src_state, uint8_t *ds
         c = d;
     }
 
-    // the tile's own blocks write their rows; a 64-byte segment spans two
-    // blocks, so an even block whose right-hand partner is empty writes the
-    // partner's half as zeros (whole segments are written)
+    // the tile's own blocks write their rows
     const bool inner = active && px >= H && px < H + kTileBlk && py >= H && py < H + kTileBlk;
-    if (inner) {
-        uint8_t *dst = dst_state + base;
-        const bool zero_partner = (gx & 1) == 0 && ((gx + 1) & gy) != 0;
-        static_for<0, kBlk>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            f32x4 v0, v1;
-            static_for<0, 4>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                v0[i] = mem(i, j) ? c.v[j][i] : 0.0f;
-                v1[i] = mem(i + 4, j) ? c.v[j][i + 4] : 0.0f;
-            });
-            f32x4 *p = reinterpret_cast<f32x4 *>(dst + j * P);
-            const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            if constexpr (FL & TILE_NT_STORE) {
-                __builtin_nontemporal_store(v0, p);
-                __builtin_nontemporal_store(v1, p + 1);
-                if (zero_partner) {
-                    __builtin_nontemporal_store(z, p + 2);
-                    __builtin_nontemporal_store(z, p + 3);
-                }
-            } else {
-                p[0] = v0;
-                p[1] = v1;
-                if (zero_partner) {
-                    p[2] = z;
-                    p[3] = z;
-                }
-            }
-        });
+    if (inner)
+        store_block<FL>(dst_state + base, P, gx, gy, c);
+}
+
+// One wavefront advances the 128 x 128 tile t of a level-k state `steps`
+// steps (1..36), src -> dst, two blocks per lane; all 64 lanes call it.  A
+// step reads each neighbouring block's cell from both slots of the lane
+// that holds it and keeps the one of the block's slot.
+template <int FL, class Layout>
+__device__ __forceinline__ void block2_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
+                                            float alpha, TileXY t, int steps, const Layout &lay)
+{
+    using namespace blk;
+    constexpr int H = halo_blocks(36);
+    Slot2 sl[2];
+    block_region2(k, t, sl);
+    const int64_t P = lay.pitch();
+    Cells c[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+        c[s] = load_block(src_state + (sl[s].active ? lay.block_off(sl[s].gx, sl[s].gy) : 0), P,
+                          sl[s].active);
+    const float c1 = 1.0f - 4.0f * alpha;
+    // the value of `v` (per slot) held by list entry q
+    auto pull2 = [](uint32_t q, float v0, float v1) {
+        const float x0 = pull(q & 63u, v0), x1 = pull(q & 63u, v1);
+        return (q & 64u) ? x1 : x0;
+    };
+    auto exchange_step = [&](const Cells (&in)[2], Cells (&out)[2]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float nN = pull2(sl[s].nb[DN], in[0].v[kBlk - 1][0], in[1].v[kBlk - 1][0]);
+            const float nS = pull2(sl[s].nb[DS], in[0].v[0][0], in[1].v[0][0]);
+            const float nW = pull2(sl[s].nb[DW], in[0].v[0][kBlk - 1], in[1].v[0][kBlk - 1]);
+            const float nE = pull2(sl[s].nb[DE], in[0].v[0][0], in[1].v[0][0]);
+            block_step(in[s], out[s], nN, nS, nW, nE, alpha, c1);
+        }
+    };
+    Cells d[2];
+    int st = 0;
+    for (; st + 2 <= steps; st += 2) {
+        exchange_step(c, d);
+        exchange_step(d, c);
+    }
+    if (st < steps) {
+        exchange_step(c, d);
+        c[0] = d[0];
+        c[1] = d[1];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const bool inner = sl[s].active && sl[s].px >= H && sl[s].px < H + kTile2Blk &&
+                           sl[s].py >= H && sl[s].py < H + kTile2Blk;
+        if (inner)
+            store_block<FL>(dst_state + lay.block_off(sl[s].gx, sl[s].gy), P, sl[s].gx, sl[s].gy,
+                            c[s]);
     }
 }
 

@@ -15,15 +15,16 @@ import numpy as np
 import pytest
 
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_2004_13475_amd", "csrc")
-VARIANTS = [("heat", False, d) for d in (16, 24, 32, 36)] + [("moore", True, d) for d in (16, 24, 32, 36)]
+VARIANTS = ([(f"heat_{d}", False, d, 64) for d in (16, 24, 32, 36)] +
+            [(f"moore_{d}", True, d, 64) for d in (16, 24, 32, 36)] + [("heat_36_t128", False, 36, 128)])
 
 
 def parse():
     text = open(os.path.join(CSRC, "block_slots.inc")).read()
     index = [int(v) for v in re.search(r"kMaskIndex\[64\] = \{([^}]*)\}", text).group(1).split(",")]
     lists = {}
-    for name, depth, body in re.findall(r"kHalo_(\w+?)_(\d+)\[\d+\]\[\d+\]\[2\] = \{(.*?)\};", text, re.S):
-        counts = [int(v) for v in re.search(rf"kHaloCount_{name}_{depth}\[\d+\] = \{{([^}}]*)\}}",
+    for name, body in re.findall(r"kHalo_(\w+)\[\d+\]\[\d+\]\[2\] = \{(.*?)\};", text, re.S):
+        counts = [int(v) for v in re.search(rf"kHaloCount_{name}\[\d+\] = \{{([^}}]*)\}}",
                                             text).group(1).split(",")]
         rows = re.findall(r"\{((?:\{-?\d+, -?\d+\}(?:, )?)+)\}", body)
         assert len(rows) == len(counts)
@@ -32,7 +33,7 @@ def parse():
             pts = [(int(a), int(b)) for a, b in re.findall(r"\{(-?\d+), (-?\d+)\}", row)]
             per.append(set(pts[:c]))
             assert len(set(pts[:c])) == c
-        lists[(name, int(depth))] = per
+        lists[name] = per
     return index, lists
 
 
@@ -71,23 +72,25 @@ def test_every_occurring_mask_is_listed():
     assert index[0] >= 0  # the lone tile of a level-6 array
 
 
-def reached_blocks(k, moore, depth):
-    """Per non-empty tile (tx, ty) of the level-k gasket: the blocks outside
-    it (relative to its first block) holding a member within `depth` steps."""
+def reached_blocks(k, moore, depth, tile=64):
+    """Per non-empty tile (tx, ty) (side `tile`) of the level-k gasket: the
+    blocks outside it (relative to its first block) holding a member within
+    `depth` steps."""
     n = 1 << k
     x = np.arange(n)
     mem = (x[None, :] & x[:, None]) == 0  # [y, x]
     out = {}
     pad = depth + 1
-    for ty in range(n >> 6):
-        for tx in range(n >> 6):
+    T = tile
+    for ty in range(n // T):
+        for tx in range(n // T):
             if tx & ty:
                 continue
-            y0, y1 = max(0, ty * 64 - pad), min(n, ty * 64 + 64 + pad)
-            x0, x1 = max(0, tx * 64 - pad), min(n, tx * 64 + 64 + pad)
+            y0, y1 = max(0, ty * T - pad), min(n, ty * T + T + pad)
+            x0, x1 = max(0, tx * T - pad), min(n, tx * T + T + pad)
             m = mem[y0:y1, x0:x1]
             cur = np.zeros_like(m)
-            sy, sx = slice(ty * 64 - y0, ty * 64 + 64 - y0), slice(tx * 64 - x0, tx * 64 + 64 - x0)
+            sy, sx = slice(ty * T - y0, ty * T + T - y0), slice(tx * T - x0, tx * T + T - x0)
             cur[sy, sx] = m[sy, sx]
             for _ in range(depth):
                 g = cur.copy()
@@ -102,27 +105,29 @@ def reached_blocks(k, moore, depth):
                     g[:-1, 1:] |= cur[1:, :-1]
                 cur = g & m
             ys, xs = np.nonzero(cur)
-            bx = (xs + x0) // 8 - tx * 8
-            by = (ys + y0) // 8 - ty * 8
+            bx = (xs + x0) // 8 - tx * (T // 8)
+            by = (ys + y0) // 8 - ty * (T // 8)
             out[(tx, ty)] = {b for b in zip(bx.tolist(), by.tolist())
-                             if not (0 <= b[0] < 8 and 0 <= b[1] < 8)}
+                             if not (0 <= b[0] < T // 8 and 0 <= b[1] < T // 8)}
     return out
 
 
-@pytest.mark.parametrize("name,moore,depth", VARIANTS)
-def test_halo_lists_are_exactly_the_reachable_blocks(name, moore, depth):
+@pytest.mark.parametrize("name,moore,depth,tile", VARIANTS)
+def test_halo_lists_are_exactly_the_reachable_blocks(name, moore, depth, tile):
     index, lists = parse()
-    per_mask = lists[(name, depth)]
-    k = 10
-    masks = tile_masks(1 << (k - 6))
+    per_mask = lists[name]
+    k = 10 if tile == 64 else 11
+    masks = tile_masks((1 << k) // tile)
     union = [set() for _ in per_mask]
-    for (tx, ty), found in reached_blocks(k, moore, depth).items():
+    for (tx, ty), found in reached_blocks(k, moore, depth, tile).items():
         i = index[int(masks[ty, tx])]
         assert i >= 0
         assert found <= per_mask[i], ((tx, ty), sorted(found - per_mask[i]))
         union[i] |= found
+    inside = 27 if tile == 64 else 81  # non-empty blocks of the tile
+    slots = 64 if tile == 64 else 128  # one or two blocks per lane
     for i, listed in enumerate(per_mask):
-        assert len(listed) <= 63 - 27, "27 tile blocks, the halo and a free zero lane fit 64 lanes"
+        assert len(listed) <= slots - 1 - inside, "the tile, the halo and a free zero slot fit"
         for b in listed:  # listed blocks are non-empty within their tile
             assert ((b[0] % 8) & (b[1] % 8)) == 0, b
         assert union[i] == listed, (i, sorted(listed - union[i]))

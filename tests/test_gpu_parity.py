@@ -297,24 +297,30 @@ def test_block_engine_every_step_count(rule, map_):
             cur, nxt = nxt, cur
             _sync()
             refs[t] = cur.view(torch.uint8).clone()
-        cases = [(F.FLAG_FUSE16, 2, 0), (F.FLAG_FUSE16, 0, F.FLAG_NT_STORE),
-                 (F.FLAG_FUSE16, 1, 0), (F.FLAG_FUSE8, 2, F.FLAG_NT_STORE),
-                 (F.FLAG_FUSE4, 2, 0), (F.FLAG_FUSE2, 0, 0), (0, 2, 0)]
-        cases += [(d, 2, 0) for d in deep] + [(d, 1, F.FLAG_NT_STORE) for d in deep]
-        for fuse, order, nt in cases:
-            if fuse in deep:
+        cases = [(F.FLAG_FUSE16, 2, 0, 6), (F.FLAG_FUSE16, 0, F.FLAG_NT_STORE, 6),
+                 (F.FLAG_FUSE16, 1, 0, 6), (F.FLAG_FUSE8, 2, F.FLAG_NT_STORE, 6),
+                 (F.FLAG_FUSE4, 2, 0, 6), (F.FLAG_FUSE2, 0, 0, 6), (0, 2, 0, 6)]
+        cases += [(d, 2, 0, 6) for d in deep] + [(d, 1, F.FLAG_NT_STORE, 6) for d in deep]
+        if rule == fi.RULE_HEAT and k >= 7:
+            # the two-slot form on 128 x 128 tiles
+            cases += [(F.FLAG_FUSE36, 1, 0, 7), (F.FLAG_FUSE16, 0, F.FLAG_NT_STORE, 7),
+                      (F.FLAG_FUSE24, 2, 0, 7)]
+        for fuse, order, nt, r in cases:
+            if fuse in deep and r == 6:
                 step_list = range(1, 73) if (order == 2 and nt == 0) else (1, 23, 24, 25, 33, 36, 47, 65)
+            elif r == 7:
+                step_list = range(1, 73) if fuse == F.FLAG_FUSE36 else (1, 15, 16, 17, 24, 25, 49)
             elif fuse == F.FLAG_FUSE16 and order == 2:
                 step_list = range(1, 41)
             else:
                 step_list = (1, 2, 3, 7, 16, 17, 33)
             for steps in step_list:
                 a0, a1 = to_device(init), zeros_state(k, rule)
-                F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, 6, 256, order,
+                F.step_tuned(map_, k, rule, ALPHA, a0, a1, steps, r, 256, order,
                              BLOCK | fuse | nt)
                 _sync()
                 fa = a0 if steps % 2 == 0 else a1
-                assert torch.equal(fa.view(torch.uint8), refs[steps]), (k, fuse, order, nt, steps)
+                assert torch.equal(fa.view(torch.uint8), refs[steps]), (k, fuse, order, nt, r, steps)
         if k == 9:
             ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 27)
             a0, a1 = to_device(init), zeros_state(k, rule)
@@ -322,11 +328,11 @@ def test_block_engine_every_step_count(rule, map_):
             _sync()
             assert_match(k, rule, a1.cpu().numpy(), ref, "block engine, 27 steps")
             ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 61)
-            for d in deep:
+            for d, r in [(d, 6) for d in deep] + ([(F.FLAG_FUSE36, 7)] if rule == fi.RULE_HEAT else []):
                 a0, a1 = to_device(init), zeros_state(k, rule)
-                F.step_tuned(map_, k, rule, ALPHA, a0, a1, 61, 6, 256, 2, BLOCK | d)
+                F.step_tuned(map_, k, rule, ALPHA, a0, a1, 61, r, 256, 2, BLOCK | d)
                 _sync()
-                assert_match(k, rule, a1.cpu().numpy(), ref, f"block engine flags {d}, 61 steps")
+                assert_match(k, rule, a1.cpu().numpy(), ref, f"block engine flags {d} r {r}, 61 steps")
 
 
 @pytest.mark.parametrize("rule", RULES)
@@ -342,21 +348,23 @@ def test_block_engine_full_size_k16_equals_march(rule):
     deep = F.FLAG_FUSE36
     for steps in (1, 16, 37, 64):
         outs = []
-        for map_, fl in ((F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16 |
-                          F.FLAG_NT_STORE),
-                         (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep),
-                         (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE24 |
-                          F.FLAG_NT_STORE),
-                         (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep),
-                         (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16)):
+        runs = [(F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16 | F.FLAG_NT_STORE, 6),
+                (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 6),
+                (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE24 | F.FLAG_NT_STORE, 6),
+                (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 6),
+                (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16, 6)]
+        if rule == fi.RULE_HEAT:  # the two-slot form on 128 x 128 tiles
+            runs += [(F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7),
+                     (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7)]
+        for map_, fl, r in runs:
             b0 = torch.empty((n, n), dtype=dt, device="cuda")
             b1 = torch.zeros_like(b0)
             F.seed_fill(k, rule, 5, b0)
-            F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, 6, 256, 2, fl)
+            F.step_tuned(map_, k, rule, ALPHA, b0, b1, steps, r, 256, 2, fl)
             _sync()
             res = b1 if steps % 2 else b0
             if outs:
-                assert torch.equal(res.view(torch.uint8), outs[0].view(torch.uint8)), (steps, fl)
+                assert torch.equal(res.view(torch.uint8), outs[0].view(torch.uint8)), (steps, fl, r)
             else:
                 outs.append(res)
             del b0, b1

@@ -87,8 +87,8 @@ def test_tuning_defaults_and_validation():
             block = tuple(4096 | 1 | fuse | nt for nt in (0, 2)
                           for fuse in (0, 8, 16, 64, 128, 8192, 16384, 32768))
             assert flags in lds + march + block, (k, rule, flags)
-            if flags & 4096:  # the block engine: 64 x 64 tiles
-                assert r == 6 and th == 256
+            if flags & 4096:  # the block engine: 64 x 64 tiles (heat also 128 x 128)
+                assert (r == 6 or (r == 7 and rule == 1)) and th == 256
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
     with pytest.raises(F.FractalError):
@@ -240,6 +240,7 @@ def test_block_engine_validation():
     else is refused before any device work."""
     B = F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16
     bad = [(0, 0, 12, 5, 256, B),                       # automaton, 32 x 32 tiles
+           (0, 0, 12, 7, 256, B),                       # automaton, 128 x 128 tiles
            (0, 1, 12, 5, 256, B),                       # 32 x 32 tiles
            (2, 1, 12, 6, 256, B),                       # matrix-core map
            (0, 1, 12, 6, 256, B | F.FLAG_MARCH),
@@ -260,6 +261,8 @@ def test_block_engine_validation():
     F.set_tuning(12, 1, 6, 256, 2, B)  # accepted as a tuning
     try:
         assert tuple(F.get_tuning(12, 1)) == (6, 256, 2, B)
+        F.set_tuning(12, 1, 7, 256, 2, B)  # heat: 128 x 128 tiles, two blocks per lane
+        assert tuple(F.get_tuning(12, 1)) == (7, 256, 2, B)
     finally:
         F.set_tuning(12, 1, *before)
 
