@@ -237,8 +237,8 @@ def bb_tuning(g, rule, r, lam=None):
     launch with whole segments."""
     t = lam or g.tunings[rule]
     fl = t[3]
-    if fl & g.F.FLAG_BLOCK and r != 6 and not (r == 7 and rule == 1):
-        # the block engine takes 64 x 64 tiles (heat also 128 x 128): the
+    if fl & g.F.FLAG_BLOCK and r not in (6, 7):
+        # the block engine takes 64 x 64 and 128 x 128 tiles: the
         # march at other sizes (16 steps per launch at most)
         fl = (fl & ~g.F.FLAG_BLOCK) | g.F.FLAG_MARCH
         deep = g.F.FLAG_FUSE24 | g.F.FLAG_FUSE32 | g.F.FLAG_FUSE36

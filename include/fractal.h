@@ -132,8 +132,8 @@ extern "C" {
                                     to 24 cells) */
 #define FRACTAL_FLAG_FUSE32 16384 /* as FUSE24, 32 steps per launch */
 #define FRACTAL_FLAG_FUSE36 32768 /* as FUSE24, 36 steps per launch */
-#define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6; heat also 128 x
-                                   128, r = 7, two blocks per lane), lambda
+#define FRACTAL_FLAG_BLOCK 4096 /* 64 x 64 tiles (r = 6) or 128 x 128
+                                   tiles (r = 7, two blocks per lane), lambda
                                    or BB map: the block engine -- one
                                    wavefront per tile, one lane per non-empty
                                    8 x 8 block of the tile and of the part of

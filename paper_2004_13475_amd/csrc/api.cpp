@@ -320,10 +320,10 @@ int check_tuning(int map, int k, int rule, const fractal_tuning *t)
         if (t->flags & (FRACTAL_FLAG_MARCH | kStackFlags | FRACTAL_FLAG_OCC_ALT))
             return set_error(FRACTAL_E_INVAL,
                              "FRACTAL_FLAG_BLOCK excludes MARCH, STACK and OCC_ALT");
-        if ((t->r != 6 && !(t->r == 7 && rule != FRACTAL_RULE_CA)) || map == MAP_MFMA)
+        if ((t->r != 6 && t->r != 7) || map == MAP_MFMA)
             return set_error(FRACTAL_E_INVAL,
-                             "the block engine runs on 64 x 64 tiles (r = 6; heat also 128 x 128, "
-                             "r = 7), lambda or BB map");
+                             "the block engine runs on 64 x 64 or 128 x 128 tiles (r = 6 or 7), "
+                             "lambda or BB map");
         if (!(t->flags & FRACTAL_FLAG_SEGMENTS))
             return set_error(FRACTAL_E_INVAL, "block launches need FRACTAL_FLAG_SEGMENTS");
         if (fuse & (fuse - 1))
@@ -578,10 +578,10 @@ int fractal_autotune(int k, int rule, float alpha, void *d_buf0, void *d_buf1, v
                                         r, 256, FRACTAL_ORDER_CURVE_XCD,
                                         FRACTAL_FLAG_MARCH | FRACTAL_FLAG_SEGMENTS | nt | fuse |
                                             stack | occ});
-        // 64 x 64 tiles (heat also 128 x 128, two blocks per lane): the
-        // block engine, 8 to 36 steps per launch, every order, with and
-        // without non-temporal stores
-        if (r == 6 || (r == 7 && rule != FRACTAL_RULE_CA))
+        // 64 x 64 and 128 x 128 tiles (two blocks per lane): the block
+        // engine, 8 to 36 steps per launch, every order, with and without
+        // non-temporal stores
+        if (r == 6 || r == 7)
             for (int fuse : {(int)FRACTAL_FLAG_FUSE8, (int)FRACTAL_FLAG_FUSE16,
                              (int)FRACTAL_FLAG_FUSE24, (int)FRACTAL_FLAG_FUSE32,
                              (int)FRACTAL_FLAG_FUSE36})

@@ -68,45 +68,49 @@ struct Board {
     uint32_t lo, hi; // rows 0..3, rows 4..7
 };
 
-// One B3/S23 step of board b.  nb: the lanes of the blocks in each
-// direction (the zero lane where there is none; for the diagonals, also
-// where the block above or below that relays the corner cell is held).
-// Every lane of the wavefront calls it.
-__device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
+// A board's row sums: per cell, two-bit sums of (i-1, j) + (i, j) + (i+1, j)
+// (x0, x1) and of (i-1, j) + (i+1, j) (c0, c1), low and high words.
+struct RowSums {
+    uint32_t x0lo, x1lo, x0hi, x1hi, c0lo, c1lo, c0hi, c1hi;
+};
+
+// w: the low word of the block to the left; elo, ehi: the words of the
+// block to the right.  The cells (i-1, j) and (i+1, j) are the board shifted
+// along its rows, with column 7 of the block to the left (a member in row 0
+// only) and column 0 of the block to the right shifted in; rows 4..7 hold
+// no member beyond column 3, so their left shift spills nothing.
+__device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t elo, uint32_t ehi)
 {
-    // the cells (i-1, j) and (i+1, j): the board shifted along its rows,
-    // with column 7 of the block to the left (a member in row 0 only) and
-    // column 0 of the block to the right shifted in; rows 4..7 hold no
-    // member beyond column 3, so their left shift spills nothing
-    const uint32_t w = pull_u32(nb[DW], b.lo);
-    const uint32_t elo = pull_u32(nb[DE], b.lo), ehi = pull_u32(nb[DE], b.hi);
     const uint32_t llo = merge(0xFEFEFEFEu, b.lo << 1, w >> 7), lhi = b.hi << 1;
     const uint32_t rlo = merge(0x7F7F7F7Fu, b.lo >> 1, elo << 7);
     const uint32_t rhi = merge(0x7F7F7F7Fu, b.hi >> 1, ehi << 7);
-    // per cell, two-bit sums of (i-1, j) + (i, j) + (i+1, j) (x) and of
-    // (i-1, j) + (i+1, j) (c)
-    const uint32_t x0lo = xor3(llo, b.lo, rlo), x1lo = maj3(llo, b.lo, rlo);
-    const uint32_t x0hi = xor3(lhi, b.hi, rhi), x1hi = maj3(lhi, b.hi, rhi);
-    const uint32_t c0lo = llo ^ rlo, c1lo = llo & rlo;
-    const uint32_t c0hi = lhi ^ rhi, c1hi = lhi & rhi;
-    // the sums of the rows above (u) and below (d): row 7 of the block above
-    // and row 0 of the block below come from their lanes.  Their sums hold
-    // the corner cells (0,7) of the block above right and (7,0) of the block
-    // below left; where the block above (below) is missing, that cell is
-    // read directly and lands in a sum that is otherwise zero.
-    const uint32_t ne = pull_u32(nb[DNE], b.hi), sw = pull_u32(nb[DSW], b.lo);
-    const uint32_t n0 = pull_u32(nb[DN], x0hi) | ((ne << 7) & 0x80000000u);
-    const uint32_t n1 = pull_u32(nb[DN], x1hi);
-    const uint32_t s0 = pull_u32(nb[DS], x0lo) | ((sw >> 7) & 1u);
-    const uint32_t s1 = pull_u32(nb[DS], x1lo);
-    const uint32_t u0lo = funnel(x0lo, n0, 24), u0hi = funnel(x0hi, x0lo, 24);
-    const uint32_t u1lo = funnel(x1lo, n1, 24), u1hi = funnel(x1hi, x1lo, 24);
-    const uint32_t d0lo = funnel(x0hi, x0lo, 8), d0hi = funnel(s0, x0hi, 8);
-    const uint32_t d1lo = funnel(x1hi, x1lo, 8), d1hi = funnel(s1, x1hi, 8);
-    // neighbours = u + d + c (at most 3 + 3 + 2): bit 0 is the xor t of the
-    // low planes; with their carry k and the high planes' sum p and carry q,
-    // the count is 2 or 3 iff k + p + 2q == 1, i.e. (k ^ p) & ~q.  Alive next
-    // iff the count is 3, or 2 and alive now; non-members stay zero.
+    RowSums r;
+    r.x0lo = xor3(llo, b.lo, rlo);
+    r.x1lo = maj3(llo, b.lo, rlo);
+    r.x0hi = xor3(lhi, b.hi, rhi);
+    r.x1hi = maj3(lhi, b.hi, rhi);
+    r.c0lo = llo ^ rlo;
+    r.c1lo = llo & rlo;
+    r.c0hi = lhi ^ rhi;
+    r.c1hi = lhi & rhi;
+    return r;
+}
+
+// The step from the row sums and the rows above and below: n0, n1 the
+// sums of row 7 of the block above (in their top bytes), s0, s1 those of
+// row 0 of the block below (in their low bytes), with the corner cells of
+// the diagonal blocks already in.  Neighbours = u + d + c (at most 3 + 3 +
+// 2): bit 0 is the xor t of the low planes; with their carry k and the
+// high planes' sum p and carry q, the count is 2 or 3 iff k + p + 2q == 1,
+// i.e. (k ^ p) & ~q.  Alive next iff the count is 3, or 2 and alive now;
+// non-members stay zero.
+__device__ __forceinline__ Board life_finish(Board b, const RowSums &r, uint32_t n0, uint32_t n1,
+                                             uint32_t s0, uint32_t s1)
+{
+    const uint32_t u0lo = funnel(r.x0lo, n0, 24), u0hi = funnel(r.x0hi, r.x0lo, 24);
+    const uint32_t u1lo = funnel(r.x1lo, n1, 24), u1hi = funnel(r.x1hi, r.x1lo, 24);
+    const uint32_t d0lo = funnel(r.x0hi, r.x0lo, 8), d0hi = funnel(s0, r.x0hi, 8);
+    const uint32_t d1lo = funnel(r.x1hi, r.x1lo, 8), d1hi = funnel(s1, r.x1hi, 8);
     auto rule = [](uint32_t u0, uint32_t d0, uint32_t c0, uint32_t u1, uint32_t d1, uint32_t c1,
                    uint32_t self, uint32_t members) {
         const uint32_t t = xor3(u0, d0, c0), k = maj3(u0, d0, c0);
@@ -114,9 +118,56 @@ __device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
         return (k ^ p) & ~q & ((t | self) & members);
     };
     Board nx;
-    nx.lo = rule(u0lo, d0lo, c0lo, u1lo, d1lo, c1lo, b.lo, kMembersLo);
-    nx.hi = rule(u0hi, d0hi, c0hi, u1hi, d1hi, c1hi, b.hi, kMembersHi);
+    nx.lo = rule(u0lo, d0lo, r.c0lo, u1lo, d1lo, r.c1lo, b.lo, kMembersLo);
+    nx.hi = rule(u0hi, d0hi, r.c0hi, u1hi, d1hi, r.c1hi, b.hi, kMembersHi);
     return nx;
+}
+
+// The corner cells (0,7) of the block above right (ne: its high word) and
+// (7,0) of the block below left (sw: its low word) join the sums of the
+// rows above and below; they are read only where the block above (below)
+// that would relay them is missing, so the sums are otherwise zero there.
+__device__ __forceinline__ uint32_t with_ne(uint32_t n0, uint32_t ne)
+{
+    return n0 | ((ne << 7) & 0x80000000u);
+}
+__device__ __forceinline__ uint32_t with_sw(uint32_t s0, uint32_t sw)
+{
+    return s0 | ((sw >> 7) & 1u);
+}
+
+// One B3/S23 step of board b.  nb: the lanes of the blocks in each
+// direction (the zero lane where there is none; for the diagonals, also
+// where the block above or below that relays the corner cell is held).
+// Every lane of the wavefront calls it.
+__device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
+{
+    const uint32_t w = pull_u32(nb[DW], b.lo);
+    const uint32_t elo = pull_u32(nb[DE], b.lo), ehi = pull_u32(nb[DE], b.hi);
+    const RowSums r = row_sums(b, w, elo, ehi);
+    const uint32_t ne = pull_u32(nb[DNE], b.hi), sw = pull_u32(nb[DSW], b.lo);
+    const uint32_t n0 = with_ne(pull_u32(nb[DN], r.x0hi), ne);
+    const uint32_t n1 = pull_u32(nb[DN], r.x1hi);
+    const uint32_t s0 = with_sw(pull_u32(nb[DS], r.x0lo), sw);
+    const uint32_t s1 = pull_u32(nb[DS], r.x1lo);
+    return life_finish(b, r, n0, n1, s0, s1);
+}
+
+// The board of the block whose first cell is at src (rows P bytes apart;
+// rows 4..7 hold members in their first four cells); zero where the lane
+// holds no block.
+__device__ __forceinline__ uint64_t load_board(const uint8_t *src, int64_t P, bool active)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    using gu2 = const __attribute__((address_space(1))) u32x2;
+    uint64_t b = 0;
+    static_for<0, kBlk>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const u32x2 v = *(gu2 *)(src + j * P);
+        const uint64_t row = pack4(v[0]) | (pack4(v[1]) << 4);
+        b |= row << (8 * j);
+    });
+    return active ? (b & kMembers) : 0ull;
 }
 
 } // namespace blk
@@ -134,19 +185,7 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
     const int64_t base = lay.block_off(g.gx, g.gy);
     const int64_t P = lay.pitch(); // bytes between a block's rows
     // load: 8 bytes a row (rows 4..7 hold members in their first four)
-    uint64_t b = 0;
-    {
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        using gu2 = const __attribute__((address_space(1))) u32x2;
-        const uint8_t *src = src_state + (g.active ? base : 0);
-        static_for<0, kBlk>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            const u32x2 v = *(gu2 *)(src + j * P);
-            const uint64_t row = pack4(v[0]) | (pack4(v[1]) << 4);
-            b |= row << (8 * j);
-        });
-        b = g.active ? (b & kMembers) : 0ull;
-    }
+    uint64_t b = load_board(src_state + (g.active ? base : 0), P, g.active);
     // the diagonal lanes only where the block relaying their corner cell is
     // not held
     uint32_t nb[kDirs];
@@ -203,6 +242,114 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
             else
                 *p = v;
         }
+    }
+}
+
+// One wavefront advances the 128 x 128 tile t of a level-k automaton state
+// `steps` steps (1..36), src -> dst, two blocks per lane; all 64 lanes call
+// it.  Each value a step reads from a neighbouring block is read from both
+// slots of the lane that holds it, keeping the one of the block's slot.
+template <int FL, class Layout>
+__device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t *dst_state, int k,
+                                               TileXY t, int steps, const Layout &lay)
+{
+    using namespace blk;
+    constexpr int H = halo_blocks(36);
+    Slot2 sl[2];
+    block_region2<true>(k, t, sl);
+    const int64_t P = lay.pitch();
+    Board cur[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const uint64_t b = load_board(
+            src_state + (sl[s].active ? lay.block_off(sl[s].gx, sl[s].gy) : 0), P, sl[s].active);
+        cur[s] = Board{(uint32_t)b, (uint32_t)(b >> 32)};
+    }
+    // the value of `v` (per slot) held by list entry q
+    auto pull2 = [](uint32_t q, uint32_t v0, uint32_t v1) {
+        const uint32_t x0 = pull_u32(q & 63u, v0), x1 = pull_u32(q & 63u, v1);
+        return (q & 64u) ? x1 : x0;
+    };
+    // the diagonal blocks only where the block relaying their corner cell
+    // is not held
+    uint32_t qne[2], qsw[2];
+    const uint32_t a0 = sl[0].active ? 1u : 0u, a1 = sl[1].active ? 1u : 0u;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        qne[s] = pull2(sl[s].nb[DN], a0, a1) ? kZeroSlot : sl[s].nb[DNE];
+        qsw[s] = pull2(sl[s].nb[DS], a0, a1) ? kZeroSlot : sl[s].nb[DSW];
+    }
+    for (int st = 0; st < steps; ++st) {
+        RowSums r[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint32_t w = pull2(sl[s].nb[DW], cur[0].lo, cur[1].lo);
+            const uint32_t elo = pull2(sl[s].nb[DE], cur[0].lo, cur[1].lo);
+            const uint32_t ehi = pull2(sl[s].nb[DE], cur[0].hi, cur[1].hi);
+            r[s] = row_sums(cur[s], w, elo, ehi);
+        }
+        Board nx[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint32_t ne = pull2(qne[s], cur[0].hi, cur[1].hi);
+            const uint32_t sw = pull2(qsw[s], cur[0].lo, cur[1].lo);
+            const uint32_t n0 = with_ne(pull2(sl[s].nb[DN], r[0].x0hi, r[1].x0hi), ne);
+            const uint32_t n1 = pull2(sl[s].nb[DN], r[0].x1hi, r[1].x1hi);
+            const uint32_t s0 = with_sw(pull2(sl[s].nb[DS], r[0].x0lo, r[1].x0lo), sw);
+            const uint32_t s1 = pull2(sl[s].nb[DS], r[0].x1lo, r[1].x1lo);
+            nx[s] = life_finish(cur[s], r[s], n0, n1, s0, s1);
+        }
+        cur[0] = nx[0];
+        cur[1] = nx[1];
+    }
+
+    // Store: a tile row is 128 bytes (sixteen blocks); the wavefront
+    // assembles the tile in LDS a half (64 rows, 8 KB) at a time, zeros where
+    // blocks are empty, and writes each half eight lanes to a row.
+    __shared__ uint32_t half[4][64 * 32]; // per wavefront: 64 rows of 128 bytes
+    uint32_t *my = half[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+    auto wave_sync = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<u32x4v *>(my + lane * 32 + 4 * q) = u32x4v{0u, 0u, 0u, 0u};
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int bx = sl[s].px - H, by = sl[s].py - H - kTileBlk * h;
+            if (sl[s].active && bx >= 0 && bx < kTile2Blk && by >= 0 && by < kTileBlk) {
+                const uint64_t b = ((uint64_t)cur[s].hi << 32) | cur[s].lo;
+                const int w0 = by * kBlk * 32 + bx * 2;
+                static_for<0, kBlk>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const uint32_t row = (uint32_t)(b >> (8 * j)) & 0xFFu;
+                    my[w0 + j * 32] = unpack4(row);
+                    my[w0 + j * 32 + 1] = unpack4(row >> 4);
+                });
+            }
+        }
+        wave_sync();
+        // eight lanes per 128-byte row: each store instruction writes eight
+        // whole rows
+        const uint32_t chunk = lane & 7u, r0 = lane >> 3;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t r = 8u * q + r0;
+            u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + lay.tile_row((int)(64 * h + r))) + chunk;
+            const u32x4v v = *reinterpret_cast<const u32x4v *>(my + r * 32 + 4 * chunk);
+            if constexpr (FL & TILE_NT_STORE)
+                __builtin_nontemporal_store(v, p);
+            else
+                *p = v;
+        }
+        wave_sync();
     }
 }
 

@@ -235,6 +235,13 @@ constexpr SlotTable2 make_slots2(const int (&halo)[kMaskCount][N][2], const int 
             ++n;
         }
         s.most = n > s.most ? n : s.most;
+        // list index of the block at each region position (kZeroSlot: none)
+        int at[32][32] = {};
+        for (int y = 0; y < 32; ++y)
+            for (int x = 0; x < 32; ++x)
+                at[y][x] = (int)kZeroSlot;
+        for (int q = 0; q < n; ++q)
+            at[ry[q] + H][rx[q] + H] = q;
         for (int q = 0; q < 128; ++q) {
             uint64_t e = 0;
             for (int d = 0; d < kDirs; ++d)
@@ -242,10 +249,9 @@ constexpr SlotTable2 make_slots2(const int (&halo)[kMaskCount][N][2], const int 
             if (q < n) {
                 e = (uint64_t)(rx[q] + H) | (uint64_t)(ry[q] + H) << 5 | 1ull << 10;
                 for (int d = 0; d < kDirs; ++d) {
-                    uint64_t l = kZeroSlot;
-                    for (int j = 0; j < n; ++j)
-                        if (rx[j] == rx[q] + dx[d] && ry[j] == ry[q] + dy[d])
-                            l = (uint64_t)j;
+                    const int x = rx[q] + H + dx[d], y = ry[q] + H + dy[d];
+                    const uint64_t l = (x >= 0 && y >= 0 && x < 32 && y < 32) ? (uint64_t)at[y][x]
+                                                                              : kZeroSlot;
                     e |= l << (16 + 8 * d);
                 }
             }
@@ -257,7 +263,11 @@ constexpr SlotTable2 make_slots2(const int (&halo)[kMaskCount][N][2], const int 
 
 static __constant__ SlotTable2 kSlots2Heat36 =
     make_slots2(kHalo_heat_36_t128, kHaloCount_heat_36_t128, halo_blocks(36));
-static_assert(make_slots2(kHalo_heat_36_t128, kHaloCount_heat_36_t128, 5).most <= (int)kZeroSlot,
+static __constant__ SlotTable2 kSlots2Moore36 =
+    make_slots2(kHalo_moore_36_t128, kHaloCount_moore_36_t128, halo_blocks(36));
+static_assert(make_slots2(kHalo_heat_36_t128, kHaloCount_heat_36_t128, 5).most <= (int)kZeroSlot &&
+                  make_slots2(kHalo_moore_36_t128, kHaloCount_moore_36_t128, 5).most <=
+                      (int)kZeroSlot,
               "the zero slot stays free");
 static_assert(halo_blocks(36) * 2 + kTile2Blk <= 32, "region positions fit five bits");
 
@@ -269,7 +279,9 @@ struct Slot2 {
 };
 
 // The two slots of this lane for tile t (128 x 128) of a level-k state,
-// heat's table of up to 36 steps.  All 64 lanes call it.
+// the table of up to 36 steps (MOORE: the automaton's).  All 64 lanes call
+// it.
+template <bool MOORE>
 __device__ __forceinline__ void block_region2(int k, TileXY t, Slot2 (&sl)[2])
 {
     constexpr int H = halo_blocks(36);
@@ -287,7 +299,7 @@ __device__ __forceinline__ void block_region2(int k, TileXY t, Slot2 (&sl)[2])
     const int m = kMaskIndex[mask] < 0 ? kMaskIndex[0] : kMaskIndex[mask];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const uint64_t e = kSlots2Heat36.e[m][s * 64 + lane];
+        const uint64_t e = MOORE ? kSlots2Moore36.e[m][s * 64 + lane] : kSlots2Heat36.e[m][s * 64 + lane];
         sl[s].active = ((e >> 10) & 1u) != 0u;
         sl[s].px = (int)(e & 31u);
         sl[s].py = (int)((e >> 5) & 31u);
@@ -304,6 +316,7 @@ struct ArrayLayout {
     int64_t row_bytes; // bytes per array row
     int S;             // bytes per cell
     TileXY t;          // the tile the wavefront advances
+    int tile_log = kTileLog; // its side, log2
     __device__ __forceinline__ int64_t block_off(int gx, int gy) const
     {
         return (int64_t)(gy * kBlk) * row_bytes + (int64_t)gx * kBlk * S;
@@ -311,7 +324,7 @@ struct ArrayLayout {
     __device__ __forceinline__ int64_t pitch() const { return row_bytes; }
     __device__ __forceinline__ int64_t tile_row(int r) const
     {
-        return (((int64_t)t.y << kTileLog) + r) * row_bytes + ((int64_t)t.x << kTileLog) * S;
+        return (((int64_t)t.y << tile_log) + r) * row_bytes + ((int64_t)t.x << tile_log) * S;
     }
 };
 

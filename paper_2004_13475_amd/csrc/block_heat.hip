@@ -100,17 +100,17 @@ static BlockFn pick_block(int map, bool nt, int depth)
 int launch_block(int map, int k, int rule, float alpha, void *b0, void *b1, int steps,
                  const fractal_tuning &t, hipStream_t s)
 {
-    // 64 x 64 tiles (one block per lane), or for heat 128 x 128 tiles (two)
+    // 64 x 64 tiles (one block per lane) or 128 x 128 tiles (two)
     const bool two = t.r == blk::kTile2Log;
-    if ((t.r != blk::kTileLog && !two) || k < t.r || (two && rule == FRACTAL_RULE_CA))
-        return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 tiles (r = 6), "
-                                          "or for heat on 128 x 128 tiles (r = 7)");
+    if ((t.r != blk::kTileLog && !two) || k < t.r)
+        return set_error(FRACTAL_E_INVAL, "the block engine runs on 64 x 64 or 128 x 128 tiles "
+                                          "(r = 6 or 7)");
     const int cap = launch_steps_of(t.flags);
     const bool nt = (t.flags & FRACTAL_FLAG_NT_STORE) != 0;
     // the kernel whose halo covers `cap` steps: 16 cells up to 16 steps,
     // then 24, 32 and 36 (the two-slot form: 36)
     const int depth = cap <= 16 ? 16 : (cap <= 24 ? 24 : (cap <= 32 ? 32 : 36));
-    BlockFn fn = two ? pick_block2(map, nt)
+    BlockFn fn = two ? (rule == FRACTAL_RULE_CA ? pick_block2_ca(map, nt) : pick_block2(map, nt))
                  : rule == FRACTAL_RULE_CA ? pick_block_ca(map, nt, depth)
                                            : pick_block(map, nt, depth);
     if (!fn || cap < 1 || cap > 36)

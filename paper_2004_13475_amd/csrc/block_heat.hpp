@@ -191,7 +191,7 @@ __device__ __forceinline__ void block2_tile(const uint8_t *src_state, uint8_t *d
     using namespace blk;
     constexpr int H = halo_blocks(36);
     Slot2 sl[2];
-    block_region2(k, t, sl);
+    block_region2<false>(k, t, sl);
     const int64_t P = lay.pitch();
     Cells c[2];
 #pragma unroll

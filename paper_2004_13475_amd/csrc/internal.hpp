@@ -128,6 +128,8 @@ typedef void (*BlockFn)(BlockArgs);
 // The automaton's block kernel for launches of up to `depth` steps (16, 24,
 // 32 or 36).
 BlockFn pick_block_ca(int map, bool nt, int depth);
+// The automaton's block kernel on 128 x 128 tiles, two blocks per lane.
+BlockFn pick_block2_ca(int map, bool nt);
 // The block engine over a batch list (table, entries, tiles, slot, steps).
 typedef void (*BatchBlockFn)(const struct BatchEntry *, int, uint64_t, int, int);
 // depth: the most steps of one launch of the list's class (16 or 32).

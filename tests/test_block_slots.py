@@ -16,7 +16,8 @@ import pytest
 
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_2004_13475_amd", "csrc")
 VARIANTS = ([(f"heat_{d}", False, d, 64) for d in (16, 24, 32, 36)] +
-            [(f"moore_{d}", True, d, 64) for d in (16, 24, 32, 36)] + [("heat_36_t128", False, 36, 128)])
+            [(f"moore_{d}", True, d, 64) for d in (16, 24, 32, 36)] +
+            [("heat_36_t128", False, 36, 128), ("moore_36_t128", True, 36, 128)])
 
 
 def parse():

@@ -283,7 +283,9 @@ def test_block_engine_every_step_count(rule, map_):
     step count 1..40 (1..72 for the 24-, 32- and 36-step launches), every
     launch cap (FUSE2 .. FUSE36, or none: one step per launch), every
     dispatch order and both store kinds, at levels 6 (one tile, the halo
-    outside the array), 7, 9 and 12; level 9 also against the oracle."""
+    outside the array), 7, 9 and 12, on 64 x 64 tiles and (from level 7)
+    128 x 128 tiles with two blocks per lane; level 9 also against the
+    oracle."""
     torch = torch_dev()
     BLOCK = F.FLAG_BLOCK | F.FLAG_SEGMENTS
     deep = [F.FLAG_FUSE24, F.FLAG_FUSE32, F.FLAG_FUSE36]
@@ -301,7 +303,7 @@ def test_block_engine_every_step_count(rule, map_):
                  (F.FLAG_FUSE16, 1, 0, 6), (F.FLAG_FUSE8, 2, F.FLAG_NT_STORE, 6),
                  (F.FLAG_FUSE4, 2, 0, 6), (F.FLAG_FUSE2, 0, 0, 6), (0, 2, 0, 6)]
         cases += [(d, 2, 0, 6) for d in deep] + [(d, 1, F.FLAG_NT_STORE, 6) for d in deep]
-        if rule == fi.RULE_HEAT and k >= 7:
+        if k >= 7:
             # the two-slot form on 128 x 128 tiles
             cases += [(F.FLAG_FUSE36, 1, 0, 7), (F.FLAG_FUSE16, 0, F.FLAG_NT_STORE, 7),
                       (F.FLAG_FUSE24, 2, 0, 7)]
@@ -328,7 +330,7 @@ def test_block_engine_every_step_count(rule, map_):
             _sync()
             assert_match(k, rule, a1.cpu().numpy(), ref, "block engine, 27 steps")
             ref = oracle_steps(k, rule, init if rule == 0 else init.astype(np.float64), 61)
-            for d, r in [(d, 6) for d in deep] + ([(F.FLAG_FUSE36, 7)] if rule == fi.RULE_HEAT else []):
+            for d, r in [(d, 6) for d in deep] + [(F.FLAG_FUSE36, 7)]:
                 a0, a1 = to_device(init), zeros_state(k, rule)
                 F.step_tuned(map_, k, rule, ALPHA, a0, a1, 61, r, 256, 2, BLOCK | d)
                 _sync()
@@ -353,9 +355,8 @@ def test_block_engine_full_size_k16_equals_march(rule):
                 (F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE24 | F.FLAG_NT_STORE, 6),
                 (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 6),
                 (F.MAP_LAMBDA, F.FLAG_MARCH | F.FLAG_SEGMENTS | F.FLAG_FUSE16, 6)]
-        if rule == fi.RULE_HEAT:  # the two-slot form on 128 x 128 tiles
-            runs += [(F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7),
-                     (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7)]
+        runs += [(F.MAP_LAMBDA, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7),  # 128 x 128 tiles
+                 (F.MAP_BB, F.FLAG_BLOCK | F.FLAG_SEGMENTS | deep, 7)]
         for map_, fl, r in runs:
             b0 = torch.empty((n, n), dtype=dt, device="cuda")
             b1 = torch.zeros_like(b0)

@@ -234,14 +234,14 @@ def test_boundary_signatures():
 
 
 def test_block_engine_validation():
-    """The block engine takes 64 x 64 tiles (r = 6) with whole segments and
+    """The block engine takes 64 x 64 or 128 x 128 tiles (r = 6 or 7) with whole segments and
     256 threads, the lambda or BB map, and no march, stack or occupancy
     flags; 24, 32 and 36 steps per launch only on the block engine; anything
     else is refused before any device work."""
     B = F.FLAG_BLOCK | F.FLAG_SEGMENTS | F.FLAG_FUSE16
     bad = [(0, 0, 12, 5, 256, B),                       # automaton, 32 x 32 tiles
-           (0, 0, 12, 7, 256, B),                       # automaton, 128 x 128 tiles
            (0, 1, 12, 5, 256, B),                       # 32 x 32 tiles
+           (0, 0, 12, 8, 256, B),                       # 256 x 256 tiles
            (2, 1, 12, 6, 256, B),                       # matrix-core map
            (0, 1, 12, 6, 256, B | F.FLAG_MARCH),
            (0, 1, 12, 6, 256, B | F.FLAG_STACK2),
@@ -257,14 +257,17 @@ def test_block_engine_validation():
         with pytest.raises(F.FractalError) as e:
             F.step_tuned(map_, k, rule, 0.2, FAKE0, FAKE1, 3, r, th, 2, fl, stream=0)
         assert e.value.code == F.E_INVAL, (map_, rule, r, th, fl)
-    before = F.get_tuning(12, 1)
+    before, before_ca = F.get_tuning(12, 1), F.get_tuning(12, 0)
     F.set_tuning(12, 1, 6, 256, 2, B)  # accepted as a tuning
     try:
         assert tuple(F.get_tuning(12, 1)) == (6, 256, 2, B)
-        F.set_tuning(12, 1, 7, 256, 2, B)  # heat: 128 x 128 tiles, two blocks per lane
+        F.set_tuning(12, 1, 7, 256, 2, B)  # 128 x 128 tiles, two blocks per lane
         assert tuple(F.get_tuning(12, 1)) == (7, 256, 2, B)
+        F.set_tuning(12, 0, 7, 256, 2, B)
+        assert tuple(F.get_tuning(12, 0)) == (7, 256, 2, B)
     finally:
         F.set_tuning(12, 1, *before)
+        F.set_tuning(12, 0, *before_ca)
 
 
 def test_reduce_raw_workspace_needs_size():
