@@ -180,7 +180,7 @@ def kernel_name(tuning, rule):
     fl = tuning[3] if len(tuning) > 3 else 0
     if fl & 4096:
         if tuning[0] == 7:
-            return "block2_heat_kernel"
+            return "block2_ca_kernel" if rule == 0 else "block2_heat_kernel"
         return "block_ca_kernel" if rule == 0 else "block_heat_kernel"
     return "march_kernel" if fl & 32 else "step_kernel"
 
