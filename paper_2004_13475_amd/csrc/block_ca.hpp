@@ -1,8 +1,10 @@
 // block_ca.hpp -- the block engine of the uint8 B3/S23 automaton (one
 // wavefront per 64 x 64 tile, one lane per 8 x 8 block; the shared setup is
-// in block_engine.hpp).  A lane keeps its block as a 64-bit board (bit
-// 8j + i holds cell (i, j); the low word holds rows 0..3, the high word rows
-// 4..7) and advances it with bitwise operations.  A step first sums each
+// in block_engine.hpp).  A lane loads and stores its block as a 64-bit
+// board (bit 8j + i holds cell (i, j)) and steps it as two words, one of
+// the even rows and one of the odd rows (byte m of each: row 2m, row
+// 2m + 1), so that the rows above and below a row of one word are the other
+// word, shifted by a row for one of the two directions only.  A step first sums each
 // cell's row neighbours, (i-1, j) + (i+1, j), and the same with the cell
 // itself; the rows above and below contribute their three-cell sums, taken
 // from this board or, for row 0 and row 7, from the lanes of the blocks
@@ -41,7 +43,15 @@ __device__ __forceinline__ uint32_t unpack4(uint32_t x)
     return ((x & 0xFu) * 0x00204081u) & 0x01010101u;
 }
 
-constexpr uint32_t kMembersLo = (uint32_t)kMembers, kMembersHi = (uint32_t)(kMembers >> 32);
+// Bytes 0, 2, 4, 6 (even) or 1, 3, 5, 7 (odd) of a board as one word.
+constexpr uint32_t rows_of(uint64_t b, int odd)
+{
+    uint32_t w = 0;
+    for (int m = 0; m < 4; ++m)
+        w |= (uint32_t)((b >> (8 * (2 * m + odd))) & 0xFFu) << (8 * m);
+    return w;
+}
+constexpr uint32_t kMembersLo = rows_of(kMembers, 0), kMembersHi = rows_of(kMembers, 1);
 
 // Three-input xor and majority (one v_bitop3 each; both are symmetric in
 // their inputs).
@@ -53,10 +63,11 @@ __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
 {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
 }
-// The bits of a where m is set, of b elsewhere.
+// The bits of a where m is set, of b elsewhere (one v_bitop3, which also
+// keeps the compiler from splitting the two halves apart for its users).
 __device__ __forceinline__ uint32_t merge(uint32_t m, uint32_t a, uint32_t b)
 {
-    return (a & m) | (b & ~m);
+    return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
 }
 // The low word of (hi:lo) >> s.
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
@@ -65,20 +76,32 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 }
 
 struct Board {
-    uint32_t lo, hi; // rows 0..3, rows 4..7
+    uint32_t lo, hi; // rows 0, 2, 4, 6 and rows 1, 3, 5, 7, a byte each
 };
+// A 64-bit board as even and odd rows, and back (one v_perm each).
+__device__ __forceinline__ Board split_rows(uint64_t b)
+{
+    const uint32_t l = (uint32_t)b, h = (uint32_t)(b >> 32);
+    return Board{__builtin_amdgcn_perm(h, l, 0x06040200u), __builtin_amdgcn_perm(h, l, 0x07050301u)};
+}
+__device__ __forceinline__ uint64_t join_rows(Board b)
+{
+    const uint32_t l = __builtin_amdgcn_perm(b.hi, b.lo, 0x05010400u);
+    const uint32_t h = __builtin_amdgcn_perm(b.hi, b.lo, 0x07030602u);
+    return ((uint64_t)h << 32) | l;
+}
 
 // A board's row sums: per cell, two-bit sums of (i-1, j) + (i, j) + (i+1, j)
-// (x0, x1) and of (i-1, j) + (i+1, j) (c0, c1), low and high words.
+// (x0, x1) and of (i-1, j) + (i+1, j) (c0, c1), even and odd rows.
 struct RowSums {
     uint32_t x0lo, x1lo, x0hi, x1hi, c0lo, c1lo, c0hi, c1hi;
 };
 
-// w: the low word of the block to the left; elo, ehi: the words of the
+// w: the even rows of the block to the left; elo, ehi: both words of the
 // block to the right.  The cells (i-1, j) and (i+1, j) are the board shifted
 // along its rows, with column 7 of the block to the left (a member in row 0
-// only) and column 0 of the block to the right shifted in; rows 4..7 hold
-// no member beyond column 3, so their left shift spills nothing.
+// only) and column 0 of the block to the right shifted in; the odd rows hold
+// no member in column 7, so their left shift spills nothing.
 __device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t elo, uint32_t ehi)
 {
     const uint32_t llo = merge(0xFEFEFEFEu, b.lo << 1, w >> 7), lhi = b.hi << 1;
@@ -99,7 +122,11 @@ __device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t elo, u
 // The step from the row sums and the rows above and below: n0, n1 the
 // sums of row 7 of the block above (in their top bytes), s0, s1 those of
 // row 0 of the block below (in their low bytes), with the corner cells of
-// the diagonal blocks already in.  Neighbours = u + d + c (at most 3 + 3 +
+// the diagonal blocks already in.  Above an even row lies the odd row of
+// the byte before (row 7 of the block above for row 0), below it the odd
+// row of the same byte; above an odd row the even row of the same byte,
+// below it the even row of the next byte (row 0 of the block below for
+// row 7).  Neighbours = u + d + c (at most 3 + 3 +
 // 2): bit 0 is the xor t of the low planes; with their carry k and the
 // high planes' sum p and carry q, the count is 2 or 3 iff k + p + 2q == 1,
 // i.e. (k ^ p) & ~q.  Alive next iff the count is 3, or 2 and alive now;
@@ -107,10 +134,10 @@ __device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t elo, u
 __device__ __forceinline__ Board life_finish(Board b, const RowSums &r, uint32_t n0, uint32_t n1,
                                              uint32_t s0, uint32_t s1)
 {
-    const uint32_t u0lo = funnel(r.x0lo, n0, 24), u0hi = funnel(r.x0hi, r.x0lo, 24);
-    const uint32_t u1lo = funnel(r.x1lo, n1, 24), u1hi = funnel(r.x1hi, r.x1lo, 24);
-    const uint32_t d0lo = funnel(r.x0hi, r.x0lo, 8), d0hi = funnel(s0, r.x0hi, 8);
-    const uint32_t d1lo = funnel(r.x1hi, r.x1lo, 8), d1hi = funnel(s1, r.x1hi, 8);
+    const uint32_t u0lo = funnel(r.x0hi, n0, 24), u0hi = r.x0lo;
+    const uint32_t u1lo = funnel(r.x1hi, n1, 24), u1hi = r.x1lo;
+    const uint32_t d0lo = r.x0hi, d0hi = funnel(s0, r.x0lo, 8);
+    const uint32_t d1lo = r.x1hi, d1hi = funnel(s1, r.x1lo, 8);
     auto rule = [](uint32_t u0, uint32_t d0, uint32_t c0, uint32_t u1, uint32_t d1, uint32_t c1,
                    uint32_t self, uint32_t members) {
         const uint32_t t = xor3(u0, d0, c0), k = maj3(u0, d0, c0);
@@ -123,8 +150,8 @@ __device__ __forceinline__ Board life_finish(Board b, const RowSums &r, uint32_t
     return nx;
 }
 
-// The corner cells (0,7) of the block above right (ne: its high word) and
-// (7,0) of the block below left (sw: its low word) join the sums of the
+// The corner cells (0,7) of the block above right (ne: its odd rows) and
+// (7,0) of the block below left (sw: its even rows) join the sums of the
 // rows above and below; they are read only where the block above (below)
 // that would relay them is missing, so the sums are otherwise zero there.
 __device__ __forceinline__ uint32_t with_ne(uint32_t n0, uint32_t ne)
@@ -196,10 +223,10 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
     const uint32_t have_s = pull_u32(g.lane[DS], g.active ? 1u : 0u);
     nb[DNE] = have_n ? kZeroLane : g.lane[DNE];
     nb[DSW] = have_s ? kZeroLane : g.lane[DSW];
-    Board cur = {(uint32_t)b, (uint32_t)(b >> 32)};
+    Board cur = split_rows(b);
     for (int s = 0; s < steps; ++s)
         cur = life_step(cur, nb);
-    b = ((uint64_t)cur.hi << 32) | cur.lo;
+    b = join_rows(cur);
 
     // Store: a 64-byte segment is a whole tile row (eight blocks), so the
     // wavefront assembles its tile in LDS (zeros where blocks are empty)
@@ -263,7 +290,7 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
     for (int s = 0; s < 2; ++s) {
         const uint64_t b = load_board(
             src_state + (sl[s].active ? lay.block_off(sl[s].gx, sl[s].gy) : 0), P, sl[s].active);
-        cur[s] = Board{(uint32_t)b, (uint32_t)(b >> 32)};
+        cur[s] = split_rows(b);
     }
     // the value of `v` (per slot) held by list entry q
     auto pull2 = [](uint32_t q, uint32_t v0, uint32_t v1) {
@@ -325,7 +352,7 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
         for (int s = 0; s < 2; ++s) {
             const int bx = sl[s].px - H, by = sl[s].py - H - kTileBlk * h;
             if (sl[s].active && bx >= 0 && bx < kTile2Blk && by >= 0 && by < kTileBlk) {
-                const uint64_t b = ((uint64_t)cur[s].hi << 32) | cur[s].lo;
+                const uint64_t b = join_rows(cur[s]);
                 const int w0 = by * kBlk * 32 + bx * 2;
                 static_for<0, kBlk>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
