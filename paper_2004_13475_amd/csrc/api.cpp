@@ -127,15 +127,14 @@ static int clamp_r(int k, int r)
 //              march on 16 x 16 tiles;
 //   heat       level >= 13: the block engine; below: the march on 16 x 16
 //              tiles (eight steps where the tile is narrower than 16 cells).
-// Heat's block engine uses plain stores (non-temporal ones measured 1.2-1.6x
-// slower), the automaton's non-temporal ones (1-2.5% faster at levels 14 to
-// 16: its stores are whole 64-byte tile rows assembled in LDS); march
-// launches from level 15 non-temporal ones.
+// The block engines use plain stores (non-temporal ones measured 1.2-1.6x
+// slower for heat, 2-12% slower for the automaton); march launches from
+// level 15 non-temporal ones.
 static fractal_tuning builtin_default(int k, int rule)
 {
     const bool ca = rule == FRACTAL_RULE_CA;
     if (k >= (ca ? 14 : 13)) {
-        // the block engine in the curve order (neighbouring
+        // the block engine, plain stores, in the curve order (neighbouring
         // tiles share halo blocks in L2; for the automaton split over the
         // dies), with the deepest halo: a launch costs about the same at 16
         // or 36 steps (its time goes to moving the tile), so the longest
@@ -148,8 +147,7 @@ static fractal_tuning builtin_default(int k, int rule)
         t.r = (ca || k < 16) ? 6 : 7;
         t.threads = 256;
         t.order = ca ? FRACTAL_ORDER_CURVE_XCD : FRACTAL_ORDER_CURVE;
-        t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE36 |
-                  (ca ? FRACTAL_FLAG_NT_STORE : 0);
+        t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE36;
         return t;
     }
     const int r = clamp_r(k, 4);

@@ -4,15 +4,17 @@
 // board (bit 8j + i holds cell (i, j)) and steps it as two words, one of
 // the even rows and one of the odd rows (byte m of each: row 2m, row
 // 2m + 1), so that the rows above and below a row of one word are the other
-// word, shifted by a row for one of the two directions only.  A step first sums each
-// cell's row neighbours, (i-1, j) + (i+1, j), and the same with the cell
-// itself; the rows above and below contribute their three-cell sums, taken
-// from this board or, for row 0 and row 7, from the lanes of the blocks
-// above and below, whose sums already hold the diagonal blocks' cells.  In
-// a gasket only these cells of other blocks touch a block's members: (7,0)
-// of the block to the left, column 0 of the block to the right, (0,7) of
-// the blocks above and above right, and row 0 of the block below with
-// (7,0) of the block below left.  The finished tile is assembled in LDS (4 KB
+// word, shifted by a row for one of the two directions only.  A step first
+// sums each cell's row neighbours, (i-1, j) + (i+1, j), and the same with
+// the cell itself; the rows above and below contribute their three-cell
+// sums, taken from this board or, for row 0 and row 7, from the lanes of
+// the blocks above and below, whose sums already hold the diagonal blocks'
+// cells.  In a gasket only these cells of other blocks touch a block's
+// members: (7,0) of the block to the left, column 0 of the block to the
+// right, (0,7) of the blocks above and above right, and row 0 of the block
+// below with (7,0) of the block below left.  Each lane publishes what its
+// neighbours read in three words (column 0; row 7's sums with cell (0,7);
+// row 0's sums with row 0), so a step costs four lane exchanges.  The finished tile is assembled in LDS (4 KB
 // per wavefront) and written four lanes to a 64-byte row.
 #pragma once
 
@@ -97,16 +99,23 @@ struct RowSums {
     uint32_t x0lo, x1lo, x0hi, x1hi, c0lo, c1lo, c0hi, c1hi;
 };
 
-// w: the even rows of the block to the left; elo, ehi: both words of the
-// block to the right.  The cells (i-1, j) and (i+1, j) are the board shifted
-// along its rows, with column 7 of the block to the left (a member in row 0
-// only) and column 0 of the block to the right shifted in; the odd rows hold
-// no member in column 7, so their left shift spills nothing.
-__device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t elo, uint32_t ehi)
+// Column 0 of a board as its right-hand neighbour reads it: the even rows'
+// cells at bits 8m, the odd rows' at bits 8m + 1.
+__device__ __forceinline__ uint32_t column0(Board b)
+{
+    return merge(0x01010101u, b.lo, b.hi << 1);
+}
+
+// w: the even rows of the block to the left; e: column0() of the block to
+// the right.  The cells (i-1, j) and (i+1, j) are the board shifted along
+// its rows, with column 7 of the block to the left (a member in row 0 only)
+// and column 0 of the block to the right shifted in; the odd rows hold no
+// member in column 7, so their left shift spills nothing.
+__device__ __forceinline__ RowSums row_sums(Board b, uint32_t w, uint32_t e)
 {
     const uint32_t llo = merge(0xFEFEFEFEu, b.lo << 1, w >> 7), lhi = b.hi << 1;
-    const uint32_t rlo = merge(0x7F7F7F7Fu, b.lo >> 1, elo << 7);
-    const uint32_t rhi = merge(0x7F7F7F7Fu, b.hi >> 1, ehi << 7);
+    const uint32_t rlo = merge(0x7F7F7F7Fu, b.lo >> 1, e << 7);
+    const uint32_t rhi = merge(0x7F7F7F7Fu, b.hi >> 1, e << 6);
     RowSums r;
     r.x0lo = xor3(llo, b.lo, rlo);
     r.x1lo = maj3(llo, b.lo, rlo);
@@ -150,34 +159,57 @@ __device__ __forceinline__ Board life_finish(Board b, const RowSums &r, uint32_t
     return nx;
 }
 
-// The corner cells (0,7) of the block above right (ne: its odd rows) and
-// (7,0) of the block below left (sw: its even rows) join the sums of the
-// rows above and below; they are read only where the block above (below)
-// that would relay them is missing, so the sums are otherwise zero there.
-__device__ __forceinline__ uint32_t with_ne(uint32_t n0, uint32_t ne)
+// What the block below reads: bytes [0, row 7, x0 of row 7, x1 of row 7]
+// (the raw row holds one member, cell (0,7), at bit 8).  What the block
+// above reads: [x1 of row 0, x0 of row 0, row 0, 0] (cell (7,0) at bit 23).
+// One v_perm gathers two sources' bytes (selector 12 gives a zero byte).
+__device__ __forceinline__ uint32_t down_word(Board b, const RowSums &r)
 {
-    return n0 | ((ne << 7) & 0x80000000u);
+    return __builtin_amdgcn_perm(b.hi, __builtin_amdgcn_perm(r.x1hi, r.x0hi, 0x07030C0Cu), 0x0302070Cu);
 }
-__device__ __forceinline__ uint32_t with_sw(uint32_t s0, uint32_t sw)
+__device__ __forceinline__ uint32_t up_word(Board b, const RowSums &r)
 {
-    return s0 | ((sw >> 7) & 1u);
+    return __builtin_amdgcn_perm(b.lo, __builtin_amdgcn_perm(r.x0lo, r.x1lo, 0x0C0C0400u), 0x0C040100u);
 }
 
-// One B3/S23 step of board b.  nb: the lanes of the blocks in each
-// direction (the zero lane where there is none; for the diagonals, also
-// where the block above or below that relays the corner cell is held).
-// Every lane of the wavefront calls it.
-__device__ __forceinline__ Board life_step(Board b, const uint32_t (&nb)[kDirs])
+// Where a lane reads each step and how it unpacks it.  The row above comes
+// from the block above when that block is held (its row 7 sums already
+// hold the corner cell of the block above right), else from the block
+// above right (its cell (0,7) alone, row sums zero); the same below.
+struct Links {
+    uint32_t w, e, n, s; // lanes (or list entries) read
+    uint32_t shn, mn;    // n0 = word << shn, n1 = word & mn
+    uint32_t shs, ms;    // s0 = word >> shs, s1 = word & ms
+};
+__device__ __forceinline__ Links make_links(uint32_t w, uint32_t e, uint32_t n, uint32_t ne, bool have_n,
+                                            uint32_t s, uint32_t sw, bool have_s)
 {
-    const uint32_t w = pull_u32(nb[DW], b.lo);
-    const uint32_t elo = pull_u32(nb[DE], b.lo), ehi = pull_u32(nb[DE], b.hi);
-    const RowSums r = row_sums(b, w, elo, ehi);
-    const uint32_t ne = pull_u32(nb[DNE], b.hi), sw = pull_u32(nb[DSW], b.lo);
-    const uint32_t n0 = with_ne(pull_u32(nb[DN], r.x0hi), ne);
-    const uint32_t n1 = pull_u32(nb[DN], r.x1hi);
-    const uint32_t s0 = with_sw(pull_u32(nb[DS], r.x0lo), sw);
-    const uint32_t s1 = pull_u32(nb[DS], r.x1lo);
-    return life_finish(b, r, n0, n1, s0, s1);
+    Links k;
+    k.w = w;
+    k.e = e;
+    k.n = have_n ? n : ne;
+    k.shn = have_n ? 8u : 23u;
+    k.mn = have_n ? ~0u : 0u;
+    k.s = have_s ? s : sw;
+    k.shs = have_s ? 8u : 23u;
+    k.ms = have_s ? ~0u : 0u;
+    return k;
+}
+// n0, n1, s0, s1 for life_finish from the words read from above and below
+__device__ __forceinline__ Board life_from(Board b, const RowSums &r, uint32_t vn, uint32_t vs,
+                                           const Links &k)
+{
+    return life_finish(b, r, vn << k.shn, vn & k.mn, vs >> k.shs, vs & k.ms);
+}
+
+// One B3/S23 step of board b, four lane exchanges.  Every lane of the
+// wavefront calls it.
+__device__ __forceinline__ Board life_step(Board b, const Links &k)
+{
+    const uint32_t w = pull_u32(k.w, b.lo), e = pull_u32(k.e, column0(b));
+    const RowSums r = row_sums(b, w, e);
+    const uint32_t vn = pull_u32(k.n, down_word(b, r)), vs = pull_u32(k.s, up_word(b, r));
+    return life_from(b, r, vn, vs, k);
 }
 
 // The board of the block whose first cell is at src (rows P bytes apart;
@@ -215,17 +247,13 @@ __device__ __forceinline__ void block_ca_tile(const uint8_t *src_state, uint8_t 
     uint64_t b = load_board(src_state + (g.active ? base : 0), P, g.active);
     // the diagonal lanes only where the block relaying their corner cell is
     // not held
-    uint32_t nb[kDirs];
-#pragma unroll
-    for (int d = 0; d < kDirs; ++d)
-        nb[d] = g.lane[d];
     const uint32_t have_n = pull_u32(g.lane[DN], g.active ? 1u : 0u);
     const uint32_t have_s = pull_u32(g.lane[DS], g.active ? 1u : 0u);
-    nb[DNE] = have_n ? kZeroLane : g.lane[DNE];
-    nb[DSW] = have_s ? kZeroLane : g.lane[DSW];
+    const Links links = make_links(g.lane[DW], g.lane[DE], g.lane[DN], g.lane[DNE], have_n != 0u,
+                                   g.lane[DS], g.lane[DSW], have_s != 0u);
     Board cur = split_rows(b);
     for (int s = 0; s < steps; ++s)
-        cur = life_step(cur, nb);
+        cur = life_step(cur, links);
     b = join_rows(cur);
 
     // Store: a 64-byte segment is a whole tile row (eight blocks), so the
@@ -299,33 +327,26 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
     };
     // the diagonal blocks only where the block relaying their corner cell
     // is not held
-    uint32_t qne[2], qsw[2];
+    Links links[2];
     const uint32_t a0 = sl[0].active ? 1u : 0u, a1 = sl[1].active ? 1u : 0u;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        qne[s] = pull2(sl[s].nb[DN], a0, a1) ? kZeroSlot : sl[s].nb[DNE];
-        qsw[s] = pull2(sl[s].nb[DS], a0, a1) ? kZeroSlot : sl[s].nb[DSW];
-    }
+    for (int s = 0; s < 2; ++s)
+        links[s] = make_links(sl[s].nb[DW], sl[s].nb[DE], sl[s].nb[DN], sl[s].nb[DNE],
+                              pull2(sl[s].nb[DN], a0, a1) != 0u, sl[s].nb[DS], sl[s].nb[DSW],
+                              pull2(sl[s].nb[DS], a0, a1) != 0u);
     for (int st = 0; st < steps; ++st) {
         RowSums r[2];
+        const uint32_t c0 = column0(cur[0]), c1 = column0(cur[1]);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const uint32_t w = pull2(sl[s].nb[DW], cur[0].lo, cur[1].lo);
-            const uint32_t elo = pull2(sl[s].nb[DE], cur[0].lo, cur[1].lo);
-            const uint32_t ehi = pull2(sl[s].nb[DE], cur[0].hi, cur[1].hi);
-            r[s] = row_sums(cur[s], w, elo, ehi);
-        }
+        for (int s = 0; s < 2; ++s)
+            r[s] = row_sums(cur[s], pull2(links[s].w, cur[0].lo, cur[1].lo), pull2(links[s].e, c0, c1));
+        const uint32_t dn0 = down_word(cur[0], r[0]), dn1 = down_word(cur[1], r[1]);
+        const uint32_t up0 = up_word(cur[0], r[0]), up1 = up_word(cur[1], r[1]);
         Board nx[2];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const uint32_t ne = pull2(qne[s], cur[0].hi, cur[1].hi);
-            const uint32_t sw = pull2(qsw[s], cur[0].lo, cur[1].lo);
-            const uint32_t n0 = with_ne(pull2(sl[s].nb[DN], r[0].x0hi, r[1].x0hi), ne);
-            const uint32_t n1 = pull2(sl[s].nb[DN], r[0].x1hi, r[1].x1hi);
-            const uint32_t s0 = with_sw(pull2(sl[s].nb[DS], r[0].x0lo, r[1].x0lo), sw);
-            const uint32_t s1 = pull2(sl[s].nb[DS], r[0].x1lo, r[1].x1lo);
-            nx[s] = life_finish(cur[s], r[s], n0, n1, s0, s1);
-        }
+        for (int s = 0; s < 2; ++s)
+            nx[s] = life_from(cur[s], r[s], pull2(links[s].n, dn0, dn1), pull2(links[s].s, up0, up1),
+                              links[s]);
         cur[0] = nx[0];
         cur[1] = nx[1];
     }
