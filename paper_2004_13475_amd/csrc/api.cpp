@@ -135,18 +135,18 @@ static fractal_tuning builtin_default(int k, int rule)
     const bool ca = rule == FRACTAL_RULE_CA;
     if (k >= (ca ? 14 : 13)) {
         // the block engine, plain stores, in the curve order (neighbouring
-        // tiles share halo blocks in L2; for the automaton split over the
-        // dies), with the deepest halo: a launch costs about the same at 16
-        // or 36 steps (its time goes to moving the tile), so the longest
-        // launch is the cheapest per step.  Heat from level 16 takes
-        // 128 x 128 tiles, two blocks per lane (a tile's halo loaded and
-        // stepped once for what would be three 64 x 64 tiles); below, too
-        // few of them (2187 at level 14, at four wavefronts per SIMD) fill
-        // the chip
+        // tiles share halo blocks in L2; for the automaton below level 16
+        // split over the dies), with the deepest halo: a launch costs about
+        // the same at 16 or 36 steps (its time goes to moving the tile), so
+        // the longest launch is the cheapest per step.  From level 16 both
+        // rules take 128 x 128 tiles, two blocks per lane (a tile's halo
+        // loaded and stepped once for what would be three 64 x 64 tiles,
+        // and fewer instructions per useful block); below, too few of them
+        // (2187 at level 14) fill the chip
         fractal_tuning t;
-        t.r = (ca || k < 16) ? 6 : 7;
+        t.r = k < 16 ? 6 : 7;
         t.threads = 256;
-        t.order = ca ? FRACTAL_ORDER_CURVE_XCD : FRACTAL_ORDER_CURVE;
+        t.order = (ca && k < 16) ? FRACTAL_ORDER_CURVE_XCD : FRACTAL_ORDER_CURVE;
         t.flags = FRACTAL_FLAG_BLOCK | FRACTAL_FLAG_SEGMENTS | FRACTAL_FLAG_FUSE36;
         return t;
     }

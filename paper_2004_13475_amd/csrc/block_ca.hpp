@@ -352,10 +352,12 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
     }
 
     // Store: a tile row is 128 bytes (sixteen blocks); the wavefront
-    // assembles the tile in LDS a half (64 rows, 8 KB) at a time, zeros where
-    // blocks are empty, and writes each half eight lanes to a row.
-    __shared__ uint32_t half[4][64 * 32]; // per wavefront: 64 rows of 128 bytes
-    uint32_t *my = half[threadIdx.x >> 6];
+    // assembles the tile in LDS a quarter (32 rows, 4 KB) at a time, zeros
+    // where blocks are empty, and writes each quarter eight lanes to a row
+    // (4 KB of LDS per wavefront keeps eight wavefronts on a SIMD).
+    constexpr int kRows = 32, kBlkRows = kRows / kBlk;
+    __shared__ uint32_t part[4][kRows * 32]; // per wavefront: 32 rows of 128 bytes
+    uint32_t *my = part[threadIdx.x >> 6];
     const uint32_t lane = lane_id();
     typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
     auto wave_sync = []() {
@@ -363,21 +365,21 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
+    const uint64_t fin[2] = {join_rows(cur[0]), join_rows(cur[1])};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kTile2Blk / kBlkRows; ++h) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            *reinterpret_cast<u32x4v *>(my + lane * 32 + 4 * q) = u32x4v{0u, 0u, 0u, 0u};
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<u32x4v *>(my + lane * 16 + 4 * q) = u32x4v{0u, 0u, 0u, 0u};
         wave_sync();
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const int bx = sl[s].px - H, by = sl[s].py - H - kTileBlk * h;
-            if (sl[s].active && bx >= 0 && bx < kTile2Blk && by >= 0 && by < kTileBlk) {
-                const uint64_t b = join_rows(cur[s]);
+            const int bx = sl[s].px - H, by = sl[s].py - H - kBlkRows * h;
+            if (sl[s].active && bx >= 0 && bx < kTile2Blk && by >= 0 && by < kBlkRows) {
                 const int w0 = by * kBlk * 32 + bx * 2;
                 static_for<0, kBlk>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
-                    const uint32_t row = (uint32_t)(b >> (8 * j)) & 0xFFu;
+                    const uint32_t row = (uint32_t)(fin[s] >> (8 * j)) & 0xFFu;
                     my[w0 + j * 32] = unpack4(row);
                     my[w0 + j * 32 + 1] = unpack4(row >> 4);
                 });
@@ -385,17 +387,22 @@ __device__ __forceinline__ void block2_ca_tile(const uint8_t *src_state, uint8_t
         }
         wave_sync();
         // eight lanes per 128-byte row: each store instruction writes eight
-        // whole rows
+        // whole rows; rows 64..127 hold no member in columns 64..127 (that
+        // quarter of a tile is empty, as the 64 x 64 tile there is), so only
+        // their first 64 bytes are written
         const uint32_t chunk = lane & 7u, r0 = lane >> 3;
+        if (kRows * h < 64 || chunk < 4u) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t r = 8u * q + r0;
-            u32x4v *p = reinterpret_cast<u32x4v *>(dst_state + lay.tile_row((int)(64 * h + r))) + chunk;
-            const u32x4v v = *reinterpret_cast<const u32x4v *>(my + r * 32 + 4 * chunk);
-            if constexpr (FL & TILE_NT_STORE)
-                __builtin_nontemporal_store(v, p);
-            else
-                *p = v;
+            for (int q = 0; q < kRows / 8; ++q) {
+                const uint32_t r = 8u * q + r0;
+                u32x4v *p =
+                    reinterpret_cast<u32x4v *>(dst_state + lay.tile_row((int)(kRows * h + r))) + chunk;
+                const u32x4v v = *reinterpret_cast<const u32x4v *>(my + r * 32 + 4 * chunk);
+                if constexpr (FL & TILE_NT_STORE)
+                    __builtin_nontemporal_store(v, p);
+                else
+                    *p = v;
+            }
         }
         wave_sync();
     }

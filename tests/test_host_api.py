@@ -87,8 +87,8 @@ def test_tuning_defaults_and_validation():
             block = tuple(4096 | 1 | fuse | nt for nt in (0, 2)
                           for fuse in (0, 8, 16, 64, 128, 8192, 16384, 32768))
             assert flags in lds + march + block, (k, rule, flags)
-            if flags & 4096:  # the block engine: 64 x 64 tiles (heat also 128 x 128)
-                assert (r == 6 or (r == 7 and rule == 1)) and th == 256
+            if flags & 4096:  # the block engine: 64 x 64 or 128 x 128 tiles
+                assert r in (6, 7) and th == 256
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
     with pytest.raises(F.FractalError):
