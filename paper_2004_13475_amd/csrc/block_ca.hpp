@@ -99,7 +99,7 @@ struct RowSums {
     uint32_t x0lo, x1lo, x0hi, x1hi, c0lo, c1lo, c0hi, c1hi;
 };
 
-// Column 0 of a board as its right-hand neighbour reads it: the even rows'
+// Column 0 of a board as the block to its left reads it: the even rows'
 // cells at bits 8m, the odd rows' at bits 8m + 1.
 __device__ __forceinline__ uint32_t column0(Board b)
 {
