@@ -91,6 +91,15 @@ def test_tuning_defaults_and_validation():
                 assert r in (6, 7) and th == 256
             if flags & 32:  # march launches need 16-byte tile rows
                 assert (1 << r) * (1 if rule == 0 else 4) >= 16
+    # at level 16 (the highest level a tuning covers) both rules default to
+    # the block engine on 128 x 128 tiles (two blocks per lane) with 36-step
+    # launches; at levels 14 and 15 to 64 x 64 tiles
+    for rule in (0, 1):
+        r, th, order, flags = F.get_tuning(16, rule)
+        assert (r, th) == (7, 256) and flags & 4096 and flags & F.FLAG_FUSE36, rule
+    for k in (14, 15):
+        for rule in (0, 1):
+            assert F.get_tuning(k, rule)[0] == 6 and F.get_tuning(k, rule)[3] & 4096, (k, rule)
     with pytest.raises(F.FractalError):
         F.set_tuning(10, 0, 8, 64, 0)
     with pytest.raises(F.FractalError):
